@@ -1,0 +1,276 @@
+#!/usr/bin/env python3
+"""Benchmark of the split block Bloom filter hot path on one MI355X.
+
+One step is one pass of the single-filter hot path over one batch: zero the
+filter, insert every hash of the batch, look up every probe of the batch
+(hash streaming, block selection, mask, insert, lookup). The default workload
+is the 100M-key geometry of the paper's evaluation table: 4,194,304 blocks
+(128 MiB), 1e8 inserted hashes, 2e8 lookups at a 10 % member rate, all
+synthetic SplitMix64 hashes resident in device memory before timing starts.
+
+Prints one JSON line. ``value`` is total keys (inserts + lookups) per second
+over the timed steps; per-kernel rates, the roofline of the dominant kernel
+(from HIP events recorded on the launch stream around every kernel in the
+timed region), the measured gather / atomic / streaming ceilings and the CPU
+oracle's rate on a bounded sample are reported beside it.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "G lookups/s & G inserts/s at 100M keys vs roofline; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Algorithmic bytes per key: hash in (8 B) + the 32-byte block + result out.
+LOOKUP_BYTES_PER_KEY = 8 + 32 + 1
+INSERT_BYTES_PER_KEY = 8 + 32
+PAPER_CONTEXT = {"insert_Mps": 32, "lookup_Mps": 43, "hardware": "not stated (CPU, AVX2 code)",
+                 "source": "evaluation table, 100M elements"}
+
+
+def _kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2101_01719_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None when
+    none exist or the kernels changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_digest") != _kernel_source_digest():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def _ensure_built():
+    lib = os.path.join(ROOT, "paper_2101_01719_amd", "libsbbf.so")
+    if not os.path.exists(lib):
+        from paper_2101_01719_amd import build
+
+        build.build()
+
+
+def _cpu_baseline(w):
+    """The oracle, untuned, on the host: all inserts into the full-size filter,
+    then the first half of the lookups. One thread."""
+    import numpy as np
+
+    import oracle
+
+    ins = w.inserts.cpu().numpy().view(np.uint64)
+    n_look = w.lookups.numel() // 2
+    look = w.lookups[:n_look].cpu().numpy().view(np.uint64)
+    words = oracle.new_filter(w.num_blocks)
+    t0 = time.perf_counter()
+    oracle.insert(words, w.num_blocks, ins)
+    t1 = time.perf_counter()
+    oracle.lookup(words, w.num_blocks, look)
+    t2 = time.perf_counter()
+    keys = ins.size + look.size
+    return {
+        "value": keys / (t2 - t0) / 1e9,
+        "unit": "G keys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"all {ins.size:,} inserts into the {w.num_blocks:,}-block filter, then the first "
+                  f"{look.size:,} of the {w.lookups.numel():,} lookups (insert {t1 - t0:.2f} s, "
+                  f"lookup {t2 - t1:.2f} s)",
+        "insert_gkeys_per_s": ins.size / (t1 - t0) / 1e9,
+        "lookup_gkeys_per_s": look.size / (t2 - t1) / 1e9,
+        "host_cpu": _host_cpu(),
+    }
+
+
+def _host_cpu() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _ceilings(P, torch, w, look_launch, ins_launch, reps=5):
+    """Measured ceilings with the same access pattern and launch shape:
+    random 32-byte gather (lookup without the mask), random 8 x 32-bit atomic
+    OR (insert without the mask), and streaming (8 B in, 1 B out)."""
+    buf = torch.full((8 * w.num_blocks,), 1, dtype=torch.int32, device="cuda")
+    out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
+    res = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    t = timed(lambda: P.sbbf_bench_gather(buf, w.num_blocks, w.lookups, out, launch=look_launch))
+    res["gather_gkeys_per_s"] = w.lookups.numel() / t / 1e9
+    res["gather_GBps"] = LOOKUP_BYTES_PER_KEY * w.lookups.numel() / t / 1e9
+    for name, strat in (("atomic32", 1), ("atomic64", 2)):
+        launch = dict(ins_launch, strategy=strat)
+        t = timed(lambda: P.sbbf_bench_atomic(buf, w.num_blocks, w.inserts, launch=launch))
+        res[f"{name}_gkeys_per_s"] = w.inserts.numel() / t / 1e9
+        res[f"{name}_GBps"] = INSERT_BYTES_PER_KEY * w.inserts.numel() / t / 1e9
+    t = timed(lambda: P.sbbf_bench_stream(w.lookups, out, launch=look_launch))
+    res["stream_gkeys_per_s"] = w.lookups.numel() / t / 1e9
+    res["stream_GBps"] = 9 * w.lookups.numel() / t / 1e9
+    del buf, out
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain_100m", choices=["plain_100k", "plain_1m", "plain_100m"])
+    ap.add_argument("--insert-strategy", type=int, default=0, help="0 = library choice, 1 atomic32, 2 atomic64, 3 LDS")
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--unroll", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceilings", action="store_true")
+    a = ap.parse_args(argv)
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the split block Bloom filter path here has no multi-GPU "
+              "form (filters shard by whole filters or by block range; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    _ensure_built()
+    import torch
+
+    import paper_2101_01719_amd as P
+    from synth import plain_workload
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    w = plain_workload(a.workload, backend="torch", device="cuda")
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    n_ins, n_look = w.inserts.numel(), w.lookups.numel()
+
+    ins_launch = dict(block_threads=a.threads, unroll=a.unroll, grid_blocks=a.grid, strategy=a.insert_strategy)
+    look_launch = dict(block_threads=a.threads, unroll=min(a.unroll, 4), grid_blocks=a.grid)
+    f = P.Filter(w.num_blocks)
+    out = torch.empty(n_look, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        f.clear(stream)
+        if ev:
+            ev[0].record(stream)
+        f.insert(w.inserts, launch=ins_launch, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        f.lookup(w.lookups, out=out, launch=look_launch, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / a.steps
+    insert_ms = sum(e[0].elapsed_time(e[1]) for e in events) / a.steps
+    lookup_ms = sum(e[1].elapsed_time(e[2]) for e in events) / a.steps
+
+    # correctness facts of the last step (cheap, device-side)
+    fp = int(out[~w.is_member].sum().item())
+    members_ok = bool(out[w.is_member].all().item())
+    n_non = int((~w.is_member).sum().item())
+
+    ins_gbps = INSERT_BYTES_PER_KEY * n_ins / (insert_ms / 1e3) / 1e9
+    look_gbps = LOOKUP_BYTES_PER_KEY * n_look / (lookup_ms / 1e3) / 1e9
+    kernels = {
+        "insert": dict(bound="hbm", achieved=ins_gbps, peak=HBM_PEAK_GBS, unit="GB/s", frac=ins_gbps / HBM_PEAK_GBS,
+                       traffic=_traffic("insert", a.workload), avg_ms=insert_ms,
+                       bytes_per_key=INSERT_BYTES_PER_KEY, keys_per_launch=n_ins),
+        "lookup": dict(bound="hbm", achieved=look_gbps, peak=HBM_PEAK_GBS, unit="GB/s", frac=look_gbps / HBM_PEAK_GBS,
+                       traffic=_traffic("lookup", a.workload), avg_ms=lookup_ms,
+                       bytes_per_key=LOOKUP_BYTES_PER_KEY, keys_per_launch=n_look),
+    }
+    dominant = "insert" if insert_ms >= lookup_ms else "lookup"
+    roofline = dict(kernels[dominant], kernel=dominant)
+
+    result = {
+        "metric": METRIC,
+        "value": (n_ins + n_look) / (ms_per_step / 1e3) / 1e9,
+        "unit": "G keys/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{a.workload}: one filter of {w.num_blocks:,} blocks ({w.num_blocks * 32 / 2**20:.0f} MiB), "
+                        f"{n_ins:,} inserts then {n_look:,} lookups ({w.n_member_lookups:,} members), "
+                        "SplitMix64 hashes resident in HBM",
+            "num_blocks": w.num_blocks,
+            "inserts": n_ins,
+            "lookups": n_look,
+            "insert_launch": ins_launch,
+            "lookup_launch": look_launch,
+        },
+        "insert_gkeys_per_s": n_ins / (insert_ms / 1e3) / 1e9,
+        "lookup_gkeys_per_s": n_look / (lookup_ms / 1e3) / 1e9,
+        "roofline": roofline,
+        "roofline_other": dict(kernels["lookup" if dominant == "insert" else "insert"],
+                               kernel="lookup" if dominant == "insert" else "insert"),
+        "false_positive_rate": fp / max(1, n_non),
+        "members_all_found": members_ok,
+        "input_generation_s": t_gen,
+        "paper_context": PAPER_CONTEXT,
+        "kernel_source_digest": _kernel_source_digest(),
+    }
+    if not a.no_ceilings:
+        c = _ceilings(P, torch, w, look_launch, ins_launch)
+        c["lookup_frac_of_gather"] = result["lookup_gkeys_per_s"] / c["gather_gkeys_per_s"]
+        best_atomic = max(c["atomic32_gkeys_per_s"], c["atomic64_gkeys_per_s"])
+        c["insert_frac_of_best_atomic"] = result["insert_gkeys_per_s"] / best_atomic
+        result["ceilings"] = c
+    if not a.no_cpu_baseline:
+        result["cpu_baseline"] = _cpu_baseline(w)
+        result["speedup_vs_cpu_baseline"] = result["value"] / result["cpu_baseline"]["value"]
+    print(json.dumps(result), flush=True)
+    f.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,172 @@
+/*
+ * sbbf.h — C ABI of the MI355X (gfx950) split block Bloom filter library.
+ *
+ * The method is the split block Bloom filter of J. Apple, "Split block Bloom
+ * filters" (arXiv 2101.01719):
+ *   - a filter is an array of 256-bit blocks, each split into eight 32-bit
+ *     words (construction paragraph; appendix figure);
+ *   - a 64-bit hash h selects block b = ((h >> 32) * num_blocks) >> 32
+ *     (appendix figure, block selection);
+ *   - its low 32 bits x are rehashed by eight odd-seed multiply-shift hashes,
+ *     idx_j = (s_j * x mod 2^32) >> 27, one per word (construction paragraph,
+ *     appendix figure, mask routine);
+ *   - insert sets bit idx_j of word j of block b for every j; lookup reports
+ *     present when all eight bits are set (appendix figure, insert and
+ *     lookup routines). Deletion is not part of the method.
+ *
+ * Memory layout shared by every entry point:
+ *   filter   uint32 words[8 * num_blocks] in device memory, little-endian,
+ *            block-major: word j of block b at index 8 * b + j. This is the
+ *            byte image of the paper's array of 256-bit vectors. 32-byte
+ *            aligned.
+ *   hashes   uint64 [n] in device memory, 8-byte aligned, caller-owned.
+ *   results  uint8 [n] (0 or 1 per hash), or a packed bitmap uint32
+ *            [ceil(n / 32)] with hash i at bit (i % 32) of word i / 32.
+ *
+ * Conventions:
+ *   - Every call returns an sbbf_status. Argument checks are synchronous: on
+ *     error nothing is enqueued and sbbf_last_error() holds a description.
+ *     n == 0 is a no-op that returns SBBF_OK.
+ *   - Work is enqueued on the given HIP stream (a hipStream_t passed as
+ *     void*; NULL is the default stream) and completes asynchronously; a
+ *     lookup sees every insert enqueued before it on the same stream. Device
+ *     faults surface when the caller synchronises the stream.
+ *   - Caller-owned buffers must stay valid until the stream passes the call.
+ *   - Handles are not locked; concurrent inserts into one filter from
+ *     several streams are safe on the device (they use atomic OR), and a
+ *     lookup running concurrently with inserts sees some subset of them.
+ *   - The filter bytes produced by any insert strategy and any launch
+ *     configuration are identical: the final filter is the OR of all masks.
+ */
+#ifndef SBBF_H_
+#define SBBF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbbf_filter sbbf_filter; /* opaque: device words + block count */
+typedef struct sbbf_group sbbf_group;   /* opaque: a grouped plan over many filters */
+typedef struct sbbf_server sbbf_server; /* opaque: the serving loop */
+typedef void *sbbf_stream;              /* a hipStream_t; NULL = default stream */
+
+typedef enum sbbf_status {
+  SBBF_OK = 0,
+  SBBF_EINVAL = 1,      /* bad argument (null pointer, size, alignment) */
+  SBBF_ENOMEM = 2,      /* device or host allocation failed */
+  SBBF_EDEVICE = 3,     /* a HIP call failed; sbbf_last_error() has HIP's text */
+  SBBF_EBUDGET = 4,     /* the serving arena budget does not admit the request */
+  SBBF_EUNSUPPORTED = 5,/* the option is not available on this device */
+  SBBF_EAGAIN = 6       /* nothing to do yet (serving poll) */
+} sbbf_status;
+
+/* Insert strategies. All produce identical filter bytes. */
+typedef enum sbbf_insert_strategy {
+  SBBF_INSERT_AUTO = 0,     /* library choice by filter size and key count */
+  SBBF_INSERT_ATOMIC32 = 1, /* one key per 8 lanes, one 32-bit global atomic OR per lane */
+  SBBF_INSERT_ATOMIC64 = 2, /* one key per 4 lanes, one 64-bit global atomic OR per lane */
+  SBBF_INSERT_LDS = 3       /* private copies of the whole filter in LDS, OR-merged;
+                               only when 32 * num_blocks fits one workgroup's LDS */
+} sbbf_insert_strategy;
+
+/* Launch shape for the plain kernels. Zero fields take library defaults. */
+typedef struct sbbf_launch {
+  uint32_t block_threads; /* workgroup size: 64 .. 1024, a multiple of 64 */
+  uint32_t grid_blocks;   /* workgroups; for SBBF_INSERT_LDS the number of private copies */
+  uint32_t unroll;        /* 64-key chunks each wave keeps in flight: 1, 2, 4 or 8 */
+  uint32_t strategy;      /* inserts only: an sbbf_insert_strategy */
+} sbbf_launch;
+
+/* Device facts the library uses to size launches (queried once per device). */
+typedef struct sbbf_device_info {
+  int32_t device;
+  int32_t compute_units;
+  int32_t max_threads_per_block;
+  int32_t warp_size;
+  uint64_t lds_per_block;    /* bytes of LDS one workgroup may allocate */
+  uint64_t lds_per_cu;       /* bytes of LDS per compute unit */
+  uint64_t l2_bytes;
+  uint64_t global_mem_bytes;
+  int32_t clock_khz;
+  int32_t memory_clock_khz;
+  int32_t memory_bus_bits;
+  char arch[64];             /* e.g. "gfx950:sramecc+:xnack-" */
+} sbbf_device_info;
+
+/* ---- library ------------------------------------------------------------ */
+
+/* Text for a status code (static storage). */
+const char *sbbf_status_string(sbbf_status s);
+/* Detail of the last failing call on this host thread ("" if none). */
+const char *sbbf_last_error(void);
+/* Facts about the current HIP device. */
+sbbf_status sbbf_device_query(sbbf_device_info *out);
+/* Blocks for n keys at bits_per_key bits each: max(1, ceil(n * bits_per_key / 256)).
+ * Returns 0 when the result would exceed 2^32 - 1 or bits_per_key <= 0. */
+uint64_t sbbf_blocks_for(uint64_t n, double bits_per_key);
+
+/* ---- single filter --------------------------------------------------------- */
+
+/* Allocate a zeroed filter of num_blocks 256-bit blocks (1 .. 2^32 - 1) in
+ * device memory owned by the handle. */
+sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out);
+/* Wrap caller-owned device memory of 32 * num_blocks bytes (32-byte
+ * aligned, e.g. a torch tensor). Not cleared; never freed by the library. */
+sbbf_status sbbf_create_wrapped(void *d_words, uint32_t num_blocks, sbbf_filter **out);
+/* Release the handle (and its memory when owned). Does not synchronise;
+ * the caller must not destroy a filter that queued work still uses. */
+sbbf_status sbbf_destroy(sbbf_filter *f);
+/* Zero every word, enqueued on the stream (a kernel, no memset node). */
+sbbf_status sbbf_clear(sbbf_filter *f, sbbf_stream s);
+uint32_t sbbf_num_blocks(const sbbf_filter *f);
+void *sbbf_device_words(const sbbf_filter *f);
+
+/* Copy the filter's 32 * num_blocks bytes to host memory, or replace them
+ * from host memory (checkpoint and restore of the byte image). Enqueued on
+ * the stream; with pageable host memory the copy completes before return,
+ * with pinned memory the caller synchronises before touching host_dst. */
+sbbf_status sbbf_copy_words_to_host(const sbbf_filter *f, void *host_dst, sbbf_stream s);
+sbbf_status sbbf_copy_words_from_host(sbbf_filter *f, const void *host_src, sbbf_stream s);
+
+/* Insert n hashes (appendix figure, insert routine; applied to every hash). */
+sbbf_status sbbf_insert_batch(sbbf_filter *f, const uint64_t *d_hashes, size_t n, sbbf_stream s);
+/* As sbbf_insert_batch with an explicit strategy and launch shape (NULL = defaults). */
+sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_t n, const sbbf_launch *cfg,
+                                 sbbf_stream s);
+/* Look up n hashes; d_out[i] = 1 when hash i is reported present, else 0
+ * (appendix figure, lookup routine). */
+sbbf_status sbbf_lookup_batch(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
+                              sbbf_stream s);
+/* As sbbf_lookup_batch, packed: bit (i % 32) of d_bits[i / 32]; all
+ * ceil(n / 32) words are written, unused high bits are 0. d_bits 4-byte aligned. */
+sbbf_status sbbf_lookup_batch_bits(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint32_t *d_bits,
+                                   sbbf_stream s);
+/* Lookup with an explicit launch shape (NULL = defaults). Exactly one of
+ * d_out and d_bits is non-NULL. */
+sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
+                                 uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s);
+
+/* ---- measurement kernels (same access pattern, no filter arithmetic) ------- */
+
+/* Random 32-byte gather ceiling: for each hash, read the 32-byte block
+ * ((h >> 32) * num_blocks) >> 32 of d_buf with 8 lanes and write one byte
+ * (1 when the block has any non-zero word). Same launch shape as lookup. */
+sbbf_status sbbf_bench_gather(const uint32_t *d_buf, uint32_t num_blocks, const uint64_t *d_hashes, size_t n,
+                              uint8_t *d_out, const sbbf_launch *cfg, sbbf_stream s);
+/* Random atomic-OR ceiling: for each hash, OR a fixed one-bit word into each
+ * of the 8 words of its block with 32-bit global atomics (or 4 x 64-bit when
+ * strategy == SBBF_INSERT_ATOMIC64). */
+sbbf_status sbbf_bench_atomic(uint32_t *d_buf, uint32_t num_blocks, const uint64_t *d_hashes, size_t n,
+                              const sbbf_launch *cfg, sbbf_stream s);
+/* Streaming ceiling: read n uint64, write n bytes (the low byte's parity). */
+sbbf_status sbbf_bench_stream(const uint64_t *d_hashes, size_t n, uint8_t *d_out, const sbbf_launch *cfg,
+                              sbbf_stream s);
+
+#ifdef __cplusplus
+} /* extern "C" */
+#endif
+
+#endif /* SBBF_H_ */

@@ -1,0 +1,276 @@
+"""Split block Bloom filters on MI355X (gfx950): Python binding of libsbbf.so.
+
+The functions below carry the names of the C ABI in ``include/sbbf.h`` and
+only marshal arguments: torch tensors supply device memory (their data
+pointers) and torch supplies the stream (``torch.cuda.current_stream()`` by
+default). Every step of insert and lookup runs in the library's HIP kernels;
+there is no Python or CPU fallback: when the library has not been built the
+first call raises ImportError.
+
+Tensors: hashes are 1-D contiguous int64 or uint64 CUDA tensors (the int64
+view carries the same 64 bits); lookup results are uint8 tensors; packed
+results are int32 tensors of ceil(n / 32) words; filter words are int32
+tensors of 8 * num_blocks elements.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import sbbf_device_info, sbbf_launch
+
+SBBF_OK = 0
+SBBF_EINVAL = 1
+SBBF_ENOMEM = 2
+SBBF_EDEVICE = 3
+SBBF_EBUDGET = 4
+SBBF_EUNSUPPORTED = 5
+SBBF_EAGAIN = 6
+
+SBBF_INSERT_AUTO = 0
+SBBF_INSERT_ATOMIC32 = 1
+SBBF_INSERT_ATOMIC64 = 2
+SBBF_INSERT_LDS = 3
+
+
+
+def _L():
+    """The loaded library; raises ImportError when it has not been built."""
+    return _lib.load()
+
+
+
+class SbbfError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        name = _L().sbbf_status_string(status).decode()
+        super().__init__(f"sbbf status {status} ({name}): {detail}")
+
+
+def _check(status: int) -> None:
+    if status != SBBF_OK:
+        raise SbbfError(status, _L().sbbf_last_error().decode())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _hashes(t: torch.Tensor):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("hashes must be a CUDA (HIP) tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("hashes must be int64 or uint64")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError("hashes must be a 1-D contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr()), t.numel()
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    if isinstance(launch, sbbf_launch):
+        return ctypes.byref(launch)
+    if isinstance(launch, dict):
+        return ctypes.byref(sbbf_launch(**launch))
+    raise TypeError("launch must be an sbbf_launch or a dict of its fields")
+
+
+# ---- library ------------------------------------------------------------------
+
+def sbbf_status_string(status: int) -> str:
+    return _L().sbbf_status_string(status).decode()
+
+
+def sbbf_last_error() -> str:
+    return _L().sbbf_last_error().decode()
+
+
+def sbbf_device_query() -> dict:
+    info = sbbf_device_info()
+    _check(_L().sbbf_device_query(ctypes.byref(info)))
+    out = {name: getattr(info, name) for name, _ in sbbf_device_info._fields_}
+    out["arch"] = info.arch.decode()
+    return out
+
+
+def sbbf_blocks_for(n: int, bits_per_key: float) -> int:
+    return int(_L().sbbf_blocks_for(n, bits_per_key))
+
+
+# ---- single filter ------------------------------------------------------------------
+
+def sbbf_create(num_blocks: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_L().sbbf_create(num_blocks, ctypes.byref(h)))
+    return h.value
+
+
+def sbbf_create_wrapped(words: torch.Tensor, num_blocks: int | None = None) -> int:
+    if not words.is_cuda or not words.is_contiguous() or words.element_size() * words.numel() % 32:
+        raise ValueError("filter words must be a contiguous CUDA tensor of whole 32-byte blocks")
+    nb = words.element_size() * words.numel() // 32 if num_blocks is None else num_blocks
+    h = ctypes.c_void_p()
+    _check(_L().sbbf_create_wrapped(ctypes.c_void_p(words.data_ptr()), nb, ctypes.byref(h)))
+    return h.value
+
+
+def sbbf_destroy(f: int) -> None:
+    _check(_L().sbbf_destroy(f))
+
+
+def sbbf_clear(f: int, stream=None) -> None:
+    _check(_L().sbbf_clear(f, _stream(stream)))
+
+
+def sbbf_num_blocks(f: int) -> int:
+    return int(_L().sbbf_num_blocks(f))
+
+
+def sbbf_device_words(f: int) -> int:
+    return _L().sbbf_device_words(f)
+
+
+def sbbf_copy_words_to_host(f: int, host: torch.Tensor, stream=None) -> torch.Tensor:
+    if host.is_cuda or not host.is_contiguous() or host.numel() * host.element_size() != 32 * sbbf_num_blocks(f):
+        raise ValueError("host buffer must be a contiguous CPU tensor of 32 * num_blocks bytes")
+    _check(_L().sbbf_copy_words_to_host(f, ctypes.c_void_p(host.data_ptr()), _stream(stream)))
+    return host
+
+
+def sbbf_copy_words_from_host(f: int, host: torch.Tensor, stream=None) -> None:
+    if host.is_cuda or not host.is_contiguous() or host.numel() * host.element_size() != 32 * sbbf_num_blocks(f):
+        raise ValueError("host buffer must be a contiguous CPU tensor of 32 * num_blocks bytes")
+    _check(_L().sbbf_copy_words_from_host(f, ctypes.c_void_p(host.data_ptr()), _stream(stream)))
+
+
+def sbbf_insert_batch(f: int, hashes: torch.Tensor, stream=None) -> None:
+    p, n = _hashes(hashes)
+    _check(_L().sbbf_insert_batch(f, p, n, _stream(stream)))
+
+
+def sbbf_insert_batch_ex(f: int, hashes: torch.Tensor, launch=None, stream=None) -> None:
+    p, n = _hashes(hashes)
+    _check(_L().sbbf_insert_batch_ex(f, p, n, _launch(launch), _stream(stream)))
+
+
+def _out_bytes(out, n, device):
+    if out is None:
+        return torch.empty(n, dtype=torch.uint8, device=device)
+    if out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+        raise ValueError("out must be a contiguous uint8 CUDA tensor of at least n elements")
+    return out
+
+
+def _out_bits(bits, n, device):
+    words = (n + 31) // 32
+    if bits is None:
+        return torch.empty(words, dtype=torch.int32, device=device)
+    if bits.dtype not in (torch.int32, torch.uint32) or not bits.is_cuda or not bits.is_contiguous() \
+            or bits.numel() < words:
+        raise ValueError("bits must be a contiguous int32 CUDA tensor of at least ceil(n/32) words")
+    return bits
+
+
+def sbbf_lookup_batch(f: int, hashes: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    p, n = _hashes(hashes)
+    out = _out_bytes(out, n, hashes.device)
+    _check(_L().sbbf_lookup_batch(f, p, n, ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def sbbf_lookup_batch_bits(f: int, hashes: torch.Tensor, bits: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+    p, n = _hashes(hashes)
+    bits = _out_bits(bits, n, hashes.device)
+    _check(_L().sbbf_lookup_batch_bits(f, p, n, ctypes.c_void_p(bits.data_ptr()), _stream(stream)))
+    return bits
+
+
+def sbbf_lookup_batch_ex(f: int, hashes: torch.Tensor, out: torch.Tensor | None = None,
+                         bits: torch.Tensor | None = None, launch=None, stream=None) -> torch.Tensor:
+    p, n = _hashes(hashes)
+    if bits is not None and out is not None:
+        raise ValueError("give out or bits, not both")
+    if bits is None:
+        out = _out_bytes(out, n, hashes.device)
+        _check(_L().sbbf_lookup_batch_ex(f, p, n, ctypes.c_void_p(out.data_ptr()), None, _launch(launch),
+                                        _stream(stream)))
+        return out
+    bits = _out_bits(bits, n, hashes.device)
+    _check(_L().sbbf_lookup_batch_ex(f, p, n, None, ctypes.c_void_p(bits.data_ptr()), _launch(launch),
+                                    _stream(stream)))
+    return bits
+
+
+# ---- measurement kernels ----------------------------------------------------------------
+
+def sbbf_bench_gather(buf: torch.Tensor, num_blocks: int, hashes: torch.Tensor, out: torch.Tensor,
+                      launch=None, stream=None) -> None:
+    p, n = _hashes(hashes)
+    _check(_L().sbbf_bench_gather(ctypes.c_void_p(buf.data_ptr()), num_blocks, p, n, ctypes.c_void_p(out.data_ptr()),
+                                 _launch(launch), _stream(stream)))
+
+
+def sbbf_bench_atomic(buf: torch.Tensor, num_blocks: int, hashes: torch.Tensor, launch=None, stream=None) -> None:
+    p, n = _hashes(hashes)
+    _check(_L().sbbf_bench_atomic(ctypes.c_void_p(buf.data_ptr()), num_blocks, p, n, _launch(launch),
+                                 _stream(stream)))
+
+
+def sbbf_bench_stream(hashes: torch.Tensor, out: torch.Tensor, launch=None, stream=None) -> None:
+    p, n = _hashes(hashes)
+    _check(_L().sbbf_bench_stream(p, n, ctypes.c_void_p(out.data_ptr()), _launch(launch), _stream(stream)))
+
+
+# ---- convenience --------------------------------------------------------------------------
+
+class Filter:
+    """A filter whose words live in a torch tensor (so they can be read back
+    with ``words.cpu()``), driven through the C ABI."""
+
+    def __init__(self, num_blocks: int, device="cuda"):
+        if not 1 <= num_blocks <= 0xFFFFFFFF:
+            raise ValueError("num_blocks must be in [1, 2**32 - 1]")
+        self.num_blocks = int(num_blocks)
+        self.words = torch.zeros(8 * self.num_blocks, dtype=torch.int32, device=device)
+        self.handle = sbbf_create_wrapped(self.words, self.num_blocks)
+
+    def insert(self, hashes, launch=None, stream=None):
+        sbbf_insert_batch_ex(self.handle, hashes, launch, stream)
+        return self
+
+    def lookup(self, hashes, out=None, launch=None, stream=None):
+        return sbbf_lookup_batch_ex(self.handle, hashes, out=out, launch=launch, stream=stream)
+
+    def lookup_bits(self, hashes, bits=None, launch=None, stream=None):
+        return sbbf_lookup_batch_ex(self.handle, hashes, bits=bits if bits is not None else _out_bits(
+            None, hashes.numel(), hashes.device), launch=launch, stream=stream)
+
+    def clear(self, stream=None):
+        sbbf_clear(self.handle, stream)
+        return self
+
+    def close(self):
+        if self.handle:
+            sbbf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,88 @@
+"""ctypes declarations of the C ABI in include/sbbf.h.
+
+The library is loaded from this package directory. torch is imported first so
+that the HIP runtime bundled with torch is the one the library binds to (both
+carry the soname libamdhip64.so.7; whichever is loaded first serves both), and
+torch's streams are then valid handles for the library.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading the library; see above)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsbbf.so")
+
+c_u32 = ctypes.c_uint32
+c_u64 = ctypes.c_uint64
+c_size = ctypes.c_size_t
+c_vp = ctypes.c_void_p
+c_int = ctypes.c_int
+
+
+class sbbf_launch(ctypes.Structure):
+    _fields_ = [("block_threads", c_u32), ("grid_blocks", c_u32), ("unroll", c_u32), ("strategy", c_u32)]
+
+
+class sbbf_device_info(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("compute_units", ctypes.c_int32),
+        ("max_threads_per_block", ctypes.c_int32),
+        ("warp_size", ctypes.c_int32),
+        ("lds_per_block", c_u64),
+        ("lds_per_cu", c_u64),
+        ("l2_bytes", c_u64),
+        ("global_mem_bytes", c_u64),
+        ("clock_khz", ctypes.c_int32),
+        ("memory_clock_khz", ctypes.c_int32),
+        ("memory_bus_bits", ctypes.c_int32),
+        ("arch", ctypes.c_char * 64),
+    ]
+
+
+# name -> (restype, argtypes); every symbol declared in include/sbbf.h.
+SIGNATURES = {
+    "sbbf_status_string": (ctypes.c_char_p, [c_int]),
+    "sbbf_last_error": (ctypes.c_char_p, []),
+    "sbbf_device_query": (c_int, [ctypes.POINTER(sbbf_device_info)]),
+    "sbbf_blocks_for": (c_u64, [c_u64, ctypes.c_double]),
+    "sbbf_create": (c_int, [c_u32, ctypes.POINTER(c_vp)]),
+    "sbbf_create_wrapped": (c_int, [c_vp, c_u32, ctypes.POINTER(c_vp)]),
+    "sbbf_destroy": (c_int, [c_vp]),
+    "sbbf_clear": (c_int, [c_vp, c_vp]),
+    "sbbf_num_blocks": (c_u32, [c_vp]),
+    "sbbf_device_words": (c_vp, [c_vp]),
+    "sbbf_copy_words_to_host": (c_int, [c_vp, c_vp, c_vp]),
+    "sbbf_copy_words_from_host": (c_int, [c_vp, c_vp, c_vp]),
+    "sbbf_insert_batch": (c_int, [c_vp, c_vp, c_size, c_vp]),
+    "sbbf_insert_batch_ex": (c_int, [c_vp, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_lookup_batch": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp]),
+    "sbbf_lookup_batch_bits": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp]),
+    "sbbf_lookup_batch_ex": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_bench_gather": (c_int, [c_vp, c_u32, c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_bench_atomic": (c_int, [c_vp, c_u32, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_bench_stream": (c_int, [c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsbbf.so, failing loudly when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2101_01719_amd.build` "
+                          "(the library has no fallback path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,347 @@
+// C ABI of the library: handles, argument checks, launch-shape defaults and
+// dispatch to the kernels. Every public function is declared in sbbf.h.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "sbbf.h"
+
+namespace sbbf {
+namespace {
+
+thread_local std::string t_last_error;
+
+std::mutex g_info_mu;
+std::vector<sbbf_device_info> g_info;  // indexed by device id
+std::vector<bool> g_info_valid;
+
+// Default launch shape: 256-thread workgroups and enough of them to give every
+// compute unit 8 workgroups (32 waves) when the batch is large enough; the
+// grid-stride loop covers the rest.
+constexpr uint32_t kDefaultThreads = 256;
+constexpr uint32_t kDefaultBlocksPerCU = 8;
+
+bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+}  // namespace
+
+sbbf_status set_error(sbbf_status s, const std::string &msg) {
+  t_last_error = msg;
+  return s;
+}
+
+sbbf_status hip_error(hipError_t e, const char *what) {
+  if (e == hipSuccess) return SBBF_OK;
+  std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return set_error(e == hipErrorOutOfMemory ? SBBF_ENOMEM : SBBF_EDEVICE, m);
+}
+
+void clear_error() { t_last_error.clear(); }
+
+const sbbf_device_info &device_info(int device) {
+  std::lock_guard<std::mutex> lock(g_info_mu);
+  if ((int)g_info.size() <= device) {
+    g_info.resize(device + 1);
+    g_info_valid.resize(device + 1, false);
+  }
+  if (!g_info_valid[device]) {
+    sbbf_device_info info;
+    memset(&info, 0, sizeof(info));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      info.device = device;
+      info.compute_units = prop.multiProcessorCount;
+      info.max_threads_per_block = prop.maxThreadsPerBlock;
+      info.warp_size = prop.warpSize;
+      info.lds_per_block = prop.sharedMemPerBlock;
+      info.lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+      info.l2_bytes = (uint64_t)prop.l2CacheSize;
+      info.global_mem_bytes = prop.totalGlobalMem;
+      info.clock_khz = prop.clockRate;
+      info.memory_clock_khz = prop.memoryClockRate;
+      info.memory_bus_bits = prop.memoryBusWidth;
+      snprintf(info.arch, sizeof(info.arch), "%s", prop.gcnArchName);
+      g_info[device] = info;
+      g_info_valid[device] = true;
+    } else {
+      (void)hipGetLastError();
+      return g_info[device];  // zeros; callers check compute_units
+    }
+  }
+  return g_info[device];
+}
+
+const sbbf_device_info *current_device_info(sbbf_status *st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *st = hip_error(e, "hipGetDevice");
+    return nullptr;
+  }
+  const sbbf_device_info &info = device_info(dev);
+  if (info.compute_units <= 0) {
+    *st = set_error(SBBF_EDEVICE, "hipGetDeviceProperties failed");
+    return nullptr;
+  }
+  *st = SBBF_OK;
+  return &info;
+}
+
+sbbf_status resolve_shape(const sbbf_launch *cfg, uint64_t n, uint32_t default_unroll, Shape *out,
+                          uint32_t max_unroll) {
+  sbbf_status st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  uint32_t threads = cfg && cfg->block_threads ? cfg->block_threads : kDefaultThreads;
+  uint32_t unroll = cfg && cfg->unroll ? cfg->unroll : default_unroll;
+  if (threads < 64 || threads > 1024 || threads % 64 != 0)
+    return set_error(SBBF_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+  if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+    return set_error(SBBF_EINVAL, "unroll must be 1, 2, 4 or 8");
+  if (unroll > max_unroll)
+    return set_error(SBBF_EINVAL, "unroll must be at most " + std::to_string(max_unroll) + " for this kernel");
+  uint32_t grid = cfg ? cfg->grid_blocks : 0;
+  if (grid == 0) {
+    const uint64_t keys_per_block = (uint64_t)(threads / 64) * 64u * unroll;
+    const uint64_t need = (n + keys_per_block - 1) / keys_per_block;
+    const uint64_t cap = (uint64_t)info->compute_units * kDefaultBlocksPerCU * (kDefaultThreads / 64) / (threads / 64);
+    grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
+  }
+  out->threads = threads;
+  out->grid = grid;
+  out->unroll = unroll;
+  return SBBF_OK;
+}
+
+}  // namespace sbbf
+
+using namespace sbbf;
+
+extern "C" {
+
+const char *sbbf_status_string(sbbf_status s) {
+  switch (s) {
+    case SBBF_OK: return "ok";
+    case SBBF_EINVAL: return "invalid argument";
+    case SBBF_ENOMEM: return "out of memory";
+    case SBBF_EDEVICE: return "device error";
+    case SBBF_EBUDGET: return "over budget";
+    case SBBF_EUNSUPPORTED: return "unsupported";
+    case SBBF_EAGAIN: return "try again";
+  }
+  return "unknown status";
+}
+
+const char *sbbf_last_error(void) { return t_last_error.c_str(); }
+
+sbbf_status sbbf_device_query(sbbf_device_info *out) {
+  if (!out) return set_error(SBBF_EINVAL, "out is NULL");
+  sbbf_status st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  *out = *info;
+  return SBBF_OK;
+}
+
+uint64_t sbbf_blocks_for(uint64_t n, double bits_per_key) {
+  if (!(bits_per_key > 0.0) || !std::isfinite(bits_per_key)) return 0;
+  const long double bits = (long double)n * (long double)bits_per_key;
+  const long double blocks = std::ceil(bits / 256.0L);
+  if (blocks > 4294967295.0L) return 0;
+  return blocks < 1.0L ? 1 : (uint64_t)blocks;
+}
+
+sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out) {
+  if (!out) return set_error(SBBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (num_blocks == 0) return set_error(SBBF_EINVAL, "num_blocks must be >= 1");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  void *p = nullptr;
+  const size_t bytes = (size_t)num_blocks * 32u;
+  e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) return hip_error(e, "hipMalloc(filter)");
+  e = hipMemset(p, 0, bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_error(e, "hipMemset(filter)");
+  }
+  sbbf_filter *f = new (std::nothrow) sbbf_filter{static_cast<uint32_t *>(p), num_blocks, true, dev};
+  if (!f) {
+    (void)hipFree(p);
+    return set_error(SBBF_ENOMEM, "handle allocation failed");
+  }
+  *out = f;
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_create_wrapped(void *d_words, uint32_t num_blocks, sbbf_filter **out) {
+  if (!out) return set_error(SBBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d_words) return set_error(SBBF_EINVAL, "d_words is NULL");
+  if (num_blocks == 0) return set_error(SBBF_EINVAL, "num_blocks must be >= 1");
+  if (!aligned(d_words, 32)) return set_error(SBBF_EINVAL, "filter memory must be 32-byte aligned");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  sbbf_filter *f = new (std::nothrow) sbbf_filter{static_cast<uint32_t *>(d_words), num_blocks, false, dev};
+  if (!f) return set_error(SBBF_ENOMEM, "handle allocation failed");
+  *out = f;
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_destroy(sbbf_filter *f) {
+  if (!f) return set_error(SBBF_EINVAL, "filter is NULL");
+  sbbf_status st = SBBF_OK;
+  if (f->owned) {
+    hipError_t e = hipFree(f->words);
+    if (e != hipSuccess) st = hip_error(e, "hipFree(filter)");
+  }
+  delete f;
+  return st;
+}
+
+sbbf_status sbbf_clear(sbbf_filter *f, sbbf_stream s) {
+  if (!f) return set_error(SBBF_EINVAL, "filter is NULL");
+  return hip_error(launch_fill(f->words, (uint64_t)f->num_blocks * 8u, 0u, (hipStream_t)s), "clear");
+}
+
+uint32_t sbbf_num_blocks(const sbbf_filter *f) { return f ? f->num_blocks : 0; }
+
+sbbf_status sbbf_copy_words_to_host(const sbbf_filter *f, void *host_dst, sbbf_stream s) {
+  if (!f || !host_dst) return set_error(SBBF_EINVAL, "filter or host_dst is NULL");
+  return hip_error(hipMemcpyAsync(host_dst, f->words, (size_t)f->num_blocks * 32u, hipMemcpyDeviceToHost,
+                                  (hipStream_t)s),
+                   "hipMemcpyAsync(filter to host)");
+}
+
+sbbf_status sbbf_copy_words_from_host(sbbf_filter *f, const void *host_src, sbbf_stream s) {
+  if (!f || !host_src) return set_error(SBBF_EINVAL, "filter or host_src is NULL");
+  return hip_error(hipMemcpyAsync(f->words, host_src, (size_t)f->num_blocks * 32u, hipMemcpyHostToDevice,
+                                  (hipStream_t)s),
+                   "hipMemcpyAsync(filter from host)");
+}
+
+void *sbbf_device_words(const sbbf_filter *f) { return f ? f->words : nullptr; }
+
+static sbbf_status check_batch(const sbbf_filter *f, const void *d_hashes, size_t n, const void *d_out,
+                               const char *out_name, uintptr_t out_align) {
+  if (!f) return set_error(SBBF_EINVAL, "filter is NULL");
+  if (n == 0) return SBBF_OK;
+  if (!d_hashes) return set_error(SBBF_EINVAL, "d_hashes is NULL");
+  if (!aligned(d_hashes, 8)) return set_error(SBBF_EINVAL, "d_hashes must be 8-byte aligned");
+  if (out_name) {
+    if (!d_out) return set_error(SBBF_EINVAL, std::string(out_name) + " is NULL");
+    if (!aligned(d_out, out_align))
+      return set_error(SBBF_EINVAL, std::string(out_name) + " is not aligned to " + std::to_string(out_align));
+  }
+  return SBBF_OK;
+}
+
+// Library choice of insert strategy (used for SBBF_INSERT_AUTO): global 32-bit
+// atomics, the layout with the most independent memory operations in flight.
+static uint32_t auto_insert_strategy(const sbbf_filter *, size_t) { return SBBF_INSERT_ATOMIC32; }
+
+sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_t n, const sbbf_launch *cfg,
+                                 sbbf_stream s) {
+  sbbf_status st = check_batch(f, d_hashes, n, nullptr, nullptr, 1);
+  if (st != SBBF_OK || n == 0) return st;
+  uint32_t strategy = cfg ? cfg->strategy : SBBF_INSERT_AUTO;
+  if (strategy == SBBF_INSERT_AUTO) strategy = auto_insert_strategy(f, n);
+  Shape shape;
+  hipStream_t stream = (hipStream_t)s;
+  switch (strategy) {
+    case SBBF_INSERT_ATOMIC32:
+      if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
+      return hip_error(launch_insert_atomic32(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
+    case SBBF_INSERT_ATOMIC64:
+      if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
+      return hip_error(launch_insert_atomic64(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
+    case SBBF_INSERT_LDS: {
+      const sbbf_device_info *info = current_device_info(&st);
+      if (!info) return st;
+      if ((uint64_t)f->num_blocks * 32u > info->lds_per_block)
+        return set_error(SBBF_EUNSUPPORTED, "filter does not fit one workgroup's LDS (" +
+                                                std::to_string(info->lds_per_block) + " bytes)");
+      sbbf_launch c = cfg ? *cfg : sbbf_launch{0, 0, 0, 0};
+      if (c.block_threads == 0) c.block_threads = 1024;
+      if (c.grid_blocks == 0) c.grid_blocks = 1;
+      if ((st = resolve_shape(&c, n, 2, &shape)) != SBBF_OK) return st;
+      return hip_error(launch_insert_lds(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
+    }
+    default:
+      return set_error(SBBF_EINVAL, "unknown insert strategy");
+  }
+}
+
+sbbf_status sbbf_insert_batch(sbbf_filter *f, const uint64_t *d_hashes, size_t n, sbbf_stream s) {
+  return sbbf_insert_batch_ex(f, d_hashes, n, nullptr, s);
+}
+
+sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
+                                 uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s) {
+  if ((d_out == nullptr) == (d_bits == nullptr) && n > 0)
+    return set_error(SBBF_EINVAL, "exactly one of d_out and d_bits must be non-NULL");
+  sbbf_status st = d_bits ? check_batch(f, d_hashes, n, d_bits, "d_bits", 4)
+                          : check_batch(f, d_hashes, n, d_out, "d_out", 1);
+  if (st != SBBF_OK || n == 0) return st;
+  Shape shape;
+  if ((st = resolve_shape(cfg, n, 2, &shape, 4)) != SBBF_OK) return st;
+  return hip_error(launch_lookup(d_hashes, n, f->words, f->num_blocks, d_out, d_bits, shape, (hipStream_t)s),
+                   "lookup");
+}
+
+sbbf_status sbbf_lookup_batch(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
+                              sbbf_stream s) {
+  return sbbf_lookup_batch_ex(f, d_hashes, n, d_out, nullptr, nullptr, s);
+}
+
+sbbf_status sbbf_lookup_batch_bits(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint32_t *d_bits,
+                                   sbbf_stream s) {
+  return sbbf_lookup_batch_ex(f, d_hashes, n, nullptr, d_bits, nullptr, s);
+}
+
+sbbf_status sbbf_bench_gather(const uint32_t *d_buf, uint32_t num_blocks, const uint64_t *d_hashes, size_t n,
+                              uint8_t *d_out, const sbbf_launch *cfg, sbbf_stream s) {
+  if (!d_buf || num_blocks == 0) return set_error(SBBF_EINVAL, "bad buffer");
+  if (n == 0) return SBBF_OK;
+  if (!d_hashes || !d_out || !aligned(d_hashes, 8)) return set_error(SBBF_EINVAL, "bad hashes or output");
+  Shape shape;
+  sbbf_status st = resolve_shape(cfg, n, 2, &shape, 4);
+  if (st != SBBF_OK) return st;
+  return hip_error(launch_bench_gather(d_buf, num_blocks, d_hashes, n, d_out, shape, (hipStream_t)s), "gather");
+}
+
+sbbf_status sbbf_bench_atomic(uint32_t *d_buf, uint32_t num_blocks, const uint64_t *d_hashes, size_t n,
+                              const sbbf_launch *cfg, sbbf_stream s) {
+  if (!d_buf || num_blocks == 0 || !aligned(d_buf, 32)) return set_error(SBBF_EINVAL, "bad buffer");
+  if (n == 0) return SBBF_OK;
+  if (!d_hashes || !aligned(d_hashes, 8)) return set_error(SBBF_EINVAL, "bad hashes");
+  Shape shape;
+  sbbf_status st = resolve_shape(cfg, n, 2, &shape);
+  if (st != SBBF_OK) return st;
+  const bool wide = cfg && cfg->strategy == SBBF_INSERT_ATOMIC64;
+  return hip_error(launch_bench_atomic(d_buf, num_blocks, d_hashes, n, wide, shape, (hipStream_t)s), "atomic");
+}
+
+sbbf_status sbbf_bench_stream(const uint64_t *d_hashes, size_t n, uint8_t *d_out, const sbbf_launch *cfg,
+                              sbbf_stream s) {
+  if (n == 0) return SBBF_OK;
+  if (!d_hashes || !d_out || !aligned(d_hashes, 8)) return set_error(SBBF_EINVAL, "bad hashes or output");
+  Shape shape;
+  sbbf_status st = resolve_shape(cfg, n, 2, &shape);
+  if (st != SBBF_OK) return st;
+  return hip_error(launch_bench_stream(d_hashes, n, d_out, shape, (hipStream_t)s), "stream");
+}
+
+}  // extern "C"

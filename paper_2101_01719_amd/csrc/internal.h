@@ -1,0 +1,61 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "sbbf.h"
+
+struct sbbf_filter {
+  uint32_t *words;      // 8 * num_blocks uint32, 32-byte aligned device memory
+  uint32_t num_blocks;  // 1 .. 2^32 - 1
+  bool owned;           // memory allocated by sbbf_create
+  int device;           // device current when the handle was made
+};
+
+namespace sbbf {
+
+// Resolved launch shape of one plain kernel call.
+struct Shape {
+  uint32_t threads;  // workgroup size, multiple of 64
+  uint32_t grid;     // workgroups
+  uint32_t unroll;   // 64-key chunks per wave in flight (1, 2, 4, 8)
+};
+
+// Cached device facts (per device, queried once).
+const sbbf_device_info &device_info(int device);
+const sbbf_device_info *current_device_info(sbbf_status *st);
+
+// Thread-local error text and status helpers.
+sbbf_status set_error(sbbf_status s, const std::string &msg);
+sbbf_status hip_error(hipError_t e, const char *what);
+void clear_error();
+
+// Launch-shape resolution: fills zero fields with defaults for n keys.
+sbbf_status resolve_shape(const sbbf_launch *cfg, uint64_t n, uint32_t default_unroll, Shape *out,
+                          uint32_t max_unroll = 8);
+
+// Kernel launchers (plain_kernels.hip). All are asynchronous on `stream`.
+hipError_t launch_lookup(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
+                         uint8_t *out8, uint32_t *out_bits, const Shape &shape, hipStream_t stream);
+hipError_t launch_insert_atomic32(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
+                                  const Shape &shape, hipStream_t stream);
+hipError_t launch_insert_atomic64(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
+                                  const Shape &shape, hipStream_t stream);
+// LDS-private insert. With shape.grid == 1 the single workgroup owns the
+// filter (load, OR, plain store); with more, each workgroup ORs a zeroed
+// private copy and merges its non-zero words with global atomics.
+hipError_t launch_insert_lds(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
+                             const Shape &shape, hipStream_t stream);
+hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipStream_t stream);
+
+hipError_t launch_bench_gather(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n,
+                               uint8_t *out, const Shape &shape, hipStream_t stream);
+hipError_t launch_bench_atomic(uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n, bool wide,
+                               const Shape &shape, hipStream_t stream);
+hipError_t launch_bench_stream(const uint64_t *hashes, uint64_t n, uint8_t *out, const Shape &shape,
+                               hipStream_t stream);
+
+}  // namespace sbbf

@@ -1,0 +1,83 @@
+// Device-side building blocks of the split block Bloom filter on gfx950.
+//
+// Work layout used by every kernel: a wave of 64 lanes is eight groups of
+// eight lanes. A key is handled by one group, and lane j of the group owns
+// word j of the key's 256-bit block, so a block access is one 32-byte piece
+// of memory touched by eight neighbouring lanes. Each lane keeps the seed of
+// its own word in a register.
+//
+// Keys are staged 64 at a time: lane l loads hash l of a 64-hash chunk
+// (a coalesced 512-byte read), and in pass p (0..7) group g takes the key held
+// by lane 8g + p, fetched with a cross-lane permute. After the eight passes
+// the wave has handled key l in group l / 8 during pass l % 8, which is what
+// lets lookups rebuild a per-lane result with scalar bit operations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbbf {
+
+constexpr int kWave = 64;
+constexpr int kLanesPerKey = 8;
+
+// The eight odd multiply-shift seeds, in word (lane) order: word 2k uses the
+// low half and word 2k+1 the high half of the k-th 64-bit constant printed in
+// the paper's appendix figure (a 256-bit vector built from four 64-bit values
+// on little-endian x86 holds them in that order).
+constexpr uint32_t kSeed0 = 0x44974d91u;
+constexpr uint32_t kSeed1 = 0x47b6137bu;
+constexpr uint32_t kSeed2 = 0xa2b7289du;
+constexpr uint32_t kSeed3 = 0x8824ad5bu;
+constexpr uint32_t kSeed4 = 0x2df1424bu;
+constexpr uint32_t kSeed5 = 0x705495c7u;
+constexpr uint32_t kSeed6 = 0x5c6bfb31u;
+constexpr uint32_t kSeed7 = 0x9efc4947u;
+
+// Seed of word j (0..7); a select chain, evaluated once per kernel.
+__device__ __forceinline__ uint32_t seed_of_word(uint32_t j) {
+  const uint32_t a = (j & 1) ? kSeed1 : kSeed0;
+  const uint32_t b = (j & 1) ? kSeed3 : kSeed2;
+  const uint32_t c = (j & 1) ? kSeed5 : kSeed4;
+  const uint32_t d = (j & 1) ? kSeed7 : kSeed6;
+  const uint32_t ab = (j & 2) ? b : a;
+  const uint32_t cd = (j & 2) ? d : c;
+  return (j & 4) ? cd : ab;
+}
+
+// Block of a hash: high 32 bits of hi32(h) * num_blocks (a 32x32 multiply-high).
+__device__ __forceinline__ uint32_t block_of(uint32_t hash_hi, uint32_t num_blocks) {
+  return __umulhi(hash_hi, num_blocks);
+}
+
+// Bit position in [0, 32) chosen for one word: top five bits of the low 32
+// bits of seed * x.
+__device__ __forceinline__ uint32_t bit_of(uint32_t seed, uint32_t hash_lo) {
+  return (seed * hash_lo) >> 27;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Value of `v` in lane `src` (0..63) of this wave.
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+
+// Wave-wide ballot of a predicate.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Streaming (non-temporal) load of one hash: the hash arrays are read once
+// and should not displace the filter from the caches.
+__device__ __forceinline__ uint64_t load_hash(const uint64_t *p) { return __builtin_nontemporal_load(p); }
+
+// From the eight ballots of one 64-key chunk (pass p holds, in byte g, the
+// eight word tests of the key of lane 8g + p), build the 64-bit result mask
+// whose bit l is 1 when all eight word tests of the key of lane l passed.
+__device__ __forceinline__ uint64_t fold_pass(uint64_t m, int p) {
+  uint64_t t = m & (m >> 4);
+  t &= t >> 2;
+  t &= t >> 1;
+  return (t & 0x0101010101010101ull) << p;
+}
+
+}  // namespace sbbf

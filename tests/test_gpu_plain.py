@@ -1,0 +1,271 @@
+"""Parity of the HIP path with the CPU oracle for single filters.
+
+Every comparison is exact: filter words byte-for-byte, lookup bytes and packed
+lookup bits element-for-element. All calls go through the C ABI (via the
+Python binding of the same names).
+"""
+
+import hashlib
+import re
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from conftest import read_golden  # noqa: E402
+from synth import plain_workload, splitmix64_stream  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+STRATEGIES = {
+    "atomic32": dict(strategy=1),
+    "atomic64": dict(strategy=2),
+    "lds_owner": dict(strategy=3, grid_blocks=1),
+    "lds_merge8": dict(strategy=3, grid_blocks=8),
+}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2101_01719_amd as P
+
+    return P
+
+
+def dev(a: np.ndarray) -> "torch.Tensor":
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+
+
+def words_of(f) -> np.ndarray:
+    torch.cuda.synchronize()
+    return f.words.cpu().numpy().view(np.uint32)
+
+
+def sha16(words: np.ndarray) -> str:
+    return hashlib.sha256(words.astype("<u4").tobytes()).hexdigest()[:16]
+
+
+def test_device_and_runtime(P):
+    info = P.sbbf_device_query()
+    print("device:", info)
+    assert info["arch"].startswith("gfx950")
+    assert info["compute_units"] > 0 and info["warp_size"] == 64
+    assert info["lds_per_block"] >= 65536
+    maps = open("/proc/self/maps").read()
+    assert len(set(re.findall(r"\S*libamdhip64\S*", maps))) == 1
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 5, 8, 13])
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
+def test_tiny_filters(P, B, strategy):
+    h = splitmix64_stream(100 + B, 64)
+    probes = np.concatenate([h, splitmix64_stream(200 + B, 300)])
+    f = P.Filter(B)
+    f.insert(dev(h), launch=STRATEGIES[strategy])
+    got = f.lookup(dev(probes)).cpu().numpy()
+    ref = oracle.build_filter(B, h)
+    assert np.array_equal(words_of(f), ref)
+    assert np.array_equal(got, oracle.lookup(ref, B, probes))
+
+
+RAGGED = [1, 2, 7, 8, 9, 63, 64, 65, 127, 128, 129, 255, 257, 511, 513, 1000, 4095, 4097, 65537]
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_ragged_counts(P, n):
+    B = 37
+    h = splitmix64_stream(300, n)
+    probes = splitmix64_stream(301, n + 77)
+    probes[: n // 2] = h[: n // 2]
+    ref = oracle.build_filter(B, h)
+    ref_look = oracle.lookup(ref, B, probes)
+    ref_bits = oracle.lookup_bits(ref, B, probes)
+    for name, launch in STRATEGIES.items():
+        f = P.Filter(B)
+        f.insert(dev(h), launch=launch)
+        assert np.array_equal(words_of(f), ref), name
+        for unroll in (1, 2, 4):
+            got = f.lookup(dev(probes), launch=dict(unroll=unroll)).cpu().numpy()
+            assert np.array_equal(got, ref_look), (name, unroll)
+            bits = f.lookup_bits(dev(probes), launch=dict(unroll=unroll)).cpu().numpy().view(np.uint32)
+            assert np.array_equal(bits, ref_bits), (name, unroll)
+        f.close()
+
+
+@pytest.mark.parametrize("threads", [64, 128, 256, 512, 1024])
+@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
+def test_launch_shapes_insert(P, threads, unroll):
+    B = 1000
+    h = splitmix64_stream(400, 50_001)
+    ref = oracle.build_filter(B, h)
+    for strat in (1, 2):
+        for grid in (0, 1, 3):
+            f = P.Filter(B)
+            f.insert(dev(h), launch=dict(block_threads=threads, unroll=unroll, strategy=strat, grid_blocks=grid))
+            assert np.array_equal(words_of(f), ref), (strat, grid)
+            f.close()
+
+
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+@pytest.mark.parametrize("unroll", [1, 2, 4])
+def test_launch_shapes_lookup(P, threads, unroll):
+    B = 1000
+    h = splitmix64_stream(401, 30_000)
+    probes = np.concatenate([h[:10_000], splitmix64_stream(402, 40_003)])
+    ref = oracle.build_filter(B, h)
+    ref_look = oracle.lookup(ref, B, probes)
+    f = P.Filter(B)
+    f.insert(dev(h))
+    for grid in (0, 1, 5):
+        got = f.lookup(dev(probes), launch=dict(block_threads=threads, unroll=unroll, grid_blocks=grid)).cpu().numpy()
+        assert np.array_equal(got, ref_look), grid
+
+
+def _paper_row(name):
+    return [r for r in read_golden("paper_code_configs.txt") if r[0] == name][0]
+
+
+@pytest.mark.parametrize("name", ["plain_100k", "plain_1m"])
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
+def test_plain_workloads(P, name, strategy):
+    w = plain_workload(name)
+    launch = STRATEGIES[strategy]
+    if strategy.startswith("lds") and w.num_blocks * 32 > P.sbbf_device_query()["lds_per_block"]:
+        pytest.skip("filter larger than one workgroup's LDS")
+    f = P.Filter(w.num_blocks)
+    f.insert(dev(w.inserts), launch=launch)
+    look = dev(w.lookups)
+    got = f.lookup(look).cpu().numpy()
+    bits = f.lookup_bits(look).cpu().numpy().view(np.uint32)
+    words = words_of(f)
+    ref = oracle.build_filter(w.num_blocks, w.inserts)
+    assert np.array_equal(words, ref)
+    assert sha16(words) == _paper_row(name)[6]
+    ref_look = oracle.lookup(ref, w.num_blocks, w.lookups)
+    assert np.array_equal(got, ref_look)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, w.num_blocks, w.lookups))
+    assert int(got[~w.is_member].sum()) == int(_paper_row(name)[5])
+
+
+def test_insert_accumulates_into_existing_filter(P):
+    B = 2000
+    a = splitmix64_stream(500, 20_000)
+    b = splitmix64_stream(501, 30_000)
+    ref = oracle.build_filter(B, np.concatenate([a, b]))
+    for name, launch in STRATEGIES.items():
+        f = P.Filter(B)
+        f.insert(dev(a), launch=STRATEGIES["atomic32"])
+        f.insert(dev(b), launch=launch)
+        assert np.array_equal(words_of(f), ref), name
+        f.clear()
+        assert not words_of(f).any()
+
+
+def test_library_owned_filter_roundtrip(P):
+    B = 777
+    h = splitmix64_stream(510, 9000)
+    ref = oracle.build_filter(B, h)
+    fh = P.sbbf_create(B)
+    try:
+        P.sbbf_insert_batch(fh, dev(h))
+        host = torch.empty(8 * B, dtype=torch.int32)
+        P.sbbf_copy_words_to_host(fh, host)
+        torch.cuda.synchronize()
+        assert np.array_equal(host.numpy().view(np.uint32), ref)
+        # restore a checkpoint into a fresh filter and keep using it
+        g = P.sbbf_create(B)
+        P.sbbf_copy_words_from_host(g, host)
+        more = splitmix64_stream(511, 5000)
+        P.sbbf_insert_batch(g, dev(more))
+        out = torch.empty(8 * B, dtype=torch.int32)
+        P.sbbf_copy_words_to_host(g, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.numpy().view(np.uint32), oracle.insert(ref.copy(), B, more))
+        P.sbbf_destroy(g)
+    finally:
+        P.sbbf_destroy(fh)
+
+
+def test_empty_batches_and_errors(P):
+    f = P.Filter(64)
+    empty = torch.empty(0, dtype=torch.int64, device="cuda")
+    f.insert(empty)
+    assert f.lookup(empty).numel() == 0
+    assert not words_of(f).any()
+    # LDS strategy on a filter larger than one workgroup's LDS is refused
+    lds = P.sbbf_device_query()["lds_per_block"]
+    big = P.Filter(lds // 32 + 1)
+    with pytest.raises(P.SbbfError) as e:
+        big.insert(dev(splitmix64_stream(1, 10)), launch=dict(strategy=3))
+    assert e.value.status == P.SBBF_EUNSUPPORTED
+    with pytest.raises(P.SbbfError) as e:
+        f.insert(dev(splitmix64_stream(1, 10)), launch=dict(block_threads=96))
+    assert e.value.status == P.SBBF_EINVAL
+    with pytest.raises(P.SbbfError):
+        f.lookup(dev(splitmix64_stream(1, 10)), launch=dict(unroll=8))
+    # misaligned hash pointer
+    import ctypes
+
+    h = dev(splitmix64_stream(1, 16))
+    st = P._L().sbbf_insert_batch(f.handle, ctypes.c_void_p(h.data_ptr() + 4), 4, None)
+    assert st == P.SBBF_EINVAL
+    assert not words_of(f).any()
+
+
+def test_all_ones_filter_reports_every_probe(P):
+    B = 321
+    f = P.Filter(B)
+    f.words.fill_(-1)
+    probes = dev(splitmix64_stream(520, 10_000))
+    assert bool(f.lookup(probes).all())
+    f.clear()
+    assert not bool(f.lookup(probes).any())
+
+
+def test_largest_block_count(P):
+    """num_blocks = 2**32 - 1 (128 GiB of words): block offsets need 64-bit
+    addressing. Checked sparsely: every block a key selects holds exactly the
+    oracle's bits, and the total set-bit count matches."""
+    B = (1 << 32) - 1
+    free, _ = torch.cuda.mem_get_info()
+    if free < 32 * B + (8 << 30):
+        pytest.skip("not enough device memory for a 128 GiB filter")
+    h = np.concatenate([splitmix64_stream(530, 4000), np.array([0, (1 << 64) - 1, 0xFFFFFFFF00000000], np.uint64)])
+    f = P.Filter(B)
+    f.insert(dev(h))
+    torch.cuda.synchronize()
+    blocks = np.array([oracle.block(int(x), B) for x in h.tolist()], dtype=np.int64)
+    got = f.words.view(-1, 8).index_select(0, torch.from_numpy(blocks).to("cuda")).cpu().numpy().view(np.uint32)
+    # oracle on a compacted filter holding only the touched blocks
+    uniq, inv = np.unique(blocks, return_inverse=True)
+    want = np.zeros((uniq.size, 8), dtype=np.uint32)
+    for k, x in enumerate(h.tolist()):
+        want[inv[k]] |= oracle.mask(x & 0xFFFFFFFF)
+    assert np.array_equal(got, want[inv])
+    look = f.lookup(dev(h)).cpu().numpy()
+    assert look.all()
+    f.close()
+    del f
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("strategy", ["atomic32", "atomic64"])
+def test_plain_100m_full(P, strategy):
+    """The 100M-key workload at full size in the launch shape the benchmark
+    times (library defaults): the whole filter and all 2e8 lookups are
+    compared with the oracle."""
+    w = plain_workload("plain_100m", backend="torch", device="cuda")
+    f = P.Filter(w.num_blocks)
+    f.insert(w.inserts, launch=STRATEGIES[strategy])
+    got = f.lookup(w.lookups)
+    torch.cuda.synchronize()
+    words = words_of(f)
+    assert sha16(words) == _paper_row("plain_100m")[6]
+    ins = w.inserts.cpu().numpy().view(np.uint64)
+    ref = oracle.build_filter(w.num_blocks, ins)
+    assert np.array_equal(words, ref)
+    look = w.lookups.cpu().numpy().view(np.uint64)
+    ref_look = oracle.lookup(ref, w.num_blocks, look)
+    assert np.array_equal(got.cpu().numpy(), ref_look)
