@@ -68,16 +68,34 @@ typedef enum sbbf_insert_strategy {
   SBBF_INSERT_AUTO = 0,     /* library choice by filter size and key count */
   SBBF_INSERT_ATOMIC32 = 1, /* one key per 8 lanes, one 32-bit global atomic OR per lane */
   SBBF_INSERT_ATOMIC64 = 2, /* one key per 4 lanes, one 64-bit global atomic OR per lane */
-  SBBF_INSERT_LDS = 3       /* private copies of the whole filter in LDS, OR-merged;
+  SBBF_INSERT_LDS = 3,      /* private copies of the whole filter in LDS, OR-merged;
                                only when 32 * num_blocks fits one workgroup's LDS */
+  SBBF_INSERT_PARTITIONED = 4 /* keys split by filter slice (a slice fits one workgroup's
+                               LDS), then one workgroup ORs each slice in LDS and stores
+                               it back; no global atomics on the filter. Uses a
+                               stream-ordered device workspace of about 8 bytes per key */
 } sbbf_insert_strategy;
+
+/* Memory-access flags of sbbf_launch (cache policy only; results are
+ * identical for every value). */
+enum {
+  SBBF_FILTER_LOAD_DEFAULT = 0u,  /* lookup block reads: cached at every level */
+  SBBF_FILTER_LOAD_NT = 1u,       /* ... with the non-temporal hint */
+  SBBF_FILTER_LOAD_DEVICE = 2u,   /* ... device-coherent (skip the per-CU cache) */
+  SBBF_FILTER_LOAD_SYSTEM = 3u,   /* ... system-coherent */
+  SBBF_FILTER_LOAD_MASK = 3u,
+  SBBF_HASH_LOAD_CACHED = 4u,     /* hash reads without the non-temporal hint */
+  SBBF_RESULT_STORE_NT = 8u,      /* lookup result writes with the non-temporal hint */
+  SBBF_FLAGS_MASK = 15u
+};
 
 /* Launch shape for the plain kernels. Zero fields take library defaults. */
 typedef struct sbbf_launch {
   uint32_t block_threads; /* workgroup size: 64 .. 1024, a multiple of 64 */
   uint32_t grid_blocks;   /* workgroups; for SBBF_INSERT_LDS the number of private copies */
-  uint32_t unroll;        /* 64-key chunks each wave keeps in flight: 1, 2, 4 or 8 */
+  uint32_t unroll;        /* 64-key chunks each wave keeps in flight: 1, 2, 4 or 8 (lookup: at most 4) */
   uint32_t strategy;      /* inserts only: an sbbf_insert_strategy */
+  uint32_t flags;         /* SBBF_* memory-access flags above; 0 = library default */
 } sbbf_launch;
 
 /* Device facts the library uses to size launches (queried once per device). */

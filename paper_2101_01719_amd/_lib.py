@@ -24,7 +24,8 @@ c_int = ctypes.c_int
 
 
 class sbbf_launch(ctypes.Structure):
-    _fields_ = [("block_threads", c_u32), ("grid_blocks", c_u32), ("unroll", c_u32), ("strategy", c_u32)]
+    _fields_ = [("block_threads", c_u32), ("grid_blocks", c_u32), ("unroll", c_u32), ("strategy", c_u32),
+                ("flags", c_u32)]
 
 
 class sbbf_device_info(ctypes.Structure):

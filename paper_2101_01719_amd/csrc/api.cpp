@@ -116,9 +116,12 @@ sbbf_status resolve_shape(const sbbf_launch *cfg, uint64_t n, uint32_t default_u
     const uint64_t cap = (uint64_t)info->compute_units * kDefaultBlocksPerCU * (kDefaultThreads / 64) / (threads / 64);
     grid = (uint32_t)(need < cap ? (need ? need : 1) : cap);
   }
+  const uint32_t flags = cfg ? cfg->flags : 0u;
+  if (flags & ~(uint32_t)SBBF_FLAGS_MASK) return set_error(SBBF_EINVAL, "unknown flag bits");
   out->threads = threads;
   out->grid = grid;
   out->unroll = unroll;
+  out->flags = flags;
   return SBBF_OK;
 }
 
@@ -248,16 +251,63 @@ static sbbf_status check_batch(const sbbf_filter *f, const void *d_hashes, size_
   return SBBF_OK;
 }
 
-// Library choice of insert strategy (used for SBBF_INSERT_AUTO): global 32-bit
-// atomics, the layout with the most independent memory operations in flight.
-static uint32_t auto_insert_strategy(const sbbf_filter *, size_t) { return SBBF_INSERT_ATOMIC32; }
+// Slice size of the partitioned insert: the largest power of two of blocks,
+// at most 4096 (128 KiB), whose words fit one workgroup's LDS.
+static uint32_t partition_slice_shift(const sbbf_device_info &info) {
+  uint32_t shift = 12;
+  while (shift > 6 && ((uint64_t)32u << shift) > info.lds_per_block) --shift;
+  return shift;
+}
+
+// Largest slice count the partitioned kernels accept (their LDS bins).
+static constexpr uint32_t kMaxPartitionSlices = 8192;
+
+static uint32_t partition_slices(uint32_t num_blocks, uint32_t shift) {
+  return (uint32_t)(((uint64_t)num_blocks + (1u << shift) - 1u) >> shift);
+}
+
+// Library choice of insert strategy (SBBF_INSERT_AUTO): the partitioned insert
+// when the batch has at least two keys per block (so the one-time read and
+// write of the whole filter costs less than per-key atomics) and the filter
+// has few enough slices; otherwise global 32-bit atomics.
+static uint32_t auto_insert_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
+  const uint32_t shift = partition_slice_shift(info);
+  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && partition_slices(f->num_blocks, shift) <= kMaxPartitionSlices)
+    return SBBF_INSERT_PARTITIONED;
+  return SBBF_INSERT_ATOMIC32;
+}
+
+// Stream-ordered workspace: allocated from the device's default memory pool
+// on the call's stream and released on it after the kernels, so concurrent
+// calls on different streams never share it. The pool keeps freed memory for
+// reuse instead of returning it at every synchronisation.
+static hipError_t workspace_alloc(void **p, size_t bytes, hipStream_t stream, int device) {
+  static std::mutex mu;
+  static std::vector<bool> configured;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)configured.size() <= device) configured.resize(device + 1, false);
+    if (!configured[device]) {
+      hipMemPool_t pool;
+      if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      }
+      (void)hipGetLastError();
+      configured[device] = true;
+    }
+  }
+  return hipMallocAsync(p, bytes, stream);
+}
 
 sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_t n, const sbbf_launch *cfg,
                                  sbbf_stream s) {
   sbbf_status st = check_batch(f, d_hashes, n, nullptr, nullptr, 1);
   if (st != SBBF_OK || n == 0) return st;
   uint32_t strategy = cfg ? cfg->strategy : SBBF_INSERT_AUTO;
-  if (strategy == SBBF_INSERT_AUTO) strategy = auto_insert_strategy(f, n);
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  if (strategy == SBBF_INSERT_AUTO) strategy = auto_insert_strategy(f, n, *info);
   Shape shape;
   hipStream_t stream = (hipStream_t)s;
   switch (strategy) {
@@ -267,13 +317,27 @@ sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_
     case SBBF_INSERT_ATOMIC64:
       if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
       return hip_error(launch_insert_atomic64(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
+    case SBBF_INSERT_PARTITIONED: {
+      const uint32_t shift = partition_slice_shift(*info);
+      const uint32_t slices = partition_slices(f->num_blocks, shift);
+      if (slices > kMaxPartitionSlices)
+        return set_error(SBBF_EUNSUPPORTED, "filter has more than " + std::to_string(kMaxPartitionSlices) +
+                                                " slices of " + std::to_string(1u << shift) + " blocks");
+      const uint32_t grid = cfg && cfg->grid_blocks ? cfg->grid_blocks : (uint32_t)info->compute_units * 2u;
+      void *ws = nullptr;
+      const size_t bytes = partition_workspace_bytes(n, slices);
+      hipError_t e = workspace_alloc(&ws, bytes, stream, info->device);
+      if (e != hipSuccess) return hip_error(e, "hipMallocAsync(partition workspace)");
+      e = launch_insert_partitioned(d_hashes, n, f->words, f->num_blocks, shift, ws, grid, stream);
+      hipError_t e2 = hipFreeAsync(ws, stream);
+      if (e != hipSuccess) return hip_error(e, "partitioned insert");
+      return hip_error(e2, "hipFreeAsync(partition workspace)");
+    }
     case SBBF_INSERT_LDS: {
-      const sbbf_device_info *info = current_device_info(&st);
-      if (!info) return st;
       if ((uint64_t)f->num_blocks * 32u > info->lds_per_block)
         return set_error(SBBF_EUNSUPPORTED, "filter does not fit one workgroup's LDS (" +
                                                 std::to_string(info->lds_per_block) + " bytes)");
-      sbbf_launch c = cfg ? *cfg : sbbf_launch{0, 0, 0, 0};
+      sbbf_launch c = cfg ? *cfg : sbbf_launch{0, 0, 0, 0, 0};
       if (c.block_threads == 0) c.block_threads = 1024;
       if (c.grid_blocks == 0) c.grid_blocks = 1;
       if ((st = resolve_shape(&c, n, 2, &shape)) != SBBF_OK) return st;

@@ -22,6 +22,7 @@ struct Shape {
   uint32_t threads;  // workgroup size, multiple of 64
   uint32_t grid;     // workgroups
   uint32_t unroll;   // 64-key chunks per wave in flight (1, 2, 4, 8)
+  uint32_t flags;    // SBBF_* memory-access flags
 };
 
 // Cached device facts (per device, queried once).
@@ -50,6 +51,13 @@ hipError_t launch_insert_atomic64(const uint64_t *hashes, uint64_t n, uint32_t *
 hipError_t launch_insert_lds(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                              const Shape &shape, hipStream_t stream);
 hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipStream_t stream);
+
+// Partitioned insert (partition_kernels.hip). Slices hold 2^slice_shift
+// blocks; `workspace` holds partition_workspace_bytes(n, slices) bytes; `grid`
+// sizes the count and scatter kernels.
+uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices);
+hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
+                                     uint32_t slice_shift, void *workspace, uint32_t grid, hipStream_t stream);
 
 hipError_t launch_bench_gather(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n,
                                uint8_t *out, const Shape &shape, hipStream_t stream);

@@ -6,6 +6,8 @@
 // (lookup) the selected 256-bit block. The batch is spread over waves with a
 // grid-stride loop over 64-key chunks; each wave keeps `U` chunks in flight so
 // that 8U independent 32-byte block accesses are outstanding per wave.
+// `kFlags` selects cache policies only (SBBF_* flags); results never depend
+// on it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,13 +31,13 @@ __device__ __forceinline__ WaveCursor wave_cursor() {
 // Stage U chunks of 64 hashes starting at key `base`: block index and low half
 // of the hash held by each lane. Keys at or past n become hash 0 (block 0,
 // always in range); their results are discarded by the callers.
-template <int U>
+template <int U, uint32_t kFlags>
 __device__ __forceinline__ void stage(const uint64_t *__restrict__ hashes, uint64_t n, uint64_t base,
                                       uint32_t num_blocks, uint32_t lane, uint32_t (&blk)[U], uint32_t (&lo)[U]) {
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const uint64_t i = base + (uint64_t)(kWave * u) + lane;
-    const uint64_t h = i < n ? load_hash(hashes + i) : 0ull;
+    const uint64_t h = i < n ? load_hash<kFlags>(hashes + i) : 0ull;
     lo[u] = (uint32_t)h;
     blk[u] = block_of((uint32_t)(h >> 32), num_blocks);
   }
@@ -43,7 +45,7 @@ __device__ __forceinline__ void stage(const uint64_t *__restrict__ hashes, uint6
 
 // ---- lookup -----------------------------------------------------------------
 
-template <int U, bool kBits>
+template <int U, bool kBits, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *__restrict__ words,
               uint32_t num_blocks, uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
@@ -56,7 +58,7 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
 
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
 
     // Issue every block read of the U chunks before testing any of them.
     uint32_t word[U][8], bit[U][8];
@@ -67,7 +69,7 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
         const uint32_t b = lane_read(blk[u], group + p);
         const uint32_t x = lane_read(lo[u], group + p);
         bit[u][p] = bit_of(seed, x);
-        word[u][p] = words[(uint64_t)b * 8u + j];
+        word[u][p] = load_word<kFlags>(words + (uint64_t)b * 8u + j);
       }
     }
 
@@ -79,13 +81,13 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
       const uint64_t i0 = base + (uint64_t)(kWave * u);
       if (i0 >= n) break;
       if constexpr (!kBits) {
-        if (i0 + lane < n) out8[i0 + lane] = (uint8_t)((r >> lane) & 1u);
+        if (i0 + lane < n) store_result<kFlags>(out8 + i0 + lane, (uint8_t)((r >> lane) & 1u));
       } else {
         const uint64_t left = n - i0;
         if (left < 64) r &= (1ull << left) - 1ull;
         const uint64_t w0 = i0 / 32;  // i0 is a multiple of 64
-        if (lane == 0) out_bits[w0] = (uint32_t)r;
-        if (lane == 1 && left > 32) out_bits[w0 + 1] = (uint32_t)(r >> 32);
+        if (lane == 0) store_result<kFlags>(out_bits + w0, (uint32_t)r);
+        if (lane == 1 && left > 32) store_result<kFlags>(out_bits + w0 + 1, (uint32_t)(r >> 32));
       }
     }
   }
@@ -93,7 +95,7 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
 
 // ---- insert: 32-bit global atomics, one key per 8 lanes ---------------------
 
-template <int U>
+template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
                        uint32_t num_blocks) {
@@ -106,7 +108,7 @@ insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -127,7 +129,7 @@ insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 // Lane l handles words 2q and 2q+1 (q = l % 4) of the key of lane 4g + p in
 // pass p (g = l / 4), so a pass covers 16 keys and four passes a chunk.
 
-template <int U>
+template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
                        uint32_t num_blocks) {
@@ -142,7 +144,7 @@ insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -167,7 +169,7 @@ insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 // each starts from zero, ORs its share of the keys, and ORs its non-zero
 // 64-bit word pairs into the filter with global atomics.
 
-template <int U>
+template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
                   uint32_t num_blocks) {
@@ -187,7 +189,7 @@ insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__r
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -232,7 +234,7 @@ __global__ void __launch_bounds__(256) fill_kernel(uint32_t *__restrict__ words,
 // ---- measurement kernels ------------------------------------------------------------
 // Same staging and block addressing as lookup/insert, without the mask.
 
-template <int U>
+template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 bench_gather_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *__restrict__ buf,
                     uint32_t num_blocks, uint8_t *__restrict__ out8) {
@@ -243,12 +245,13 @@ bench_gather_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint3
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
     uint32_t word[U][8];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int p = 0; p < 8; ++p) word[u][p] = buf[(uint64_t)lane_read(blk[u], group + p) * 8u + j];
+      for (int p = 0; p < 8; ++p)
+        word[u][p] = load_word<kFlags>(buf + (uint64_t)lane_read(blk[u], group + p) * 8u + j);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -262,12 +265,12 @@ bench_gather_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint3
         any |= (t & 0x0101010101010101ull) << p;
       }
       const uint64_t i0 = base + (uint64_t)(kWave * u);
-      if (i0 + lane < n) out8[i0 + lane] = (uint8_t)((any >> lane) & 1u);
+      if (i0 + lane < n) store_result<kFlags>(out8 + i0 + lane, (uint8_t)((any >> lane) & 1u));
     }
   }
 }
 
-template <int U, bool kWide>
+template <int U, bool kWide, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 bench_atomic_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ buf,
                     uint32_t num_blocks) {
@@ -279,7 +282,7 @@ bench_atomic_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *_
   const uint32_t group = lane & ~(kLanes - 1u);
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -301,7 +304,7 @@ bench_atomic_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *_
   }
 }
 
-template <int U>
+template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 bench_stream_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint8_t *__restrict__ out8) {
   const uint32_t lane = lane_id();
@@ -312,90 +315,153 @@ bench_stream_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint8_t *__
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t i = base + (uint64_t)(kWave * u) + lane;
-      h[u] = i < n ? load_hash(hashes + i) : 0ull;
+      h[u] = i < n ? load_hash<kFlags>(hashes + i) : 0ull;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t i = base + (uint64_t)(kWave * u) + lane;
-      if (i < n) out8[i] = (uint8_t)(__popcll(h[u]) & 1);
+      if (i < n) store_result<kFlags>(out8 + i, (uint8_t)(__popcll(h[u]) & 1));
     }
   }
 }
 
-// ---- dispatch helpers ---------------------------------------------------------------
+// ---- dispatch -------------------------------------------------------------------------
+// SBBF_DISPATCH_U{4,8}(u, BODY) instantiates BODY(U) for the unroll value u;
+// BODY must end in `return`.
 
-#define SBBF_DISPATCH_UNROLL4(U, CALL) \
-  switch (U) {                        \
-    case 1: CALL(1); break;           \
-    case 2: CALL(2); break;           \
-    case 4: CALL(4); break;           \
+#define SBBF_DISPATCH_U4(u, BODY)         \
+  switch (u) {                            \
+    case 1: { BODY(1) }                   \
+    case 2: { BODY(2) }                   \
+    case 4: { BODY(4) }                   \
     default: return hipErrorInvalidValue; \
   }
 
-#define SBBF_DISPATCH_UNROLL(U, CALL) \
-  switch (U) {                        \
-    case 1: CALL(1); break;           \
-    case 2: CALL(2); break;           \
-    case 4: CALL(4); break;           \
-    case 8: CALL(8); break;           \
+#define SBBF_DISPATCH_U8(u, BODY)         \
+  switch (u) {                            \
+    case 1: { BODY(1) }                   \
+    case 2: { BODY(2) }                   \
+    case 4: { BODY(4) }                   \
+    case 8: { BODY(8) }                   \
     default: return hipErrorInvalidValue; \
   }
+
+// Runs Launcher<F>::run for the flag value F equal to `flags` (0..15).
+template <template <uint32_t> class Launcher, typename... Args>
+hipError_t dispatch_flags(uint32_t flags, Args... args) {
+  switch (flags & SBBF_FLAGS_MASK) {
+    case 0: return Launcher<0>::run(args...);
+    case 1: return Launcher<1>::run(args...);
+    case 2: return Launcher<2>::run(args...);
+    case 3: return Launcher<3>::run(args...);
+    case 4: return Launcher<4>::run(args...);
+    case 5: return Launcher<5>::run(args...);
+    case 6: return Launcher<6>::run(args...);
+    case 7: return Launcher<7>::run(args...);
+    case 8: return Launcher<8>::run(args...);
+    case 9: return Launcher<9>::run(args...);
+    case 10: return Launcher<10>::run(args...);
+    case 11: return Launcher<11>::run(args...);
+    case 12: return Launcher<12>::run(args...);
+    case 13: return Launcher<13>::run(args...);
+    case 14: return Launcher<14>::run(args...);
+    case 15: return Launcher<15>::run(args...);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <uint32_t F>
+struct LookupLauncher {
+  static hipError_t run(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
+                        uint8_t *out8, uint32_t *out_bits, Shape s, hipStream_t stream) {
+    const dim3 g(s.grid), b(s.threads);
+#define BODY(U)                                                                                              \
+  if (out_bits)                                                                                              \
+    hipLaunchKernelGGL((lookup_kernel<U, true, F>), g, b, 0, stream, hashes, n, words, num_blocks, nullptr,  \
+                       out_bits);                                                                            \
+  else                                                                                                       \
+    hipLaunchKernelGGL((lookup_kernel<U, false, F>), g, b, 0, stream, hashes, n, words, num_blocks, out8,    \
+                       nullptr);                                                                             \
+  return hipGetLastError();
+    SBBF_DISPATCH_U4(s.unroll, BODY)
+#undef BODY
+  }
+};
+
+template <uint32_t F>
+struct GatherLauncher {
+  static hipError_t run(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n, uint8_t *out,
+                        Shape s, hipStream_t stream) {
+    const dim3 g(s.grid), b(s.threads);
+#define BODY(U)                                                                                              \
+  hipLaunchKernelGGL((bench_gather_kernel<U, F>), g, b, 0, stream, hashes, n, buf, num_blocks, out);         \
+  return hipGetLastError();
+    SBBF_DISPATCH_U4(s.unroll, BODY)
+#undef BODY
+  }
+};
+
+// Inserts only use the hash-load flag, so each insert kernel exists in two
+// cache variants (H = 0 or SBBF_HASH_LOAD_CACHED).
+template <uint32_t H>
+hipError_t run_insert(int kind, const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
+                      const Shape &s, hipStream_t stream) {
+  const dim3 g(s.grid), b(s.threads);
+  if (kind == SBBF_INSERT_ATOMIC32) {
+#define BODY(U)                                                                                       \
+  hipLaunchKernelGGL((insert_atomic32_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks);  \
+  return hipGetLastError();
+    SBBF_DISPATCH_U8(s.unroll, BODY)
+#undef BODY
+  }
+  if (kind == SBBF_INSERT_ATOMIC64) {
+#define BODY(U)                                                                                       \
+  hipLaunchKernelGGL((insert_atomic64_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks);  \
+  return hipGetLastError();
+    SBBF_DISPATCH_U8(s.unroll, BODY)
+#undef BODY
+  }
+  const size_t lds_bytes = (size_t)num_blocks * 32u;
+#define BODY(U)                                                                                              \
+  /* Raise the dynamic LDS limit; an error here shows up at launch. */                                       \
+  (void)hipFuncSetAttribute((const void *)insert_lds_kernel<U, H>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)lds_bytes);                                                                 \
+  (void)hipGetLastError();                                                                                   \
+  hipLaunchKernelGGL((insert_lds_kernel<U, H>), g, b, lds_bytes, stream, hashes, n, words, num_blocks);      \
+  return hipGetLastError();
+  SBBF_DISPATCH_U8(s.unroll, BODY)
+#undef BODY
+}
+
+hipError_t insert_any(int kind, const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
+                      const Shape &s, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  if (s.flags & SBBF_HASH_LOAD_CACHED)
+    return run_insert<SBBF_HASH_LOAD_CACHED>(kind, hashes, n, words, num_blocks, s, stream);
+  return run_insert<0>(kind, hashes, n, words, num_blocks, s, stream);
+}
 
 }  // namespace
 
 hipError_t launch_lookup(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
                          uint8_t *out8, uint32_t *out_bits, const Shape &s, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  if (s.unroll > 4) return hipErrorInvalidValue;  // eight chunks in flight exceed the register file
-  const dim3 g(s.grid), b(s.threads);
-#define CALL(U)                                                                                            \
-  if (out_bits)                                                                                            \
-    hipLaunchKernelGGL((lookup_kernel<U, true>), g, b, 0, stream, hashes, n, words, num_blocks, nullptr,   \
-                       out_bits);                                                                          \
-  else                                                                                                     \
-    hipLaunchKernelGGL((lookup_kernel<U, false>), g, b, 0, stream, hashes, n, words, num_blocks, out8,     \
-                       nullptr);
-  SBBF_DISPATCH_UNROLL4(s.unroll, CALL)
-#undef CALL
-  return hipGetLastError();
+  return dispatch_flags<LookupLauncher>(s.flags, hashes, n, words, num_blocks, out8, out_bits, s, stream);
 }
 
 hipError_t launch_insert_atomic32(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                                   const Shape &s, hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  const dim3 g(s.grid), b(s.threads);
-#define CALL(U) hipLaunchKernelGGL((insert_atomic32_kernel<U>), g, b, 0, stream, hashes, n, words, num_blocks);
-  SBBF_DISPATCH_UNROLL(s.unroll, CALL)
-#undef CALL
-  return hipGetLastError();
+  return insert_any(SBBF_INSERT_ATOMIC32, hashes, n, words, num_blocks, s, stream);
 }
 
 hipError_t launch_insert_atomic64(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                                   const Shape &s, hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  const dim3 g(s.grid), b(s.threads);
-#define CALL(U) hipLaunchKernelGGL((insert_atomic64_kernel<U>), g, b, 0, stream, hashes, n, words, num_blocks);
-  SBBF_DISPATCH_UNROLL(s.unroll, CALL)
-#undef CALL
-  return hipGetLastError();
+  return insert_any(SBBF_INSERT_ATOMIC64, hashes, n, words, num_blocks, s, stream);
 }
 
 hipError_t launch_insert_lds(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                              const Shape &s, hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  const dim3 g(s.grid), b(s.threads);
-  const size_t lds_bytes = (size_t)num_blocks * 32u;
-#define CALL(U)                                                                                      \
-  {                                                                                                  \
-    /* Raise the dynamic LDS limit; an error here shows up at launch. */                           \
-    (void)hipFuncSetAttribute((const void *)insert_lds_kernel<U>,                                     \
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);            \
-    (void)hipGetLastError();                                                                         \
-    hipLaunchKernelGGL((insert_lds_kernel<U>), g, b, lds_bytes, stream, hashes, n, words, num_blocks); \
-  }
-  SBBF_DISPATCH_UNROLL(s.unroll, CALL)
-#undef CALL
-  return hipGetLastError();
+  return insert_any(SBBF_INSERT_LDS, hashes, n, words, num_blocks, s, stream);
 }
 
 hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipStream_t stream) {
@@ -409,36 +475,35 @@ hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipS
 hipError_t launch_bench_gather(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n,
                                uint8_t *out, const Shape &s, hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  if (s.unroll > 4) return hipErrorInvalidValue;
-  const dim3 g(s.grid), b(s.threads);
-#define CALL(U) hipLaunchKernelGGL((bench_gather_kernel<U>), g, b, 0, stream, hashes, n, buf, num_blocks, out);
-  SBBF_DISPATCH_UNROLL4(s.unroll, CALL)
-#undef CALL
-  return hipGetLastError();
+  return dispatch_flags<GatherLauncher>(s.flags, buf, num_blocks, hashes, n, out, s, stream);
 }
 
 hipError_t launch_bench_atomic(uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n, bool wide,
                                const Shape &s, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const dim3 g(s.grid), b(s.threads);
-#define CALL(U)                                                                                        \
-  if (wide)                                                                                            \
-    hipLaunchKernelGGL((bench_atomic_kernel<U, true>), g, b, 0, stream, hashes, n, buf, num_blocks);   \
-  else                                                                                                 \
-    hipLaunchKernelGGL((bench_atomic_kernel<U, false>), g, b, 0, stream, hashes, n, buf, num_blocks);
-  SBBF_DISPATCH_UNROLL(s.unroll, CALL)
-#undef CALL
+#define BODY(U)                                                                                              \
+  if (wide)                                                                                                  \
+    hipLaunchKernelGGL((bench_atomic_kernel<U, true, 0>), g, b, 0, stream, hashes, n, buf, num_blocks);      \
+  else                                                                                                       \
+    hipLaunchKernelGGL((bench_atomic_kernel<U, false, 0>), g, b, 0, stream, hashes, n, buf, num_blocks);     \
   return hipGetLastError();
+  SBBF_DISPATCH_U8(s.unroll, BODY)
+#undef BODY
 }
 
 hipError_t launch_bench_stream(const uint64_t *hashes, uint64_t n, uint8_t *out, const Shape &s,
                                hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const dim3 g(s.grid), b(s.threads);
-#define CALL(U) hipLaunchKernelGGL((bench_stream_kernel<U>), g, b, 0, stream, hashes, n, out);
-  SBBF_DISPATCH_UNROLL(s.unroll, CALL)
-#undef CALL
+#define BODY(U)                                                                                              \
+  if (s.flags & SBBF_RESULT_STORE_NT)                                                                        \
+    hipLaunchKernelGGL((bench_stream_kernel<U, SBBF_RESULT_STORE_NT>), g, b, 0, stream, hashes, n, out);     \
+  else                                                                                                       \
+    hipLaunchKernelGGL((bench_stream_kernel<U, 0>), g, b, 0, stream, hashes, n, out);                        \
   return hipGetLastError();
+  SBBF_DISPATCH_U8(s.unroll, BODY)
+#undef BODY
 }
 
 }  // namespace sbbf

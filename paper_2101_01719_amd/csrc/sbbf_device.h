@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sbbf.h"
+
 namespace sbbf {
 
 constexpr int kWave = 64;
@@ -66,9 +68,41 @@ __device__ __forceinline__ uint32_t lane_read(uint32_t v, uint32_t src) {
 // Wave-wide ballot of a predicate.
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-// Streaming (non-temporal) load of one hash: the hash arrays are read once
-// and should not displace the filter from the caches.
-__device__ __forceinline__ uint64_t load_hash(const uint64_t *p) { return __builtin_nontemporal_load(p); }
+// Load of one hash. By default with the non-temporal hint: the hash arrays are
+// read once and should not displace the filter from the caches.
+template <uint32_t kFlags>
+__device__ __forceinline__ uint64_t load_hash(const uint64_t *p) {
+  if constexpr ((kFlags & SBBF_HASH_LOAD_CACHED) != 0) {
+    return *p;
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
+}
+
+// Load of one filter word for a lookup, with the cache policy of the flags.
+template <uint32_t kFlags>
+__device__ __forceinline__ uint32_t load_word(const uint32_t *p) {
+  constexpr uint32_t pol = kFlags & SBBF_FILTER_LOAD_MASK;
+  if constexpr (pol == SBBF_FILTER_LOAD_NT) {
+    return __builtin_nontemporal_load(p);
+  } else if constexpr (pol == SBBF_FILTER_LOAD_DEVICE) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else if constexpr (pol == SBBF_FILTER_LOAD_SYSTEM) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    return *p;
+  }
+}
+
+// Store of one result value, non-temporal when the flags ask for it.
+template <uint32_t kFlags, typename T>
+__device__ __forceinline__ void store_result(T *p, T v) {
+  if constexpr ((kFlags & SBBF_RESULT_STORE_NT) != 0) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    *p = v;
+  }
+}
 
 // From the eight ballots of one 64-key chunk (pass p holds, in byte g, the
 // eight word tests of the key of lane 8g + p), build the 64-bit result mask

@@ -24,6 +24,8 @@ STRATEGIES = {
     "atomic64": dict(strategy=2),
     "lds_owner": dict(strategy=3, grid_blocks=1),
     "lds_merge8": dict(strategy=3, grid_blocks=8),
+    "partitioned": dict(strategy=4),
+    "auto": dict(strategy=0),
 }
 
 
@@ -214,6 +216,26 @@ def test_empty_batches_and_errors(P):
     assert not words_of(f).any()
 
 
+@pytest.mark.parametrize("B", [1, 63, 4096, 4097, 8191, 12288 + 5, 1 << 20, (1 << 20) + 3])
+def test_partitioned_slice_edges(P, B):
+    """Filters of one slice, exactly one slice, one block over, several slices
+    with a short last slice, and many slices."""
+    h = splitmix64_stream(540 + B % 97, max(3 * B, 10_000) if B < (1 << 20) else 2_500_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h[: h.size // 3]), launch=dict(strategy=1))  # start from a non-empty filter
+    f.insert(dev(h[h.size // 3:]), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+
+
+def test_partitioned_refuses_too_many_slices(P):
+    f = P.Filter(8192 * 4096 + 1)  # one slice over the limit
+    with pytest.raises(P.SbbfError) as e:
+        f.insert(dev(splitmix64_stream(1, 1000)), launch=dict(strategy=4))
+    assert e.value.status == P.SBBF_EUNSUPPORTED
+    f.insert(dev(splitmix64_stream(1, 1000)))  # the library's choice still works
+
+
 def test_all_ones_filter_reports_every_probe(P):
     B = 321
     f = P.Filter(B)
@@ -251,7 +273,7 @@ def test_largest_block_count(P):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("strategy", ["atomic32", "atomic64"])
+@pytest.mark.parametrize("strategy", ["atomic32", "atomic64", "partitioned"])
 def test_plain_100m_full(P, strategy):
     """The 100M-key workload at full size in the launch shape the benchmark
     times (library defaults): the whole filter and all 2e8 lookups are
