@@ -149,18 +149,23 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_100m", choices=["plain_100k", "plain_1m", "plain_100m"])
-    ap.add_argument("--insert-strategy", type=int, default=0, help="0 = library choice, 1 atomic32, 2 atomic64, 3 LDS")
+    ap.add_argument("--insert-strategy", type=int, default=0,
+                    help="0 = library choice, 1 atomic32, 2 atomic64, 3 LDS, 4 partitioned")
+    ap.add_argument("--lookup-strategy", type=int, default=0, help="0 = library choice, 1 gather, 2 partitioned")
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the steps, copy this many MiB once with a plain device copy (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the split block Bloom filter path here has no multi-GPU "
-              "form (filters shard by whole filters or by block range; see the design notes). "
-              "Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only. Independent filters would shard across GPUs as whole "
+              "filters, and one large filter by block range with an all-to-all exchange of hashes; "
+              "neither is built here. Run with --gpus 1.", file=sys.stderr)
         return 2
 
     _ensure_built()
@@ -177,8 +182,13 @@ def main(argv=None):
     n_ins, n_look = w.inserts.numel(), w.lookups.numel()
 
     ins_launch = dict(block_threads=a.threads, unroll=a.unroll, grid_blocks=a.grid, strategy=a.insert_strategy)
-    look_launch = dict(block_threads=a.threads, unroll=min(a.unroll, 4), grid_blocks=a.grid)
+    look_launch = dict(block_threads=a.threads, unroll=min(a.unroll, 4), grid_blocks=a.grid,
+                       strategy=a.lookup_strategy)
     f = P.Filter(w.num_blocks)
+    names_ins = {1: "atomic32", 2: "atomic64", 3: "lds", 4: "partitioned"}
+    names_look = {1: "gather", 2: "partitioned"}
+    ins_used = names_ins[a.insert_strategy or P.sbbf_auto_insert_strategy(f.handle, n_ins)]
+    look_used = names_look[a.lookup_strategy or P.sbbf_auto_lookup_strategy(f.handle, n_look)]
     out = torch.empty(n_look, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -193,6 +203,13 @@ def main(argv=None):
         if ev:
             ev[2].record(stream)
 
+    if a.calibrate_copy_mib:
+        src = torch.ones(a.calibrate_copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -221,8 +238,10 @@ def main(argv=None):
                        traffic=_traffic("lookup", a.workload), avg_ms=lookup_ms,
                        bytes_per_key=LOOKUP_BYTES_PER_KEY, keys_per_launch=n_look),
     }
+    kernels["insert"]["kernel"] = f"insert ({ins_used})"
+    kernels["lookup"]["kernel"] = f"lookup ({look_used})"
     dominant = "insert" if insert_ms >= lookup_ms else "lookup"
-    roofline = dict(kernels[dominant], kernel=dominant)
+    roofline = kernels[dominant]
 
     result = {
         "metric": METRIC,
@@ -246,12 +265,13 @@ def main(argv=None):
             "lookups": n_look,
             "insert_launch": ins_launch,
             "lookup_launch": look_launch,
+            "insert_strategy": ins_used,
+            "lookup_strategy": look_used,
         },
         "insert_gkeys_per_s": n_ins / (insert_ms / 1e3) / 1e9,
         "lookup_gkeys_per_s": n_look / (lookup_ms / 1e3) / 1e9,
         "roofline": roofline,
-        "roofline_other": dict(kernels["lookup" if dominant == "insert" else "insert"],
-                               kernel="lookup" if dominant == "insert" else "insert"),
+        "roofline_other": kernels["lookup" if dominant == "insert" else "insert"],
         "false_positive_rate": fp / max(1, n_non),
         "members_all_found": members_ok,
         "input_generation_s": t_gen,

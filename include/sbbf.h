@@ -73,8 +73,20 @@ typedef enum sbbf_insert_strategy {
   SBBF_INSERT_PARTITIONED = 4 /* keys split by filter slice (a slice fits one workgroup's
                                LDS), then one workgroup ORs each slice in LDS and stores
                                it back; no global atomics on the filter. Uses a
-                               stream-ordered device workspace of about 8 bytes per key */
+                               stream-ordered device workspace of about 8 bytes per key
+                               (batches above 2^31 keys are processed 2^31 at a time) */
 } sbbf_insert_strategy;
+
+/* Lookup strategies (the `strategy` field of sbbf_launch for lookups). All
+ * give identical results. */
+typedef enum sbbf_lookup_strategy {
+  SBBF_LOOKUP_AUTO = 0,        /* library choice by filter size and key count */
+  SBBF_LOOKUP_GATHER = 1,      /* one 32-byte block read per key, 8 lanes per key */
+  SBBF_LOOKUP_PARTITIONED = 2  /* keys split by filter slice, each slice tested from one
+                                  workgroup's LDS, results returned to input order; uses a
+                                  stream-ordered device workspace of about 13 bytes per key
+                                  (batches above 2^31 keys are processed 2^31 at a time) */
+} sbbf_lookup_strategy;
 
 /* Memory-access flags of sbbf_launch (cache policy only; results are
  * identical for every value). */
@@ -94,7 +106,7 @@ typedef struct sbbf_launch {
   uint32_t block_threads; /* workgroup size: 64 .. 1024, a multiple of 64 */
   uint32_t grid_blocks;   /* workgroups; for SBBF_INSERT_LDS the number of private copies */
   uint32_t unroll;        /* 64-key chunks each wave keeps in flight: 1, 2, 4 or 8 (lookup: at most 4) */
-  uint32_t strategy;      /* inserts only: an sbbf_insert_strategy */
+  uint32_t strategy;      /* an sbbf_insert_strategy (inserts) or sbbf_lookup_strategy (lookups) */
   uint32_t flags;         /* SBBF_* memory-access flags above; 0 = library default */
 } sbbf_launch;
 
@@ -148,6 +160,11 @@ void *sbbf_device_words(const sbbf_filter *f);
  * with pinned memory the caller synchronises before touching host_dst. */
 sbbf_status sbbf_copy_words_to_host(const sbbf_filter *f, void *host_dst, sbbf_stream s);
 sbbf_status sbbf_copy_words_from_host(sbbf_filter *f, const void *host_src, sbbf_stream s);
+
+/* The strategy SBBF_INSERT_AUTO / SBBF_LOOKUP_AUTO picks for a batch of n
+ * hashes on this filter and the current device (0 on a bad argument). */
+uint32_t sbbf_auto_insert_strategy(const sbbf_filter *f, size_t n);
+uint32_t sbbf_auto_lookup_strategy(const sbbf_filter *f, size_t n);
 
 /* Insert n hashes (appendix figure, insert routine; applied to every hash). */
 sbbf_status sbbf_insert_batch(sbbf_filter *f, const uint64_t *d_hashes, size_t n, sbbf_stream s);

@@ -34,6 +34,11 @@ SBBF_INSERT_AUTO = 0
 SBBF_INSERT_ATOMIC32 = 1
 SBBF_INSERT_ATOMIC64 = 2
 SBBF_INSERT_LDS = 3
+SBBF_INSERT_PARTITIONED = 4
+
+SBBF_LOOKUP_AUTO = 0
+SBBF_LOOKUP_GATHER = 1
+SBBF_LOOKUP_PARTITIONED = 2
 
 
 
@@ -149,6 +154,14 @@ def sbbf_copy_words_from_host(f: int, host: torch.Tensor, stream=None) -> None:
     if host.is_cuda or not host.is_contiguous() or host.numel() * host.element_size() != 32 * sbbf_num_blocks(f):
         raise ValueError("host buffer must be a contiguous CPU tensor of 32 * num_blocks bytes")
     _check(_L().sbbf_copy_words_from_host(f, ctypes.c_void_p(host.data_ptr()), _stream(stream)))
+
+
+def sbbf_auto_insert_strategy(f: int, n: int) -> int:
+    return int(_L().sbbf_auto_insert_strategy(f, n))
+
+
+def sbbf_auto_lookup_strategy(f: int, n: int) -> int:
+    return int(_L().sbbf_auto_lookup_strategy(f, n))
 
 
 def sbbf_insert_batch(f: int, hashes: torch.Tensor, stream=None) -> None:

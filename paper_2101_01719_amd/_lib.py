@@ -59,6 +59,8 @@ SIGNATURES = {
     "sbbf_device_words": (c_vp, [c_vp]),
     "sbbf_copy_words_to_host": (c_int, [c_vp, c_vp, c_vp]),
     "sbbf_copy_words_from_host": (c_int, [c_vp, c_vp, c_vp]),
+    "sbbf_auto_insert_strategy": (c_u32, [c_vp, c_size]),
+    "sbbf_auto_lookup_strategy": (c_u32, [c_vp, c_size]),
     "sbbf_insert_batch": (c_int, [c_vp, c_vp, c_size, c_vp]),
     "sbbf_insert_batch_ex": (c_int, [c_vp, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_lookup_batch": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp]),

@@ -251,30 +251,47 @@ static sbbf_status check_batch(const sbbf_filter *f, const void *d_hashes, size_
   return SBBF_OK;
 }
 
-// Slice size of the partitioned insert: the largest power of two of blocks,
-// at most 4096 (128 KiB), whose words fit one workgroup's LDS.
-static uint32_t partition_slice_shift(const sbbf_device_info &info) {
-  uint32_t shift = 12;
-  while (shift > 6 && ((uint64_t)32u << shift) > info.lds_per_block) --shift;
+// Slice size of the partitioned kernels: about four slices per compute unit
+// so the slice phase fills the device, at least 64 blocks (2 KiB) and at most
+// the largest power of two of blocks (up to 4096, 128 KiB) whose words fit one
+// workgroup's LDS.
+static uint32_t partition_slice_shift(const sbbf_device_info &info, uint32_t num_blocks) {
+  uint32_t max_shift = 12;
+  while (max_shift > 6 && ((uint64_t)32u << max_shift) > info.lds_per_block) --max_shift;
+  const uint64_t target = (uint64_t)num_blocks / (4u * (uint64_t)info.compute_units);
+  uint32_t shift = 6;
+  while (shift < max_shift && ((uint64_t)1u << (shift + 1)) <= target) ++shift;
   return shift;
 }
-
-// Largest slice count the partitioned kernels accept (their LDS bins).
-static constexpr uint32_t kMaxPartitionSlices = 8192;
 
 static uint32_t partition_slices(uint32_t num_blocks, uint32_t shift) {
   return (uint32_t)(((uint64_t)num_blocks + (1u << shift) - 1u) >> shift);
 }
 
+static bool partition_fits(const sbbf_device_info &info, uint32_t num_blocks) {
+  return partition_slices(num_blocks, partition_slice_shift(info, num_blocks)) <= partition_max_slices();
+}
+
 // Library choice of insert strategy (SBBF_INSERT_AUTO): the partitioned insert
 // when the batch has at least two keys per block (so the one-time read and
-// write of the whole filter costs less than per-key atomics) and the filter
-// has few enough slices; otherwise global 32-bit atomics.
+// write of the whole filter costs less than per-key atomics, which the device
+// caps at about 27 G keys/s whatever the filter size) and the filter splits
+// into few enough slices; otherwise global 32-bit atomics.
 static uint32_t auto_insert_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
-  const uint32_t shift = partition_slice_shift(info);
-  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && partition_slices(f->num_blocks, shift) <= kMaxPartitionSlices)
+  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && partition_fits(info, f->num_blocks))
     return SBBF_INSERT_PARTITIONED;
   return SBBF_INSERT_ATOMIC32;
+}
+
+// Library choice of lookup strategy (SBBF_LOOKUP_AUTO): random 32-byte reads
+// run at L2 speed while the filter fits the per-XCD L2 and fall to the
+// miss-handling rate beyond it, so the partitioned lookup (streaming traffic
+// only) is used for filters above 16 MiB with at least four keys per block.
+static uint32_t auto_lookup_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
+  if ((uint64_t)f->num_blocks * 32u > (16ull << 20) && (uint64_t)n >= 4u * (uint64_t)f->num_blocks &&
+      partition_fits(info, f->num_blocks))
+    return SBBF_LOOKUP_PARTITIONED;
+  return SBBF_LOOKUP_GATHER;
 }
 
 // Stream-ordered workspace: allocated from the device's default memory pool
@@ -318,17 +335,21 @@ sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_
       if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
       return hip_error(launch_insert_atomic64(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     case SBBF_INSERT_PARTITIONED: {
-      const uint32_t shift = partition_slice_shift(*info);
+      const uint32_t shift = partition_slice_shift(*info, f->num_blocks);
       const uint32_t slices = partition_slices(f->num_blocks, shift);
-      if (slices > kMaxPartitionSlices)
-        return set_error(SBBF_EUNSUPPORTED, "filter has more than " + std::to_string(kMaxPartitionSlices) +
+      if (slices > partition_max_slices())
+        return set_error(SBBF_EUNSUPPORTED, "filter has more than " + std::to_string(partition_max_slices()) +
                                                 " slices of " + std::to_string(1u << shift) + " blocks");
-      const uint32_t grid = cfg && cfg->grid_blocks ? cfg->grid_blocks : (uint32_t)info->compute_units * 2u;
+      const uint32_t groups = cfg && cfg->grid_blocks ? cfg->grid_blocks : (uint32_t)info->compute_units * 2u;
+      const uint64_t step = partition_max_keys();
       void *ws = nullptr;
-      const size_t bytes = partition_workspace_bytes(n, slices);
-      hipError_t e = workspace_alloc(&ws, bytes, stream, info->device);
+      hipError_t e = workspace_alloc(&ws, partition_workspace_bytes(n < step ? n : step, slices, groups, false),
+                                     stream, info->device);
       if (e != hipSuccess) return hip_error(e, "hipMallocAsync(partition workspace)");
-      e = launch_insert_partitioned(d_hashes, n, f->words, f->num_blocks, shift, ws, grid, stream);
+      for (uint64_t at = 0; at < n && e == hipSuccess; at += step) {
+        const uint64_t m = n - at < step ? n - at : step;
+        e = launch_insert_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups, stream);
+      }
       hipError_t e2 = hipFreeAsync(ws, stream);
       if (e != hipSuccess) return hip_error(e, "partitioned insert");
       return hip_error(e2, "hipFreeAsync(partition workspace)");
@@ -348,6 +369,18 @@ sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_
   }
 }
 
+uint32_t sbbf_auto_insert_strategy(const sbbf_filter *f, size_t n) {
+  sbbf_status st;
+  const sbbf_device_info *info = f ? current_device_info(&st) : nullptr;
+  return info ? auto_insert_strategy(f, n, *info) : 0u;
+}
+
+uint32_t sbbf_auto_lookup_strategy(const sbbf_filter *f, size_t n) {
+  sbbf_status st;
+  const sbbf_device_info *info = f ? current_device_info(&st) : nullptr;
+  return info ? auto_lookup_strategy(f, n, *info) : 0u;
+}
+
 sbbf_status sbbf_insert_batch(sbbf_filter *f, const uint64_t *d_hashes, size_t n, sbbf_stream s) {
   return sbbf_insert_batch_ex(f, d_hashes, n, nullptr, s);
 }
@@ -359,10 +392,36 @@ sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes,
   sbbf_status st = d_bits ? check_batch(f, d_hashes, n, d_bits, "d_bits", 4)
                           : check_batch(f, d_hashes, n, d_out, "d_out", 1);
   if (st != SBBF_OK || n == 0) return st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  hipStream_t stream = (hipStream_t)s;
+  uint32_t strategy = cfg ? cfg->strategy : SBBF_LOOKUP_AUTO;
+  if (strategy == SBBF_LOOKUP_AUTO) strategy = auto_lookup_strategy(f, n, *info);
+  if (strategy == SBBF_LOOKUP_PARTITIONED) {
+    const uint32_t shift = partition_slice_shift(*info, f->num_blocks);
+    const uint32_t slices = partition_slices(f->num_blocks, shift);
+    if (slices > partition_max_slices())
+      return set_error(SBBF_EUNSUPPORTED, "filter has more than " + std::to_string(partition_max_slices()) +
+                                              " slices of " + std::to_string(1u << shift) + " blocks");
+    const uint32_t groups = cfg && cfg->grid_blocks ? cfg->grid_blocks : (uint32_t)info->compute_units * 2u;
+    const uint64_t step = partition_max_keys();  // a multiple of 32: packed outputs split on word boundaries
+    void *ws = nullptr;
+    hipError_t e = workspace_alloc(&ws, partition_workspace_bytes(n < step ? n : step, slices, groups, true), stream,
+                                   info->device);
+    if (e != hipSuccess) return hip_error(e, "hipMallocAsync(partition workspace)");
+    for (uint64_t at = 0; at < n && e == hipSuccess; at += step) {
+      const uint64_t m = n - at < step ? n - at : step;
+      e = launch_lookup_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups,
+                                    d_out ? d_out + at : nullptr, d_bits ? d_bits + at / 32 : nullptr, stream);
+    }
+    hipError_t e2 = hipFreeAsync(ws, stream);
+    if (e != hipSuccess) return hip_error(e, "partitioned lookup");
+    return hip_error(e2, "hipFreeAsync(partition workspace)");
+  }
+  if (strategy != SBBF_LOOKUP_GATHER) return set_error(SBBF_EINVAL, "unknown lookup strategy");
   Shape shape;
   if ((st = resolve_shape(cfg, n, 2, &shape, 4)) != SBBF_OK) return st;
-  return hip_error(launch_lookup(d_hashes, n, f->words, f->num_blocks, d_out, d_bits, shape, (hipStream_t)s),
-                   "lookup");
+  return hip_error(launch_lookup(d_hashes, n, f->words, f->num_blocks, d_out, d_bits, shape, stream), "lookup");
 }
 
 sbbf_status sbbf_lookup_batch(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,

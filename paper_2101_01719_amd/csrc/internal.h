@@ -52,12 +52,19 @@ hipError_t launch_insert_lds(const uint64_t *hashes, uint64_t n, uint32_t *words
                              const Shape &shape, hipStream_t stream);
 hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipStream_t stream);
 
-// Partitioned insert (partition_kernels.hip). Slices hold 2^slice_shift
-// blocks; `workspace` holds partition_workspace_bytes(n, slices) bytes; `grid`
-// sizes the count and scatter kernels.
-uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices);
+// Partitioned insert and lookup (partition_kernels.hip). Slices hold
+// 2^slice_shift blocks (at most partition_max_slices() slices); one launch
+// takes at most partition_max_keys() keys; the batch is cut into at most
+// `max_groups` chunks (one partitioning workgroup each); `workspace` holds
+// partition_workspace_bytes(n, slices, max_groups, lookup) bytes.
+uint32_t partition_max_slices();
+uint64_t partition_max_keys();
+uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup);
 hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
-                                     uint32_t slice_shift, void *workspace, uint32_t grid, hipStream_t stream);
+                                     uint32_t slice_shift, void *workspace, uint32_t max_groups, hipStream_t stream);
+hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
+                                     uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
+                                     uint32_t *out_bits, hipStream_t stream);
 
 hipError_t launch_bench_gather(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n,
                                uint8_t *out, const Shape &shape, hipStream_t stream);

@@ -28,6 +28,12 @@ STRATEGIES = {
     "auto": dict(strategy=0),
 }
 
+LOOKUPS = {
+    "gather": dict(strategy=1),
+    "partitioned": dict(strategy=2),
+    "auto": dict(strategy=0),
+}
+
 
 @pytest.fixture(scope="module")
 def P():
@@ -93,6 +99,10 @@ def test_ragged_counts(P, n):
             assert np.array_equal(got, ref_look), (name, unroll)
             bits = f.lookup_bits(dev(probes), launch=dict(unroll=unroll)).cpu().numpy().view(np.uint32)
             assert np.array_equal(bits, ref_bits), (name, unroll)
+        got = f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy()
+        assert np.array_equal(got, ref_look), (name, "partitioned lookup")
+        bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+        assert np.array_equal(bits, ref_bits), (name, "partitioned lookup bits")
         f.close()
 
 
@@ -141,6 +151,9 @@ def test_plain_workloads(P, name, strategy):
     look = dev(w.lookups)
     got = f.lookup(look).cpu().numpy()
     bits = f.lookup_bits(look).cpu().numpy().view(np.uint32)
+    for lname, llaunch in LOOKUPS.items():
+        assert np.array_equal(f.lookup(look, launch=llaunch).cpu().numpy(), got), lname
+        assert np.array_equal(f.lookup_bits(look, launch=llaunch).cpu().numpy().view(np.uint32), bits), lname
     words = words_of(f)
     ref = oracle.build_filter(w.num_blocks, w.inserts)
     assert np.array_equal(words, ref)
@@ -226,14 +239,25 @@ def test_partitioned_slice_edges(P, B):
     f.insert(dev(h[: h.size // 3]), launch=dict(strategy=1))  # start from a non-empty filter
     f.insert(dev(h[h.size // 3:]), launch=dict(strategy=4))
     assert np.array_equal(words_of(f), ref)
+    probes = np.concatenate([h[::7], splitmix64_stream(600 + B % 89, 3 * B + 1001)])
+    want = oracle.lookup(ref, B, probes)
+    got = f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy()
+    assert np.array_equal(got, want)
+    bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
 
 
 def test_partitioned_refuses_too_many_slices(P):
-    f = P.Filter(8192 * 4096 + 1)  # one slice over the limit
+    f = P.Filter(4096 * 4096 + 1)  # one slice over the limit of 4096 slices of 4096 blocks
+    h = dev(splitmix64_stream(1, 1000))
     with pytest.raises(P.SbbfError) as e:
-        f.insert(dev(splitmix64_stream(1, 1000)), launch=dict(strategy=4))
+        f.insert(h, launch=dict(strategy=4))
     assert e.value.status == P.SBBF_EUNSUPPORTED
-    f.insert(dev(splitmix64_stream(1, 1000)))  # the library's choice still works
+    with pytest.raises(P.SbbfError) as e:
+        f.lookup(h, launch=dict(strategy=2))
+    assert e.value.status == P.SBBF_EUNSUPPORTED
+    f.insert(h)  # the library's choices still work
+    assert bool(f.lookup(h).all())
 
 
 def test_all_ones_filter_reports_every_probe(P):
@@ -281,7 +305,7 @@ def test_plain_100m_full(P, strategy):
     w = plain_workload("plain_100m", backend="torch", device="cuda")
     f = P.Filter(w.num_blocks)
     f.insert(w.inserts, launch=STRATEGIES[strategy])
-    got = f.lookup(w.lookups)
+    got = {name: f.lookup(w.lookups, launch=launch).cpu().numpy() for name, launch in LOOKUPS.items()}
     torch.cuda.synchronize()
     words = words_of(f)
     assert sha16(words) == _paper_row("plain_100m")[6]
@@ -290,4 +314,5 @@ def test_plain_100m_full(P, strategy):
     assert np.array_equal(words, ref)
     look = w.lookups.cpu().numpy().view(np.uint64)
     ref_look = oracle.lookup(ref, w.num_blocks, look)
-    assert np.array_equal(got.cpu().numpy(), ref_look)
+    for name, g in got.items():
+        assert np.array_equal(g, ref_look), name
