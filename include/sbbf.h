@@ -200,6 +200,60 @@ sbbf_status sbbf_bench_atomic(uint32_t *d_buf, uint32_t num_blocks, const uint64
 sbbf_status sbbf_bench_stream(const uint64_t *d_hashes, size_t n, uint8_t *d_out, const sbbf_launch *cfg,
                               sbbf_stream s);
 
+/* ---- grouped: many filters in one launch ----------------------------------- */
+/* A group holds F filters. A plan fixes, for one batch shape, how many keys each
+ * filter inserts and looks up (CSR offsets: filter f inserts d_ins[ins_off[f] ..
+ * ins_off[f+1]) and looks up d_look[look_off[f] .. look_off[f+1]), writing
+ * d_out[look_off[f] ..]). A run performs every filter's inserts, then every
+ * filter's lookups, as one HIP graph launch (three kernel nodes); results are
+ * identical to one plain insert and one plain lookup per filter. */
+
+typedef struct sbbf_grouped_config {
+  uint32_t lookup_tile_keys;     /* keys per lookup tile, a multiple of 64 */
+  uint32_t lookup_threads;       /* lookup workgroup size: 64, 128, 192 or 256 */
+  uint32_t lookup_unroll;        /* 64-key chunks in flight per wave: 1, 2 or 4 */
+  uint32_t lookup_blocks_per_cu; /* persistent lookup workgroups per compute unit */
+  uint32_t insert_slice_shift;   /* log2 blocks per insert slice (a slice fits one workgroup's LDS) */
+  uint32_t xcd_queues;           /* 1: lookup tiles of a filter stay on one XCD queue; 0: one queue */
+  uint64_t insert_lds_bytes;     /* filters up to this size are inserted whole by one workgroup */
+} sbbf_grouped_config;
+
+/* Defaults for the current device. */
+sbbf_status sbbf_grouped_default_config(sbbf_grouped_config *out);
+/* A group over filters[0 .. num_filters) (handles are borrowed; they must outlive
+ * the group). */
+sbbf_status sbbf_grouped_create(sbbf_filter *const *filters, uint32_t num_filters, sbbf_group **out);
+sbbf_status sbbf_grouped_destroy(sbbf_group *g);
+/* Build the plan from host offsets (num_filters + 1 entries each, non-decreasing;
+ * at most 2^32 - 1 insert keys per filter). cfg NULL = defaults. Synchronous. */
+sbbf_status sbbf_grouped_plan(sbbf_group *g, const uint64_t *h_ins_offsets, const uint64_t *h_look_offsets,
+                              const sbbf_grouped_config *cfg);
+/* The configuration of the current plan. */
+sbbf_status sbbf_grouped_get_config(const sbbf_group *g, sbbf_grouped_config *out);
+/* Inserts, then lookups, of the planned batch as one graph launch on the stream. */
+sbbf_status sbbf_grouped_run(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                             sbbf_stream s);
+/* The two phases as separate kernel launches (no graph). */
+sbbf_status sbbf_grouped_insert(sbbf_group *g, const uint64_t *d_ins, sbbf_stream s);
+sbbf_status sbbf_grouped_lookup(sbbf_group *g, const uint64_t *d_look, uint8_t *d_out, sbbf_stream s);
+/* Baseline with the same results: one plain launch per filter per operation
+ * (32-bit atomic insert, gather lookup). */
+sbbf_status sbbf_grouped_run_per_filter(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look,
+                                        uint8_t *d_out, sbbf_stream s);
+/* 64-bit digest of every filter's words (in group order) and of d_out over the
+ * planned lookups (d_out may be NULL). Synchronises the stream. */
+sbbf_status sbbf_grouped_digest(sbbf_group *g, const uint8_t *d_out, sbbf_stream s, uint64_t *digest);
+/* Search launch configurations for the planned batch, timing `reps` graph
+ * launches per candidate. Synchronous: waits for the device first, so the
+ * inputs may come from any stream. The filters are restored to their contents before
+ * every candidate and after the search, so the search leaves them unchanged.
+ * Every candidate must produce the same digest as the first, else
+ * SBBF_EDEVICE. The best configuration is planned and returned in *best.
+ * With cache_path, a stored result for this device and batch shape is used
+ * instead of searching (unless force != 0), and a new result is appended. */
+sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                                  uint32_t reps, const char *cache_path, int force, sbbf_grouped_config *best);
+
 #ifdef __cplusplus
 } /* extern "C" */
 #endif

@@ -20,7 +20,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import sbbf_device_info, sbbf_launch
+from ._lib import sbbf_device_info, sbbf_grouped_config, sbbf_launch
 
 SBBF_OK = 0
 SBBF_EINVAL = 1
@@ -243,6 +243,93 @@ def sbbf_bench_stream(hashes: torch.Tensor, out: torch.Tensor, launch=None, stre
     _check(_L().sbbf_bench_stream(p, n, ctypes.c_void_p(out.data_ptr()), _launch(launch), _stream(stream)))
 
 
+# ---- grouped ---------------------------------------------------------------------------------
+
+def _cfg_struct(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, sbbf_grouped_config):
+        return ctypes.byref(cfg)
+    base = sbbf_grouped_default_config()
+    for k, v in dict(cfg).items():
+        setattr(base, k, v)
+    return ctypes.byref(base)
+
+
+def _cfg_dict(c: sbbf_grouped_config) -> dict:
+    return {name: getattr(c, name) for name, _ in sbbf_grouped_config._fields_}
+
+
+def _offsets(off):
+    import numpy as np
+
+    a = np.ascontiguousarray(np.asarray(off, dtype=np.uint64))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def sbbf_grouped_default_config() -> sbbf_grouped_config:
+    c = sbbf_grouped_config()
+    _check(_L().sbbf_grouped_default_config(ctypes.byref(c)))
+    return c
+
+
+def sbbf_grouped_create(filter_handles) -> int:
+    arr = (ctypes.c_void_p * len(filter_handles))(*filter_handles)
+    g = ctypes.c_void_p()
+    _check(_L().sbbf_grouped_create(arr, len(filter_handles), ctypes.byref(g)))
+    return g.value
+
+
+def sbbf_grouped_destroy(g: int) -> None:
+    _check(_L().sbbf_grouped_destroy(g))
+
+
+def sbbf_grouped_plan(g: int, ins_offsets, look_offsets, cfg=None) -> None:
+    io, iop = _offsets(ins_offsets)
+    lo, lop = _offsets(look_offsets)
+    _check(_L().sbbf_grouped_plan(g, iop, lop, _cfg_struct(cfg)))
+
+
+def sbbf_grouped_get_config(g: int) -> dict:
+    c = sbbf_grouped_config()
+    _check(_L().sbbf_grouped_get_config(g, ctypes.byref(c)))
+    return _cfg_dict(c)
+
+
+def sbbf_grouped_run(g: int, d_ins, d_look, d_out, stream=None) -> None:
+    _check(_L().sbbf_grouped_run(g, _dptr(d_ins), _dptr(d_look), _dptr(d_out), _stream(stream)))
+
+
+def sbbf_grouped_insert(g: int, d_ins, stream=None) -> None:
+    _check(_L().sbbf_grouped_insert(g, _dptr(d_ins), _stream(stream)))
+
+
+def sbbf_grouped_lookup(g: int, d_look, d_out, stream=None) -> None:
+    _check(_L().sbbf_grouped_lookup(g, _dptr(d_look), _dptr(d_out), _stream(stream)))
+
+
+def sbbf_grouped_run_per_filter(g: int, d_ins, d_look, d_out, stream=None) -> None:
+    _check(_L().sbbf_grouped_run_per_filter(g, _dptr(d_ins), _dptr(d_look), _dptr(d_out), _stream(stream)))
+
+
+def sbbf_grouped_digest(g: int, d_out=None, stream=None) -> int:
+    v = ctypes.c_uint64()
+    _check(_L().sbbf_grouped_digest(g, _dptr(d_out), _stream(stream), ctypes.byref(v)))
+    return v.value
+
+
+def sbbf_grouped_autotune(g: int, d_ins, d_look, d_out, reps: int = 5, cache_path=None, force: bool = False) -> dict:
+    c = sbbf_grouped_config()
+    path = cache_path.encode() if cache_path else None
+    _check(_L().sbbf_grouped_autotune(g, _dptr(d_ins), _dptr(d_look), _dptr(d_out), reps, path, int(force),
+                                      ctypes.byref(c)))
+    return _cfg_dict(c)
+
+
 # ---- convenience --------------------------------------------------------------------------
 
 class Filter:
@@ -287,3 +374,48 @@ class Filter:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Group:
+    """Many filters driven as one group (see sbbf_grouped_*). The filters are
+    Filter objects (torch-backed words); offsets are host CSR arrays."""
+
+    def __init__(self, filters, ins_offsets, look_offsets, cfg=None):
+        self.filters = list(filters)
+        self.handle = sbbf_grouped_create([f.handle for f in self.filters])
+        self.ins_offsets = ins_offsets
+        self.look_offsets = look_offsets
+        sbbf_grouped_plan(self.handle, ins_offsets, look_offsets, cfg)
+
+    def replan(self, cfg=None):
+        sbbf_grouped_plan(self.handle, self.ins_offsets, self.look_offsets, cfg)
+
+    def config(self) -> dict:
+        return sbbf_grouped_get_config(self.handle)
+
+    def run(self, d_ins, d_look, d_out, stream=None):
+        sbbf_grouped_run(self.handle, d_ins, d_look, d_out, stream)
+
+    def run_per_filter(self, d_ins, d_look, d_out, stream=None):
+        sbbf_grouped_run_per_filter(self.handle, d_ins, d_look, d_out, stream)
+
+    def digest(self, d_out=None, stream=None) -> int:
+        return sbbf_grouped_digest(self.handle, d_out, stream)
+
+    def autotune(self, d_ins, d_look, d_out, reps=5, cache_path=None, force=False) -> dict:
+        return sbbf_grouped_autotune(self.handle, d_ins, d_look, d_out, reps, cache_path, force)
+
+    def clear(self, stream=None):
+        for f in self.filters:
+            f.clear(stream)
+
+    def close(self):
+        if self.handle:
+            sbbf_grouped_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -45,6 +45,20 @@ class sbbf_device_info(ctypes.Structure):
     ]
 
 
+class sbbf_grouped_config(ctypes.Structure):
+    _fields_ = [
+        ("lookup_tile_keys", c_u32),
+        ("lookup_threads", c_u32),
+        ("lookup_unroll", c_u32),
+        ("lookup_blocks_per_cu", c_u32),
+        ("insert_slice_shift", c_u32),
+        ("xcd_queues", c_u32),
+        ("insert_lds_bytes", c_u64),
+    ]
+
+
+_CFGP = ctypes.POINTER(sbbf_grouped_config)
+
 # name -> (restype, argtypes); every symbol declared in include/sbbf.h.
 SIGNATURES = {
     "sbbf_status_string": (ctypes.c_char_p, [c_int]),
@@ -69,6 +83,17 @@ SIGNATURES = {
     "sbbf_bench_gather": (c_int, [c_vp, c_u32, c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_bench_atomic": (c_int, [c_vp, c_u32, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_bench_stream": (c_int, [c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_grouped_default_config": (c_int, [_CFGP]),
+    "sbbf_grouped_create": (c_int, [ctypes.POINTER(c_vp), c_u32, ctypes.POINTER(c_vp)]),
+    "sbbf_grouped_destroy": (c_int, [c_vp]),
+    "sbbf_grouped_plan": (c_int, [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64), _CFGP]),
+    "sbbf_grouped_get_config": (c_int, [c_vp, _CFGP]),
+    "sbbf_grouped_run": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "sbbf_grouped_insert": (c_int, [c_vp, c_vp, c_vp]),
+    "sbbf_grouped_lookup": (c_int, [c_vp, c_vp, c_vp, c_vp]),
+    "sbbf_grouped_run_per_filter": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "sbbf_grouped_digest": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(c_u64)]),
+    "sbbf_grouped_autotune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_u32, ctypes.c_char_p, c_int, _CFGP]),
 }
 
 _lib = None

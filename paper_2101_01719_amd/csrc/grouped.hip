@@ -1,0 +1,908 @@
+// Grouped launches: inserts into and lookups in many filters of uneven sizes
+// in one launch (a HIP graph of three kernels), instead of one launch per
+// filter per operation.
+//
+// Every filter runs the same method as the single-filter path; the group only
+// changes how work is spread over the device:
+//
+//   insert  one persistent kernel over (filter, slice) tiles. A filter whose
+//           words fit the LDS threshold is one tile; a larger filter is cut
+//           into slices of 2^slice_shift blocks, one tile each. The workgroup
+//           of a tile loads its slice into LDS, streams all of the filter's
+//           insert keys, ORs the masks of the keys that fall in the slice, and
+//           stores the slice back with plain stores. Tiles are ordered by cost
+//           (keys streamed), largest first, and taken from one atomic queue.
+//   lookup  one persistent kernel over (filter, key range) tiles with the
+//           8-lane gather of the single-filter lookup. Tiles sit in eight
+//           queues, one per XCD (workgroups are dispatched to the XCDs round
+//           robin, so workgroup w starts on queue w % 8); all tiles of a filter
+//           go to one queue so its blocks stay in that XCD's L2. A workgroup
+//           whose queue is empty takes tiles from the other queues.
+//
+// The plan (tiles, queues, filter table) lives in device memory and is built
+// on the host from the per-filter key counts.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "sbbf_device.h"
+
+namespace sbbf {
+namespace {
+
+constexpr int kQueues = 8;  // XCDs of the device (lookup queues)
+constexpr uint32_t kInsertThreads = 1024;
+
+struct GFilter {
+  uint32_t *words;
+  uint32_t num_blocks;
+  uint32_t pad;
+};
+
+struct GInsTile {
+  uint32_t filter;
+  uint32_t b0;  // first block of the tile's slice
+  uint32_t nb;  // blocks in the slice
+  uint32_t pad;
+};
+
+struct GLookTile {
+  uint64_t begin;  // first lookup key (index into the lookup hash array)
+  uint32_t count;  // keys in the tile
+  uint32_t filter;
+};
+
+// Device-side plan: pointers into one allocation.
+struct GPlanDev {
+  const GFilter *filters;
+  const uint64_t *ins_off;   // [F + 1]
+  const GInsTile *ins_tiles; // [n_ins_tiles]
+  const GLookTile *look_tiles;
+  const uint32_t *queue_begin;  // [kQueues + 1] tile ranges per queue
+  uint32_t *counters;           // [1 + kQueues]: insert queue, lookup queues
+  uint32_t n_ins_tiles;
+  uint32_t pad;
+};
+
+// ---- insert -----------------------------------------------------------------
+
+__global__ void __launch_bounds__(kInsertThreads)
+grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes) {
+  extern __shared__ uint4 lds4[];
+  unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
+  __shared__ uint32_t tile_id;
+  const uint32_t lane = lane_id();
+  const uint32_t q = lane & 3u;
+  const uint32_t group4 = lane & ~3u;
+  const uint32_t seed_lo = seed_of_word(2u * q);
+  const uint32_t seed_hi = seed_of_word(2u * q + 1u);
+  const uint32_t waves = blockDim.x / kWave;
+  constexpr uint32_t U = 4;
+  constexpr uint32_t kChunk = 64u * U;
+
+  for (;;) {
+    if (threadIdx.x == 0)
+      tile_id = __hip_atomic_fetch_add(plan.counters, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t t = tile_id;
+    __syncthreads();  // every thread has read tile_id before it is overwritten
+    if (t >= plan.n_ins_tiles) break;
+    const GInsTile tile = plan.ins_tiles[t];
+    const GFilter flt = plan.filters[tile.filter];
+    const uint4 *src4 = reinterpret_cast<const uint4 *>(flt.words + (uint64_t)tile.b0 * 8u);
+    for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += blockDim.x) lds4[i] = src4[i];
+    __syncthreads();
+    const uint64_t kb = plan.ins_off[tile.filter];
+    const uint32_t n = (uint32_t)(plan.ins_off[tile.filter + 1] - kb);
+    const uint64_t *keys = hashes + kb;
+    // Four lanes per key (64-bit LDS words), keys loaded directly per group
+    // (tail lanes re-read the last key; OR-ing a mask twice changes nothing).
+    // Keys outside the slice OR a zero mask into word 0, also a no-op.
+    for (uint32_t base = (threadIdx.x / kWave) * kChunk; base < n; base += waves * kChunk) {
+      uint64_t h[U][4];
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+#pragma unroll
+        for (uint32_t p = 0; p < 4; ++p) {
+          const uint32_t i = base + 64u * u + group4 + p;
+          h[u][p] = load_hash<0>(keys + (i < n ? i : n - 1u));
+        }
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+#pragma unroll
+        for (uint32_t p = 0; p < 4; ++p) {
+          const uint32_t rel = block_of((uint32_t)(h[u][p] >> 32), flt.num_blocks) - tile.b0;
+          const bool in = rel < tile.nb;
+          const uint32_t x = (uint32_t)h[u][p];
+          const unsigned long long m = (unsigned long long)(1u << bit_of(seed_lo, x)) |
+                                       ((unsigned long long)(1u << bit_of(seed_hi, x)) << 32);
+          __hip_atomic_fetch_or(lds2 + (in ? rel : 0u) * 4u + q, in ? m : 0ull, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+    __syncthreads();
+    uint4 *dst4 = reinterpret_cast<uint4 *>(flt.words + (uint64_t)tile.b0 * 8u);
+    for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += blockDim.x) dst4[i] = lds4[i];
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+// ---- lookup -----------------------------------------------------------------
+
+template <int U>
+__global__ void __launch_bounds__(256)
+grouped_lookup_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint8_t *__restrict__ out) {
+  __shared__ uint32_t tile_id;
+  const uint32_t lane = lane_id();
+  const uint32_t j = lane & 7u;
+  const uint32_t group = lane & ~7u;
+  const uint32_t seed = seed_of_word(j);
+  const uint32_t waves = blockDim.x / kWave;
+  const uint32_t wave = threadIdx.x / kWave;
+  constexpr uint32_t kChunk = 64u * U;
+  const uint32_t home = blockIdx.x % kQueues;
+
+  for (uint32_t qi = 0; qi < kQueues; ++qi) {
+    const uint32_t queue = (home + qi) % kQueues;
+    const uint32_t qb = plan.queue_begin[queue];
+    const uint32_t qn = plan.queue_begin[queue + 1] - qb;
+    for (;;) {
+      if (threadIdx.x == 0)
+        tile_id = __hip_atomic_fetch_add(plan.counters + 1 + queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      const uint32_t t = tile_id;
+      __syncthreads();
+      if (t >= qn) break;
+      const GLookTile tile = plan.look_tiles[qb + t];
+      const GFilter flt = plan.filters[tile.filter];
+      const uint64_t *keys = hashes + tile.begin;
+      uint8_t *res = out + tile.begin;
+      const uint32_t n = tile.count;
+      for (uint32_t base = wave * kChunk; base < n; base += waves * kChunk) {
+        uint32_t blk[U], lo[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t i = base + 64u * u + lane;
+          const uint64_t h = load_hash<0>(keys + (i < n ? i : n - 1u));
+          lo[u] = (uint32_t)h;
+          blk[u] = block_of((uint32_t)(h >> 32), flt.num_blocks);
+        }
+        uint32_t word[U][8], bit[U][8];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int p = 0; p < 8; ++p) {
+            const uint32_t b = lane_read(blk[u], group + p);
+            bit[u][p] = bit_of(seed, lane_read(lo[u], group + p));
+            word[u][p] = flt.words[(uint64_t)b * 8u + j];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          uint64_t r = 0;
+#pragma unroll
+          for (int p = 0; p < 8; ++p) r |= fold_pass(ballot((word[u][p] >> bit[u][p]) & 1u), p);
+          const uint32_t i = base + 64u * u + lane;
+          if (i < n) res[i] = (uint8_t)((r >> lane) & 1u);
+        }
+      }
+    }
+  }
+}
+
+// Clears the queue counters (a kernel rather than a memset so the graph holds
+// kernel nodes only).
+__global__ void grouped_reset_kernel(uint32_t *counters, uint32_t n) {
+  if (threadIdx.x < n) counters[threadIdx.x] = 0u;
+}
+
+// Order-sensitive 64-bit digest of device words, for comparing autotune
+// candidates: sum over i of mix(i, w[i]) with 64-bit wrap-around.
+__global__ void digest_kernel(const uint32_t *__restrict__ words, uint64_t n, unsigned long long *acc) {
+  unsigned long long s = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    unsigned long long z = ((unsigned long long)i << 32) ^ words[i];
+    z = (z ^ (z >> 31)) * 0x7fb5d329728ea185ull;
+    z = (z ^ (z >> 27)) * 0x81dadef4bc2dd44dull;
+    s += z ^ (z >> 33);
+  }
+  __hip_atomic_fetch_add(acc, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void fill_kernel_u32(uint32_t *p, uint32_t n) {
+  if (threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+__global__ void digest_chain_kernel(unsigned long long *acc, unsigned long long f) {
+  unsigned long long z = acc[0] + f * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  acc[0] = z ^ (z >> 31);
+}
+
+__global__ void digest_tail_kernel(const uint8_t *p, uint32_t n, unsigned long long *acc) {
+  if (threadIdx.x == 0) {
+    unsigned long long v = 0;
+    for (uint32_t i = 0; i < n; ++i) v = (v << 8) | p[i];
+    acc[0] += (v + 1) * 0xff51afd7ed558ccdull;
+  }
+}
+
+}  // namespace
+
+// ---- host side ------------------------------------------------------------------
+
+struct GroupedPlanHost {
+  std::vector<uint64_t> ins_off, look_off;
+  sbbf_grouped_config cfg;
+  bool planned = false;
+  uint32_t n_ins_tiles = 0, n_look_tiles = 0;
+  size_t insert_lds = 0;
+  void *dev = nullptr;  // device allocation holding the plan tables
+  GPlanDev pd{};
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t n_reset = nullptr, n_ins = nullptr, n_look = nullptr;
+  const void *g_ins = nullptr, *g_look = nullptr;
+  void *g_out = nullptr;
+};
+
+}  // namespace sbbf
+
+struct sbbf_group {
+  std::vector<sbbf_filter *> filters;
+  int device = 0;
+  sbbf::GroupedPlanHost plan;
+};
+
+namespace sbbf {
+
+void free_plan(GroupedPlanHost &p) {
+  // Queued runs may still read the plan tables or use the graph.
+  if (p.exec || p.dev) (void)hipDeviceSynchronize();
+  if (p.exec) (void)hipGraphExecDestroy(p.exec);
+  if (p.graph) (void)hipGraphDestroy(p.graph);
+  if (p.dev) (void)hipFree(p.dev);
+  p.exec = nullptr;
+  p.graph = nullptr;
+  p.dev = nullptr;
+  p.planned = false;
+  p.g_ins = p.g_look = nullptr;
+  p.g_out = nullptr;
+}
+
+sbbf_grouped_config default_config(const sbbf_device_info &info) {
+  sbbf_grouped_config c;
+  memset(&c, 0, sizeof(c));
+  c.lookup_tile_keys = 16384;
+  c.lookup_threads = 256;
+  c.lookup_unroll = 2;
+  c.lookup_blocks_per_cu = 8;
+  c.insert_slice_shift = 12;
+  while (c.insert_slice_shift > 6 && ((uint64_t)32u << c.insert_slice_shift) > info.lds_per_block) --c.insert_slice_shift;
+  c.insert_lds_bytes = (uint64_t)32u << c.insert_slice_shift;
+  c.xcd_queues = 1;
+  return c;
+}
+
+sbbf_status check_config(const sbbf_grouped_config &c, const sbbf_device_info &info) {
+  if (c.lookup_tile_keys < 64 || c.lookup_tile_keys % 64) return set_error(SBBF_EINVAL, "lookup_tile_keys must be a multiple of 64");
+  if (c.lookup_threads < 64 || c.lookup_threads > 256 || c.lookup_threads % 64)
+    return set_error(SBBF_EINVAL, "lookup_threads must be 64, 128, 192 or 256");
+  if (c.lookup_unroll != 1 && c.lookup_unroll != 2 && c.lookup_unroll != 4)
+    return set_error(SBBF_EINVAL, "lookup_unroll must be 1, 2 or 4");
+  if (c.lookup_blocks_per_cu < 1 || c.lookup_blocks_per_cu > 64) return set_error(SBBF_EINVAL, "lookup_blocks_per_cu out of range");
+  if (c.insert_slice_shift < 6 || ((uint64_t)32u << c.insert_slice_shift) > info.lds_per_block)
+    return set_error(SBBF_EINVAL, "insert slice must fit one workgroup's LDS");
+  if (c.insert_lds_bytes > info.lds_per_block) return set_error(SBBF_EINVAL, "insert_lds_bytes exceeds the LDS per workgroup");
+  return SBBF_OK;
+}
+
+hipError_t launch_lookup_any(int unroll, dim3 g, dim3 b, hipStream_t s, const GPlanDev &pd, const uint64_t *h, uint8_t *out) {
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL(grouped_lookup_kernel<1>, g, b, 0, s, pd, h, out); break;
+    case 2: hipLaunchKernelGGL(grouped_lookup_kernel<2>, g, b, 0, s, pd, h, out); break;
+    default: hipLaunchKernelGGL(grouped_lookup_kernel<4>, g, b, 0, s, pd, h, out); break;
+  }
+  return hipGetLastError();
+}
+
+const void *lookup_func(int unroll) {
+  switch (unroll) {
+    case 1: return (const void *)grouped_lookup_kernel<1>;
+    case 2: return (const void *)grouped_lookup_kernel<2>;
+    default: return (const void *)grouped_lookup_kernel<4>;
+  }
+}
+
+// Build tiles and queues for the group and copy them to the device.
+sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uint64_t *look_off,
+                               const sbbf_grouped_config &cfg, const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  free_plan(p);
+  const uint32_t F = (uint32_t)g->filters.size();
+  p.ins_off.assign(ins_off, ins_off + F + 1);
+  p.look_off.assign(look_off, look_off + F + 1);
+  for (uint32_t f = 0; f < F; ++f) {
+    if (p.ins_off[f + 1] < p.ins_off[f] || p.look_off[f + 1] < p.look_off[f])
+      return set_error(SBBF_EINVAL, "offsets must be non-decreasing");
+    if (p.ins_off[f + 1] - p.ins_off[f] > 0xFFFFFFFFull)
+      return set_error(SBBF_EUNSUPPORTED, "a filter takes at most 2^32 - 1 insert keys per grouped call");
+  }
+  p.cfg = cfg;
+
+  // Insert tiles: whole filter when it fits insert_lds_bytes, else slices.
+  struct Cost {
+    uint64_t cost;
+    GInsTile t;
+  };
+  std::vector<Cost> ins;
+  size_t max_lds = 32;
+  const uint32_t S = 1u << cfg.insert_slice_shift;
+  for (uint32_t f = 0; f < F; ++f) {
+    const uint64_t n = p.ins_off[f + 1] - p.ins_off[f];
+    if (n == 0) continue;
+    const uint32_t B = g->filters[f]->num_blocks;
+    if ((uint64_t)B * 32u <= cfg.insert_lds_bytes) {
+      ins.push_back({n, {f, 0u, B, 0u}});
+      max_lds = std::max(max_lds, (size_t)B * 32u);
+    } else {
+      for (uint64_t b0 = 0; b0 < B; b0 += S) {
+        const uint32_t nb = (uint32_t)std::min<uint64_t>(S, B - b0);
+        ins.push_back({n, {f, (uint32_t)b0, nb, 0u}});
+        max_lds = std::max(max_lds, (size_t)nb * 32u);
+      }
+    }
+  }
+  std::stable_sort(ins.begin(), ins.end(), [](const Cost &a, const Cost &b) { return a.cost > b.cost; });
+  p.n_ins_tiles = (uint32_t)ins.size();
+  p.insert_lds = max_lds;
+
+  // Lookup tiles, filters assigned to queues greedily by work (largest first).
+  std::vector<uint32_t> order(F);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+    return p.look_off[a + 1] - p.look_off[a] > p.look_off[b + 1] - p.look_off[b];
+  });
+  const int nq = cfg.xcd_queues ? kQueues : 1;
+  std::vector<std::vector<GLookTile>> qt(kQueues);
+  std::vector<uint64_t> load(kQueues, 0);
+  for (uint32_t f : order) {
+    const uint64_t n = p.look_off[f + 1] - p.look_off[f];
+    if (n == 0) continue;
+    int best = 0;
+    for (int k = 1; k < nq; ++k)
+      if (load[k] < load[best]) best = k;
+    load[best] += n;
+    for (uint64_t at = 0; at < n; at += cfg.lookup_tile_keys) {
+      const uint32_t c = (uint32_t)std::min<uint64_t>(cfg.lookup_tile_keys, n - at);
+      qt[best].push_back({p.look_off[f] + at, c, f});
+    }
+  }
+  std::vector<uint32_t> qbegin(kQueues + 1, 0);
+  std::vector<GLookTile> look;
+  for (int k = 0; k < kQueues; ++k) {
+    qbegin[k] = (uint32_t)look.size();
+    look.insert(look.end(), qt[k].begin(), qt[k].end());
+  }
+  qbegin[kQueues] = (uint32_t)look.size();
+  p.n_look_tiles = (uint32_t)look.size();
+
+  std::vector<GFilter> ft(F);
+  for (uint32_t f = 0; f < F; ++f) ft[f] = {g->filters[f]->words, g->filters[f]->num_blocks, 0u};
+
+  // One device allocation: filters | ins_off | ins tiles | look tiles | queue_begin | counters.
+  auto up = [](size_t v) { return (v + 255u) & ~(size_t)255u; };
+  const size_t o_f = 0;
+  const size_t o_io = o_f + up(F * sizeof(GFilter));
+  const size_t o_it = o_io + up((F + 1) * sizeof(uint64_t));
+  const size_t o_lt = o_it + up(std::max<size_t>(1, ins.size()) * sizeof(GInsTile));
+  const size_t o_qb = o_lt + up(std::max<size_t>(1, look.size()) * sizeof(GLookTile));
+  const size_t o_c = o_qb + up((kQueues + 1) * sizeof(uint32_t));
+  const size_t total = o_c + up((1 + kQueues) * sizeof(uint32_t));
+  std::vector<char> host(total, 0);
+  memcpy(host.data() + o_f, ft.data(), F * sizeof(GFilter));
+  memcpy(host.data() + o_io, p.ins_off.data(), (F + 1) * sizeof(uint64_t));
+  for (size_t i = 0; i < ins.size(); ++i) memcpy(host.data() + o_it + i * sizeof(GInsTile), &ins[i].t, sizeof(GInsTile));
+  if (!look.empty()) memcpy(host.data() + o_lt, look.data(), look.size() * sizeof(GLookTile));
+  memcpy(host.data() + o_qb, qbegin.data(), (kQueues + 1) * sizeof(uint32_t));
+  hipError_t e = hipMalloc(&p.dev, total);
+  if (e != hipSuccess) return hip_error(e, "hipMalloc(grouped plan)");
+  e = hipMemcpy(p.dev, host.data(), total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpy(grouped plan)");
+  char *d = static_cast<char *>(p.dev);
+  p.pd.filters = reinterpret_cast<const GFilter *>(d + o_f);
+  p.pd.ins_off = reinterpret_cast<const uint64_t *>(d + o_io);
+  p.pd.ins_tiles = reinterpret_cast<const GInsTile *>(d + o_it);
+  p.pd.look_tiles = reinterpret_cast<const GLookTile *>(d + o_lt);
+  p.pd.queue_begin = reinterpret_cast<const uint32_t *>(d + o_qb);
+  p.pd.counters = reinterpret_cast<uint32_t *>(d + o_c);
+  p.pd.n_ins_tiles = p.n_ins_tiles;
+  (void)hipFuncSetAttribute((const void *)grouped_insert_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)p.insert_lds);
+  (void)hipGetLastError();
+  p.planned = true;
+  return SBBF_OK;
+}
+
+static dim3 insert_grid(const sbbf_device_info &info, const GroupedPlanHost &p) {
+  return dim3(std::max(1u, std::min<uint32_t>(p.n_ins_tiles, (uint32_t)info.compute_units)));
+}
+
+static dim3 lookup_grid(const sbbf_device_info &info, const GroupedPlanHost &p) {
+  const uint32_t want = (uint32_t)info.compute_units * p.cfg.lookup_blocks_per_cu;
+  return dim3(std::max<uint32_t>(kQueues, std::min<uint32_t>(want, std::max<uint32_t>(p.n_look_tiles, kQueues))));
+}
+
+sbbf_status grouped_insert_phase(sbbf_group *g, const uint64_t *d_ins, hipStream_t s, const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  hipLaunchKernelGGL(grouped_reset_kernel, dim3(1), dim3(64), 0, s, p.pd.counters, 1u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "grouped reset");
+  if (p.n_ins_tiles == 0) return SBBF_OK;
+  hipLaunchKernelGGL(grouped_insert_kernel, insert_grid(info, p), dim3(kInsertThreads), p.insert_lds, s, p.pd, d_ins);
+  return hip_error(hipGetLastError(), "grouped insert");
+}
+
+sbbf_status grouped_lookup_phase(sbbf_group *g, const uint64_t *d_look, uint8_t *d_out, hipStream_t s,
+                                 const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  hipLaunchKernelGGL(grouped_reset_kernel, dim3(1), dim3(64), 0, s, p.pd.counters + 1, (uint32_t)kQueues);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(e, "grouped reset");
+  if (p.n_look_tiles == 0) return SBBF_OK;
+  return hip_error(launch_lookup_any(p.cfg.lookup_unroll, lookup_grid(info, p), dim3(p.cfg.lookup_threads), s, p.pd,
+                                     d_look, d_out),
+                   "grouped lookup");
+}
+
+// The graph: reset counters -> insert -> lookup (kernel nodes only).
+static sbbf_status build_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                               const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  hipError_t e = hipGraphCreate(&p.graph, 0);
+  if (e != hipSuccess) return hip_error(e, "hipGraphCreate");
+  static uint32_t all_counters = 1u + kQueues;
+  // Kernel parameters are copied into the graph when a node is added or updated.
+  void *reset_args[] = {(void *)&p.pd.counters, (void *)&all_counters};
+  hipKernelNodeParams kp;
+  memset(&kp, 0, sizeof(kp));
+  kp.func = (void *)grouped_reset_kernel;
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(64);
+  kp.kernelParams = reset_args;
+  e = hipGraphAddKernelNode(&p.n_reset, p.graph, nullptr, 0, &kp);
+  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(reset)");
+  const uint64_t *ins_arg = d_ins;
+  void *ins_args[] = {(void *)&p.pd, (void *)&ins_arg};
+  kp.func = (void *)grouped_insert_kernel;
+  kp.gridDim = insert_grid(info, p);
+  kp.blockDim = dim3(kInsertThreads);
+  kp.sharedMemBytes = (unsigned)p.insert_lds;
+  kp.kernelParams = ins_args;
+  e = hipGraphAddKernelNode(&p.n_ins, p.graph, &p.n_reset, 1, &kp);
+  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(insert)");
+  const uint64_t *look_arg = d_look;
+  uint8_t *out_arg = d_out;
+  void *look_args[] = {(void *)&p.pd, (void *)&look_arg, (void *)&out_arg};
+  kp.func = (void *)lookup_func(p.cfg.lookup_unroll);
+  kp.gridDim = lookup_grid(info, p);
+  kp.blockDim = dim3(p.cfg.lookup_threads);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = look_args;
+  e = hipGraphAddKernelNode(&p.n_look, p.graph, &p.n_ins, 1, &kp);
+  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(lookup)");
+  e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
+  p.g_ins = d_ins;
+  p.g_look = d_look;
+  p.g_out = d_out;
+  return SBBF_OK;
+}
+
+static sbbf_status update_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                                const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  hipKernelNodeParams kp;
+  memset(&kp, 0, sizeof(kp));
+  const uint64_t *ins_arg = d_ins;
+  void *ins_args[] = {(void *)&p.pd, (void *)&ins_arg};
+  kp.func = (void *)grouped_insert_kernel;
+  kp.gridDim = insert_grid(info, p);
+  kp.blockDim = dim3(kInsertThreads);
+  kp.sharedMemBytes = (unsigned)p.insert_lds;
+  kp.kernelParams = ins_args;
+  hipError_t e = hipGraphExecKernelNodeSetParams(p.exec, p.n_ins, &kp);
+  if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams(insert)");
+  const uint64_t *look_arg = d_look;
+  uint8_t *out_arg = d_out;
+  void *look_args[] = {(void *)&p.pd, (void *)&look_arg, (void *)&out_arg};
+  kp.func = (void *)lookup_func(p.cfg.lookup_unroll);
+  kp.gridDim = lookup_grid(info, p);
+  kp.blockDim = dim3(p.cfg.lookup_threads);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = look_args;
+  e = hipGraphExecKernelNodeSetParams(p.exec, p.n_look, &kp);
+  if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams(lookup)");
+  p.g_ins = d_ins;
+  p.g_look = d_look;
+  p.g_out = d_out;
+  return SBBF_OK;
+}
+
+sbbf_status grouped_run_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                              hipStream_t s, const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  sbbf_status st = SBBF_OK;
+  if (!p.exec) {
+    st = build_graph(g, d_ins, d_look, d_out, info);
+  } else if (p.g_ins != d_ins || p.g_look != d_look || p.g_out != d_out) {
+    st = update_graph(g, d_ins, d_look, d_out, info);
+  }
+  if (st != SBBF_OK) return st;
+  return hip_error(hipGraphLaunch(p.exec, s), "hipGraphLaunch(grouped)");
+}
+
+static void digest_launch(const uint32_t *words, uint64_t n, unsigned long long *acc, hipStream_t s) {
+  if (n == 0) return;
+  const uint64_t want = (n + 255) / 256;
+  hipLaunchKernelGGL(digest_kernel, dim3((uint32_t)std::min<uint64_t>(want, 1024)), dim3(256), 0, s, words, n, acc);
+}
+
+// Digest of all filters (in group order) and of the planned lookup outputs.
+static sbbf_status group_digest(sbbf_group *g, const uint8_t *d_out, hipStream_t s, uint64_t *digest) {
+  unsigned long long *acc = nullptr;
+  hipError_t e = hipMallocAsync((void **)&acc, sizeof(unsigned long long) * 2, s);
+  if (e != hipSuccess) return hip_error(e, "hipMallocAsync(digest)");
+  hipLaunchKernelGGL(fill_kernel_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(acc), 4u);
+  unsigned long long h = 0x243f6a8885a308d3ull;
+  for (size_t f = 0; f < g->filters.size(); ++f) {
+    digest_launch(g->filters[f]->words, (uint64_t)g->filters[f]->num_blocks * 8u, acc, s);
+    // Chain filters so that swapping two equal-sized filters changes the digest.
+    hipLaunchKernelGGL(digest_chain_kernel, dim3(1), dim3(1), 0, s, acc, (unsigned long long)f);
+  }
+  const uint64_t nl = g->plan.look_off.empty() ? 0 : g->plan.look_off.back();
+  if (d_out && nl) {
+    // Bytes are digested as 32-bit words plus the ragged tail.
+    digest_launch(reinterpret_cast<const uint32_t *>(d_out), nl / 4, acc + 1, s);
+    if (nl % 4) {
+      hipLaunchKernelGGL(digest_tail_kernel, dim3(1), dim3(64), 0, s, d_out + (nl / 4) * 4, (uint32_t)(nl % 4), acc + 1);
+    }
+  }
+  unsigned long long hostv[2] = {0, 0};
+  e = hipMemcpyAsync(hostv, acc, sizeof(hostv), hipMemcpyDeviceToHost, s);
+  hipError_t e2 = hipFreeAsync(acc, s);
+  hipError_t e3 = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(digest)");
+  if (e2 != hipSuccess) return hip_error(e2, "hipFreeAsync(digest)");
+  if (e3 != hipSuccess) return hip_error(e3, "hipStreamSynchronize(digest)");
+  *digest = hostv[0] * 0x9e3779b97f4a7c15ull ^ hostv[1] ^ h;
+  return SBBF_OK;
+}
+
+}  // namespace sbbf
+
+// ---- C ABI -----------------------------------------------------------------------
+
+using namespace sbbf;
+
+namespace {
+
+// Cache key of an autotune result: device, ROCm runtime, and the batch shape
+// (filter count, total keys, largest filter) in powers of two.
+std::string tune_key(const sbbf_device_info &info, const sbbf_group *g) {
+  int rt = 0;
+  (void)hipRuntimeGetVersion(&rt);
+  uint64_t ins = g->plan.ins_off.back(), look = g->plan.look_off.back();
+  uint32_t maxb = 0;
+  for (auto *f : g->filters) maxb = std::max(maxb, f->num_blocks);
+  auto lg = [](uint64_t v) { int k = 0; while (v > 1) { v >>= 1; ++k; } return k; };
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s|cu%d|hip%d|F%zu|ins2^%d|look2^%d|maxb2^%d", info.arch, info.compute_units, rt,
+           g->filters.size(), lg(ins), lg(look), lg(maxb));
+  for (char *c = buf; *c; ++c)
+    if (*c == ' ') *c = '_';
+  return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, sbbf_grouped_config *cfg) {
+  FILE *fp = fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof(line), fp)) {
+    char k[256];
+    sbbf_grouped_config c;
+    unsigned long long lds = 0;
+    if (sscanf(line, "%255s %u %u %u %u %u %u %llu", k, &c.lookup_tile_keys, &c.lookup_threads, &c.lookup_unroll,
+               &c.lookup_blocks_per_cu, &c.insert_slice_shift, &c.xcd_queues, &lds) == 8 &&
+        key == k) {
+      c.insert_lds_bytes = lds;
+      *cfg = c;  // the last matching line wins
+      found = true;
+    }
+  }
+  fclose(fp);
+  return found;
+}
+
+void cache_store(const char *path, const std::string &key, const sbbf_grouped_config &c) {
+  FILE *fp = fopen(path, "a");
+  if (!fp) return;
+  fprintf(fp, "%s %u %u %u %u %u %u %llu\n", key.c_str(), c.lookup_tile_keys, c.lookup_threads, c.lookup_unroll,
+          c.lookup_blocks_per_cu, c.insert_slice_shift, c.xcd_queues, (unsigned long long)c.insert_lds_bytes);
+  fclose(fp);
+}
+
+sbbf_status need_plan(const sbbf_group *g) {
+  if (!g) return set_error(SBBF_EINVAL, "group is NULL");
+  if (!g->plan.planned) return set_error(SBBF_EINVAL, "group has no plan (call sbbf_grouped_plan)");
+  return SBBF_OK;
+}
+
+sbbf_status check_io(const sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, const uint8_t *d_out) {
+  const uint64_t ni = g->plan.ins_off.back(), nl = g->plan.look_off.back();
+  if (ni && (!d_ins || ((uintptr_t)d_ins & 7))) return set_error(SBBF_EINVAL, "d_ins is NULL or not 8-byte aligned");
+  if (nl && (!d_look || ((uintptr_t)d_look & 7))) return set_error(SBBF_EINVAL, "d_look is NULL or not 8-byte aligned");
+  if (nl && !d_out) return set_error(SBBF_EINVAL, "d_out is NULL");
+  return SBBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbbf_status sbbf_grouped_default_config(sbbf_grouped_config *out) {
+  if (!out) return set_error(SBBF_EINVAL, "out is NULL");
+  sbbf_status st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  *out = default_config(*info);
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_grouped_create(sbbf_filter *const *filters, uint32_t num_filters, sbbf_group **out) {
+  if (!out) return set_error(SBBF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (num_filters == 0 || !filters) return set_error(SBBF_EINVAL, "a group needs at least one filter");
+  for (uint32_t f = 0; f < num_filters; ++f)
+    if (!filters[f]) return set_error(SBBF_EINVAL, "filter " + std::to_string(f) + " is NULL");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  sbbf_group *g = new (std::nothrow) sbbf_group();
+  if (!g) return set_error(SBBF_ENOMEM, "group allocation failed");
+  g->filters.assign(filters, filters + num_filters);
+  g->device = dev;
+  *out = g;
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_grouped_destroy(sbbf_group *g) {
+  if (!g) return set_error(SBBF_EINVAL, "group is NULL");
+  free_plan(g->plan);
+  delete g;
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_grouped_plan(sbbf_group *g, const uint64_t *h_ins_offsets, const uint64_t *h_look_offsets,
+                              const sbbf_grouped_config *cfg) {
+  if (!g || !h_ins_offsets || !h_look_offsets) return set_error(SBBF_EINVAL, "group or offsets is NULL");
+  sbbf_status st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  const sbbf_grouped_config c = cfg ? *cfg : default_config(*info);
+  if ((st = check_config(c, *info)) != SBBF_OK) return st;
+  return grouped_build_plan(g, h_ins_offsets, h_look_offsets, c, *info);
+}
+
+sbbf_status sbbf_grouped_get_config(const sbbf_group *g, sbbf_grouped_config *out) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK) return st;
+  if (!out) return set_error(SBBF_EINVAL, "out is NULL");
+  *out = g->plan.cfg;
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_grouped_run(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                             sbbf_stream s) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  return grouped_run_graph(g, d_ins, d_look, d_out, (hipStream_t)s, *info);
+}
+
+sbbf_status sbbf_grouped_insert(sbbf_group *g, const uint64_t *d_ins, sbbf_stream s) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK) return st;
+  if (g->plan.ins_off.back() && (!d_ins || ((uintptr_t)d_ins & 7)))
+    return set_error(SBBF_EINVAL, "d_ins is NULL or not 8-byte aligned");
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  return grouped_insert_phase(g, d_ins, (hipStream_t)s, *info);
+}
+
+sbbf_status sbbf_grouped_lookup(sbbf_group *g, const uint64_t *d_look, uint8_t *d_out, sbbf_stream s) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK) return st;
+  const uint64_t nl = g->plan.look_off.back();
+  if (nl && (!d_look || ((uintptr_t)d_look & 7) || !d_out))
+    return set_error(SBBF_EINVAL, "d_look or d_out is NULL, or d_look is not 8-byte aligned");
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  return grouped_lookup_phase(g, d_look, d_out, (hipStream_t)s, *info);
+}
+
+sbbf_status sbbf_grouped_run_per_filter(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look,
+                                        uint8_t *d_out, sbbf_stream s) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
+  const auto &io = g->plan.ins_off, &lo = g->plan.look_off;
+  sbbf_launch ins_cfg{0, 0, 0, SBBF_INSERT_ATOMIC32, 0};
+  sbbf_launch look_cfg{0, 0, 0, SBBF_LOOKUP_GATHER, 0};
+  for (size_t f = 0; f < g->filters.size(); ++f) {
+    st = sbbf_insert_batch_ex(g->filters[f], d_ins + io[f], io[f + 1] - io[f], &ins_cfg, s);
+    if (st != SBBF_OK) return st;
+  }
+  for (size_t f = 0; f < g->filters.size(); ++f) {
+    st = sbbf_lookup_batch_ex(g->filters[f], d_look + lo[f], lo[f + 1] - lo[f], d_out + lo[f], nullptr, &look_cfg, s);
+    if (st != SBBF_OK) return st;
+  }
+  return SBBF_OK;
+}
+
+sbbf_status sbbf_grouped_digest(sbbf_group *g, const uint8_t *d_out, sbbf_stream s, uint64_t *digest) {
+  if (!g || !digest) return set_error(SBBF_EINVAL, "group or digest is NULL");
+  if (d_out && !g->plan.planned) return set_error(SBBF_EINVAL, "output digest needs a plan");
+  return group_digest(g, d_out, (hipStream_t)s, digest);
+}
+
+sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                                  uint32_t reps, const char *cache_path, int force, sbbf_grouped_config *best) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  const std::string key = tune_key(*info, g);
+  const std::vector<uint64_t> ins_off = g->plan.ins_off, look_off = g->plan.look_off;
+  if (cache_path && !force) {
+    sbbf_grouped_config c;
+    if (cache_lookup(cache_path, key, &c) && check_config(c, *info) == SBBF_OK) {
+      if ((st = grouped_build_plan(g, ins_off.data(), look_off.data(), c, *info)) != SBBF_OK) return st;
+      if (best) *best = c;
+      return SBBF_OK;
+    }
+  }
+  if (reps == 0) reps = 5;
+  // The inputs come from the caller's streams; wait for them.
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_error(e, "hipDeviceSynchronize(autotune)");
+  hipStream_t s = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_error(e, "hipStreamCreate(autotune)");
+  // Snapshot the filters so every candidate starts from the same contents.
+  uint64_t total = 0;
+  for (auto *f : g->filters) total += (uint64_t)f->num_blocks * 32u;
+  char *snap = nullptr;
+  e = hipMalloc((void **)&snap, total);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return hip_error(e, "hipMalloc(autotune snapshot)");
+  }
+  auto copy_all = [&](bool save) {
+    uint64_t at = 0;
+    for (auto *f : g->filters) {
+      const size_t b = (size_t)f->num_blocks * 32u;
+      if (save)
+        (void)hipMemcpyAsync(snap + at, f->words, b, hipMemcpyDeviceToDevice, s);
+      else
+        (void)hipMemcpyAsync(f->words, snap + at, b, hipMemcpyDeviceToDevice, s);
+      at += b;
+    }
+  };
+  copy_all(true);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+
+  // Coordinate descent from the defaults over each parameter's candidate values.
+  sbbf_grouped_config cur = default_config(*info);
+  std::vector<std::pair<int, std::vector<uint64_t>>> axes = {
+      {0, {4096, 16384, 65536}},  // lookup_tile_keys
+      {1, {64, 128, 256}},        // lookup_threads
+      {2, {1, 2, 4}},             // lookup_unroll
+      {3, {2, 4, 8, 16}},         // lookup_blocks_per_cu
+      {5, {0, 1}},                // xcd_queues
+      {6, {16384, 65536, (uint64_t)32u << cur.insert_slice_shift}},  // insert_lds_bytes
+  };
+  auto with = [](sbbf_grouped_config c, int axis, uint64_t v) {
+    switch (axis) {
+      case 0: c.lookup_tile_keys = (uint32_t)v; break;
+      case 1: c.lookup_threads = (uint32_t)v; break;
+      case 2: c.lookup_unroll = (uint32_t)v; break;
+      case 3: c.lookup_blocks_per_cu = (uint32_t)v; break;
+      case 5: c.xcd_queues = (uint32_t)v; break;
+      case 6: c.insert_lds_bytes = v; break;
+    }
+    return c;
+  };
+  bool have_ref = false;
+  uint64_t ref_digest = 0;
+  float best_ms = 1e30f;
+  sbbf_grouped_config best_cfg = cur;
+  auto measure = [&](const sbbf_grouped_config &c, float *ms) -> sbbf_status {
+    sbbf_status r = grouped_build_plan(g, ins_off.data(), look_off.data(), c, *info);
+    if (r != SBBF_OK) return r;
+    std::vector<float> t;
+    for (uint32_t k = 0; k <= reps; ++k) {
+      copy_all(false);
+      (void)hipEventRecord(e0, s);
+      r = grouped_run_graph(g, d_ins, d_look, d_out, s, *info);
+      if (r != SBBF_OK) return r;
+      (void)hipEventRecord(e1, s);
+      hipError_t es = hipEventSynchronize(e1);
+      if (es != hipSuccess) return hip_error(es, "autotune run");
+      float v = 0;
+      (void)hipEventElapsedTime(&v, e0, e1);
+      if (k > 0) t.push_back(v);  // the first run warms up
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    uint64_t dg = 0;
+    if ((r = group_digest(g, d_out, s, &dg)) != SBBF_OK) return r;
+    if (!have_ref) {
+      ref_digest = dg;
+      have_ref = true;
+    } else if (dg != ref_digest) {
+      return set_error(SBBF_EDEVICE, "autotune candidate produced different results");
+    }
+    return SBBF_OK;
+  };
+  float ms = 0;
+  st = measure(cur, &ms);
+  if (st == SBBF_OK) {
+    best_ms = ms;
+    best_cfg = cur;
+    for (int sweep = 0; sweep < 2 && st == SBBF_OK; ++sweep) {
+      for (auto &ax : axes) {
+        for (uint64_t v : ax.second) {
+          sbbf_grouped_config c = with(best_cfg, ax.first, v);
+          if (memcmp(&c, &best_cfg, sizeof(c)) == 0 || check_config(c, *info) != SBBF_OK) continue;
+          if ((st = measure(c, &ms)) != SBBF_OK) break;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_cfg = c;
+          }
+        }
+        if (st != SBBF_OK) break;
+      }
+    }
+  }
+  copy_all(false);  // leave the filters as they were
+  hipError_t es = hipStreamSynchronize(s);
+  (void)hipFree(snap);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (st != SBBF_OK) return st;
+  if (es != hipSuccess) return hip_error(es, "autotune synchronise");
+  if ((st = grouped_build_plan(g, ins_off.data(), look_off.data(), best_cfg, *info)) != SBBF_OK) return st;
+  if (cache_path) cache_store(cache_path, key, best_cfg);
+  if (best) *best = best_cfg;
+  return SBBF_OK;
+}
+
+}  // extern "C"

@@ -66,6 +66,8 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
                                      uint32_t *out_bits, hipStream_t stream);
 
+// The grouped C ABI (sbbf_grouped_*) is implemented in grouped.hip.
+
 hipError_t launch_bench_gather(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n,
                                uint8_t *out, const Shape &shape, hipStream_t stream);
 hipError_t launch_bench_atomic(uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n, bool wide,

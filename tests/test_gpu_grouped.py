@@ -1,0 +1,192 @@
+"""Parity of the grouped launch (many filters, one graph launch) with the CPU
+oracle applied filter by filter, and with one plain launch per filter."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from synth import grouped_workload, splitmix64_stream  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2101_01719_amd as P
+
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+
+
+def make_group(P, w, cfg=None):
+    filters = [P.Filter(int(b)) for b in w.blocks]
+    return filters, P.Group(filters, w.ins_off, w.look_off, cfg)
+
+
+def check_against_oracle(w, filters, out, which):
+    out = out.cpu().numpy() if hasattr(out, "cpu") else out
+    ins = w.inserts if isinstance(w.inserts, np.ndarray) else None
+    for f in which:
+        B = int(w.blocks[f])
+        i0, i1 = int(w.ins_off[f]), int(w.ins_off[f + 1])
+        l0, l1 = int(w.look_off[f]), int(w.look_off[f + 1])
+        h = ins[i0:i1] if ins is not None else w.inserts[i0:i1].cpu().numpy().view(np.uint64)
+        look = (w.lookups[l0:l1] if isinstance(w.lookups, np.ndarray)
+                else w.lookups[l0:l1].cpu().numpy().view(np.uint64))
+        ref = oracle.build_filter(B, h)
+        got_words = filters[f].words.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got_words, ref), f"filter {f} words"
+        assert np.array_equal(out[l0:l1], oracle.lookup(ref, B, look)), f"filter {f} lookups"
+
+
+@pytest.fixture(scope="module")
+def small():
+    return grouped_workload(num_filters=64, log10_min=2.0, log10_max=5.2)
+
+
+def test_grouped_small_matches_oracle(P, small):
+    w = small
+    filters, g = make_group(P, w)
+    ins, look = dev(w.inserts), dev(w.lookups)
+    out = torch.empty(look.numel(), dtype=torch.uint8, device="cuda")
+    g.run(ins, look, out)
+    torch.cuda.synchronize()
+    check_against_oracle(w, filters, out, range(w.num_filters))
+    # plain per-filter launches give the same filters and results
+    d1 = g.digest(out)
+    g.clear()
+    out2 = torch.zeros_like(out)
+    g.run_per_filter(ins, look, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    assert g.digest(out2) == d1
+    g.close()
+
+
+CONFIGS = [
+    dict(xcd_queues=0),
+    dict(lookup_tile_keys=64, lookup_threads=64, lookup_unroll=1, lookup_blocks_per_cu=1),
+    dict(lookup_tile_keys=4096, lookup_unroll=4, lookup_threads=128),
+    dict(insert_lds_bytes=2048, insert_slice_shift=6),   # every filter above 2 KiB cut into 64-block slices
+    dict(insert_lds_bytes=1 << 16, insert_slice_shift=11),
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS, ids=[str(i) for i in range(len(CONFIGS))])
+def test_grouped_configs_identical(P, small, cfg):
+    w = small
+    filters, g = make_group(P, w, cfg)
+    ins, look = dev(w.inserts), dev(w.lookups)
+    out = torch.empty(look.numel(), dtype=torch.uint8, device="cuda")
+    g.run(ins, look, out)
+    torch.cuda.synchronize()
+    check_against_oracle(w, filters, out, range(0, w.num_filters, 3))
+    g.close()
+
+
+def test_grouped_phases_and_graph_replays(P, small):
+    """The graph is replayed several times with eager work (clears, copies,
+    synchronisations) between replays; every replay matches the eager phases."""
+    w = small
+    filters, g = make_group(P, w)
+    ins, look = dev(w.inserts), dev(w.lookups)
+    ref_out = torch.empty(look.numel(), dtype=torch.uint8, device="cuda")
+    P.sbbf_grouped_insert(g.handle, ins)
+    P.sbbf_grouped_lookup(g.handle, look, ref_out)
+    ref_digest = g.digest(ref_out)
+    check_against_oracle(w, filters, ref_out, range(0, w.num_filters, 5))
+    for k in range(4):
+        g.clear()
+        out = torch.full_like(ref_out, 7)
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.run(ins, look, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref_out), k
+        assert g.digest(out) == ref_digest, k
+        del junk
+    # new buffers: the graph's kernel arguments are updated
+    ins2, look2 = ins.clone(), look.clone()
+    out2 = torch.empty_like(ref_out)
+    g.clear()
+    g.run(ins2, look2, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, ref_out)
+    g.close()
+
+
+def test_grouped_autotune(P, small, tmp_path):
+    w = small
+    filters, g = make_group(P, w)
+    ins, look = dev(w.inserts), dev(w.lookups)
+    out = torch.empty(look.numel(), dtype=torch.uint8, device="cuda")
+    before = g.digest()
+    cache = str(tmp_path / "tune.txt")
+    best = g.autotune(ins, look, out, reps=2, cache_path=cache)
+    assert g.digest() == before  # tuning leaves the filters as they were
+    assert g.config() == best
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("gfx950")
+    again = g.autotune(ins, look, out, reps=2, cache_path=cache)  # served from the cache
+    assert again == best
+    assert len(open(cache).read().strip().splitlines()) == 1
+    g.run(ins, look, out)
+    torch.cuda.synchronize()
+    check_against_oracle(w, filters, out, range(0, w.num_filters, 4))
+    g.close()
+
+
+def test_grouped_edge_cases(P):
+    # empty filters (no inserts, no lookups), a single huge-but-sparse filter,
+    # and filters whose counts are not multiples of anything
+    blocks = np.array([1, 5000, 9000, 3, 70000], dtype=np.int64)
+    n_ins = np.array([0, 7, 100_001, 0, 5], dtype=np.int64)
+    n_look = np.array([0, 0, 33, 9, 65_537], dtype=np.int64)
+    ins_off = np.concatenate([[0], np.cumsum(n_ins)])
+    look_off = np.concatenate([[0], np.cumsum(n_look)])
+    ins = splitmix64_stream(700, int(ins_off[-1]))
+    look = splitmix64_stream(701, int(look_off[-1]))
+    look[:3] = ins[:3]
+    filters = [P.Filter(int(b)) for b in blocks]
+    g = P.Group(filters, ins_off, look_off)
+    out = torch.empty(int(look_off[-1]), dtype=torch.uint8, device="cuda")
+    g.run(dev(ins), dev(look), out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    for f, B in enumerate(blocks.tolist()):
+        ref = oracle.build_filter(B, ins[ins_off[f]:ins_off[f + 1]])
+        assert np.array_equal(filters[f].words.cpu().numpy().view(np.uint32), ref)
+        assert np.array_equal(res[look_off[f]:look_off[f + 1]], oracle.lookup(ref, B, look[look_off[f]:look_off[f + 1]]))
+    with pytest.raises(P.SbbfError):
+        P.sbbf_grouped_plan(g.handle, ins_off[::-1].copy(), look_off)  # decreasing offsets
+    g.close()
+
+
+def test_grouped_full_workload(P):
+    """The 2,048-filter workload (key counts log-uniform in [1e3, 1e6], 10.5
+    bits per key, four lookups per inserted key) in the launch shape the
+    benchmark times: all outputs equal the per-filter plain launches, and a
+    sample of filters (the two largest, the two smallest and 16 others) equals
+    the oracle exactly."""
+    w = grouped_workload(num_filters=2048, backend="torch", device="cuda")
+    filters, g = make_group(P, w)
+    out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
+    g.run(w.inserts, w.lookups, out)
+    torch.cuda.synchronize()
+    digest = g.digest(out)
+    order = np.argsort(w.n)
+    rng = np.random.default_rng(7)
+    sample = sorted(set(order[:2].tolist() + order[-2:].tolist() + rng.choice(2048, 16, replace=False).tolist()))
+    check_against_oracle(w, filters, out, sample)
+    g.clear()
+    out2 = torch.empty_like(out)
+    g.run_per_filter(w.inserts, w.lookups, out2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)
+    assert g.digest(out2) == digest
+    g.close()
