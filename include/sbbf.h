@@ -254,6 +254,75 @@ sbbf_status sbbf_grouped_digest(sbbf_group *g, const uint8_t *d_out, sbbf_stream
 sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
                                   uint32_t reps, const char *cache_path, int force, sbbf_grouped_config *best);
 
+/* ---- serving: resident filters, continuous batching ------------------------ */
+/* The server keeps filters resident in a device arena bounded by a byte budget
+ * and queues requests (insert or lookup batches of any size, hashes and outputs
+ * in device memory) per filter. Each round of its loop launches, into every
+ * free step slot, one step made of the queued requests: per filter the longest
+ * queue prefix of the form inserts-then-lookups, so a lookup sees exactly the
+ * inserts that arrived before it on its filter, as if run alone. Steps run in
+ * order on the server's stream; new requests join the next step while earlier
+ * ones run. Not thread-safe: one host thread drives a server. */
+
+typedef struct sbbf_server_config {
+  uint64_t hbm_budget_bytes;   /* bytes of filters the arena admits */
+  uint32_t max_inflight_steps; /* steps queued on the device at once (slots), 1..64 */
+  uint32_t max_step_requests;  /* requests per step */
+  uint64_t max_step_keys;      /* keys per step (a larger single request runs alone) */
+  uint32_t tile_keys;          /* keys per workgroup tile, a multiple of 64 */
+  uint32_t reserved;
+} sbbf_server_config;
+
+typedef struct sbbf_request {
+  uint64_t arrival_ns;   /* replay: arrival time relative to the start of the replay */
+  uint32_t filter_id;
+  uint32_t op;           /* 0 insert, 1 lookup */
+  const uint64_t *d_hashes;
+  uint8_t *d_out;        /* lookups: one byte per hash */
+  uint64_t n;
+} sbbf_request;
+
+typedef struct sbbf_serving_stats {
+  uint64_t requests_done, keys_done, steps;
+  double p50_us, p99_us, max_us; /* latency: completion seen by the host minus arrival */
+  double span_s;                 /* first arrival to last completion */
+  double gkeys_per_s;            /* keys_done / span_s / 1e9 */
+  uint64_t arena_used_bytes, arena_reserved_bytes;
+} sbbf_serving_stats;
+
+sbbf_status sbbf_server_default_config(sbbf_server_config *out);
+sbbf_status sbbf_server_create(const sbbf_server_config *cfg, sbbf_server **out);
+/* Waits for queued device work, then frees everything. */
+sbbf_status sbbf_server_destroy(sbbf_server *s);
+/* Admit a zeroed filter of num_blocks blocks; SBBF_EBUDGET when the budget does
+ * not allow it (the caller may retry after removing filters). */
+sbbf_status sbbf_server_add_filter(sbbf_server *s, uint32_t num_blocks, uint32_t *filter_id);
+/* Finish the filter's queued work, then release its memory and id. */
+sbbf_status sbbf_server_remove_filter(sbbf_server *s, uint32_t filter_id);
+sbbf_status sbbf_server_arena_usage(const sbbf_server *s, uint64_t *used_bytes, uint64_t *reserved_bytes);
+/* Queue one request (arrival = now). Buffers stay caller-owned and must
+ * remain valid until the request completes. */
+sbbf_status sbbf_server_submit(sbbf_server *s, uint32_t filter_id, int op, const uint64_t *d_hashes, uint64_t n,
+                               uint8_t *d_out, uint64_t *req_id);
+/* One round of the loop: record finished steps, launch steps into free slots;
+ * with wait != 0 and nothing launched, block until one step finishes. */
+sbbf_status sbbf_server_pump(sbbf_server *s, int wait);
+/* Run the loop until every queued request has completed. */
+sbbf_status sbbf_server_drain(sbbf_server *s);
+/* Completed request ids since the last poll (SBBF_EAGAIN when none). */
+sbbf_status sbbf_server_poll(sbbf_server *s, uint64_t *done_ids, uint32_t cap, uint32_t *n_done);
+sbbf_status sbbf_server_request_times(const sbbf_server *s, uint64_t req_id, uint64_t *arrival_ns, uint64_t *done_ns);
+/* Drive a request log (sorted by arrival_ns) through the loop from this thread:
+ * with realtime != 0 each request is queued when its arrival time is reached,
+ * else all at once. Returns when all have completed; *first_id is the id of
+ * log[0] (ids are consecutive). */
+sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t count, int realtime,
+                               uint64_t *first_id);
+sbbf_status sbbf_server_stats(const sbbf_server *s, sbbf_serving_stats *out);
+/* Checkpoint / restore one filter's bytes (waits for all queued work first). */
+sbbf_status sbbf_server_snapshot(sbbf_server *s, uint32_t filter_id, void *host_dst);
+sbbf_status sbbf_server_restore(sbbf_server *s, uint32_t filter_id, const void *host_src);
+
 #ifdef __cplusplus
 } /* extern "C" */
 #endif

@@ -168,3 +168,25 @@ def block_histogram(hashes, num_blocks: int) -> np.ndarray:
 def build_filter(num_blocks: int, hashes) -> np.ndarray:
     """A fresh filter holding ``hashes``."""
     return insert(new_filter(num_blocks), num_blocks, hashes)
+
+
+def replay_requests(blocks, filt, op, key_off, payload, out_off=None):
+    """Apply a request log in order, one request at a time: request r inserts
+    payload[key_off[r]:key_off[r+1]] into filter filt[r] (op 0) or looks those
+    hashes up (op 1). Returns (filters, outputs): the final word arrays and the
+    lookup result bytes laid end to end in request order."""
+    filters = [new_filter(int(b)) for b in blocks]
+    n_out = int(sum(int(key_off[r + 1] - key_off[r]) for r in range(len(op)) if op[r] == 1))
+    outputs = np.zeros(n_out, dtype=np.uint8)
+    at = 0
+    for r in range(len(op)):
+        f = int(filt[r])
+        h = payload[int(key_off[r]):int(key_off[r + 1])]
+        if op[r] == 0:
+            insert(filters[f], int(blocks[f]), h)
+        else:
+            if out_off is not None:
+                assert int(out_off[r]) == at
+            outputs[at:at + h.size] = lookup(filters[f], int(blocks[f]), h)
+            at += h.size
+    return filters, outputs

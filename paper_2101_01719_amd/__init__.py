@@ -20,7 +20,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import sbbf_device_info, sbbf_grouped_config, sbbf_launch
+from ._lib import sbbf_device_info, sbbf_grouped_config, sbbf_launch, sbbf_server_config, sbbf_serving_stats
 
 SBBF_OK = 0
 SBBF_EINVAL = 1
@@ -330,6 +330,105 @@ def sbbf_grouped_autotune(g: int, d_ins, d_look, d_out, reps: int = 5, cache_pat
     return _cfg_dict(c)
 
 
+# ---- serving --------------------------------------------------------------------------------
+
+def sbbf_server_default_config() -> sbbf_server_config:
+    c = sbbf_server_config()
+    _check(_L().sbbf_server_default_config(ctypes.byref(c)))
+    return c
+
+
+def sbbf_server_create(cfg=None) -> int:
+    c = sbbf_server_default_config()
+    for k, v in dict(cfg or {}).items():
+        setattr(c, k, v)
+    h = ctypes.c_void_p()
+    _check(_L().sbbf_server_create(ctypes.byref(c), ctypes.byref(h)))
+    return h.value
+
+
+def sbbf_server_destroy(s: int) -> None:
+    _check(_L().sbbf_server_destroy(s))
+
+
+def sbbf_server_add_filter(s: int, num_blocks: int) -> int:
+    fid = ctypes.c_uint32()
+    _check(_L().sbbf_server_add_filter(s, num_blocks, ctypes.byref(fid)))
+    return fid.value
+
+
+def sbbf_server_remove_filter(s: int, filter_id: int) -> None:
+    _check(_L().sbbf_server_remove_filter(s, filter_id))
+
+
+def sbbf_server_arena_usage(s: int):
+    used, reserved = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_L().sbbf_server_arena_usage(s, ctypes.byref(used), ctypes.byref(reserved)))
+    return used.value, reserved.value
+
+
+def sbbf_server_submit(s: int, filter_id: int, op: int, d_hashes, d_out=None) -> int:
+    p, n = _hashes(d_hashes)
+    rid = ctypes.c_uint64()
+    _check(_L().sbbf_server_submit(s, filter_id, op, p, n, _dptr(d_out), ctypes.byref(rid)))
+    return rid.value
+
+
+def sbbf_server_pump(s: int, wait: bool = False) -> None:
+    _check(_L().sbbf_server_pump(s, int(wait)))
+
+
+def sbbf_server_drain(s: int) -> None:
+    _check(_L().sbbf_server_drain(s))
+
+
+def sbbf_server_poll(s: int, cap: int = 4096) -> list:
+    buf = (ctypes.c_uint64 * cap)()
+    n = ctypes.c_uint32()
+    st = _L().sbbf_server_poll(s, buf, cap, ctypes.byref(n))
+    if st not in (SBBF_OK, SBBF_EAGAIN):
+        _check(st)
+    return list(buf[: n.value])
+
+
+def sbbf_server_request_times(s: int, req_id: int):
+    a, d = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_L().sbbf_server_request_times(s, req_id, ctypes.byref(a), ctypes.byref(d)))
+    return a.value, d.value
+
+
+# numpy layout of sbbf_request (40 bytes)
+REQUEST_DTYPE = [("arrival_ns", "<u8"), ("filter_id", "<u4"), ("op", "<u4"), ("d_hashes", "<u8"),
+                 ("d_out", "<u8"), ("n", "<u8")]
+
+
+def sbbf_server_replay(s: int, requests, realtime: bool = True) -> int:
+    """requests: a numpy structured array of REQUEST_DTYPE. Returns the id of the first request."""
+    import numpy as np
+
+    req = np.ascontiguousarray(requests)
+    if req.dtype != np.dtype(REQUEST_DTYPE):
+        raise TypeError("requests must use REQUEST_DTYPE")
+    first = ctypes.c_uint64()
+    _check(_L().sbbf_server_replay(s, ctypes.c_void_p(req.ctypes.data), req.size, int(realtime), ctypes.byref(first)))
+    return first.value
+
+
+def sbbf_server_stats(s: int) -> dict:
+    st = sbbf_serving_stats()
+    _check(_L().sbbf_server_stats(s, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in sbbf_serving_stats._fields_}
+
+
+def sbbf_server_snapshot(s: int, filter_id: int, host: torch.Tensor) -> torch.Tensor:
+    _check(_L().sbbf_server_snapshot(s, filter_id, ctypes.c_void_p(host.data_ptr())))
+    return host
+
+
+def sbbf_server_restore(s: int, filter_id: int, host: torch.Tensor) -> None:
+    _check(_L().sbbf_server_restore(s, filter_id, ctypes.c_void_p(host.data_ptr())))
+
+
 # ---- convenience --------------------------------------------------------------------------
 
 class Filter:
@@ -419,3 +518,19 @@ class Group:
             self.close()
         except Exception:
             pass
+
+
+def serving_requests(log, d_payload, d_out):
+    """The sbbf_request array for a synth ServingLog whose payload is staged in
+    d_payload (int64 view, device) and whose lookup outputs go to d_out (uint8)."""
+    import numpy as np
+
+    req = np.zeros(log.num_requests, dtype=REQUEST_DTYPE)
+    req["arrival_ns"] = log.arrival_ns
+    req["filter_id"] = log.filter
+    req["op"] = log.op
+    req["n"] = log.n
+    req["d_hashes"] = np.uint64(d_payload.data_ptr()) + log.key_off[:-1].astype(np.uint64) * np.uint64(8)
+    look = log.op == 1
+    req["d_out"] = np.where(look, np.uint64(d_out.data_ptr()) + log.out_off[:-1].astype(np.uint64), np.uint64(0))
+    return req

@@ -59,6 +59,35 @@ class sbbf_grouped_config(ctypes.Structure):
 
 _CFGP = ctypes.POINTER(sbbf_grouped_config)
 
+
+class sbbf_server_config(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", c_u64),
+        ("max_inflight_steps", c_u32),
+        ("max_step_requests", c_u32),
+        ("max_step_keys", c_u64),
+        ("tile_keys", c_u32),
+        ("reserved", c_u32),
+    ]
+
+
+class sbbf_serving_stats(ctypes.Structure):
+    _fields_ = [
+        ("requests_done", c_u64),
+        ("keys_done", c_u64),
+        ("steps", c_u64),
+        ("p50_us", ctypes.c_double),
+        ("p99_us", ctypes.c_double),
+        ("max_us", ctypes.c_double),
+        ("span_s", ctypes.c_double),
+        ("gkeys_per_s", ctypes.c_double),
+        ("arena_used_bytes", c_u64),
+        ("arena_reserved_bytes", c_u64),
+    ]
+
+
+_SCFGP = ctypes.POINTER(sbbf_server_config)
+
 # name -> (restype, argtypes); every symbol declared in include/sbbf.h.
 SIGNATURES = {
     "sbbf_status_string": (ctypes.c_char_p, [c_int]),
@@ -94,6 +123,21 @@ SIGNATURES = {
     "sbbf_grouped_run_per_filter": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "sbbf_grouped_digest": (c_int, [c_vp, c_vp, c_vp, ctypes.POINTER(c_u64)]),
     "sbbf_grouped_autotune": (c_int, [c_vp, c_vp, c_vp, c_vp, c_u32, ctypes.c_char_p, c_int, _CFGP]),
+    "sbbf_server_default_config": (c_int, [_SCFGP]),
+    "sbbf_server_create": (c_int, [_SCFGP, ctypes.POINTER(c_vp)]),
+    "sbbf_server_destroy": (c_int, [c_vp]),
+    "sbbf_server_add_filter": (c_int, [c_vp, c_u32, ctypes.POINTER(c_u32)]),
+    "sbbf_server_remove_filter": (c_int, [c_vp, c_u32]),
+    "sbbf_server_arena_usage": (c_int, [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64)]),
+    "sbbf_server_submit": (c_int, [c_vp, c_u32, c_int, c_vp, c_u64, c_vp, ctypes.POINTER(c_u64)]),
+    "sbbf_server_pump": (c_int, [c_vp, c_int]),
+    "sbbf_server_drain": (c_int, [c_vp]),
+    "sbbf_server_poll": (c_int, [c_vp, ctypes.POINTER(c_u64), c_u32, ctypes.POINTER(c_u32)]),
+    "sbbf_server_request_times": (c_int, [c_vp, c_u64, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64)]),
+    "sbbf_server_replay": (c_int, [c_vp, c_vp, c_u64, c_int, ctypes.POINTER(c_u64)]),
+    "sbbf_server_stats": (c_int, [c_vp, ctypes.POINTER(sbbf_serving_stats)]),
+    "sbbf_server_snapshot": (c_int, [c_vp, c_u32, c_vp]),
+    "sbbf_server_restore": (c_int, [c_vp, c_u32, c_vp]),
 }
 
 _lib = None

@@ -1,0 +1,170 @@
+"""The serving loop: results of continuous batching equal the oracle replaying
+the same request log in arrival order, and equal each request run alone;
+admission by budget; checkpoint and restore."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from synth.serving import serving_log  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2101_01719_amd as P
+
+    return P
+
+
+@pytest.fixture(scope="module")
+def small_log():
+    return serving_log(num_filters=256, num_requests=3000, rate_per_s=2e6, max_size=4096, log10_min=2.0,
+                       log10_max=4.5)
+
+
+@pytest.fixture(scope="module")
+def small_ref(small_log):
+    L = small_log
+    return oracle.replay_requests(L.blocks, L.filter, L.op, L.key_off, L.payload, L.out_off)
+
+
+def staged(L):
+    d_payload = torch.from_numpy(L.payload.view(np.int64)).to("cuda")
+    d_out = torch.full((int(L.out_off[-1]),), 7, dtype=torch.uint8, device="cuda")
+    return d_payload, d_out
+
+
+def make_server(P, L, **cfg):
+    s = P.sbbf_server_create(cfg)
+    ids = [P.sbbf_server_add_filter(s, int(b)) for b in L.blocks]
+    assert ids == list(range(L.num_filters))
+    return s
+
+
+def snapshot_all(P, s, L):
+    out = []
+    for f, b in enumerate(L.blocks.tolist()):
+        host = torch.empty(8 * b, dtype=torch.int32)
+        P.sbbf_server_snapshot(s, f, host)
+        out.append(host.numpy().view(np.uint32).copy())
+    return out
+
+
+def check(P, s, L, d_out, ref):
+    filters, outputs = ref
+    got = d_out.cpu().numpy()
+    assert np.array_equal(got, outputs)
+    for f, words in enumerate(snapshot_all(P, s, L)):
+        assert np.array_equal(words, filters[f]), f
+
+
+@pytest.mark.parametrize("realtime,inflight,step_keys", [(False, 2, 1 << 20), (True, 2, 1 << 20), (False, 1, 4096),
+                                                         (True, 4, 65536), (False, 3, 1)])
+def test_mix_matches_oracle(P, small_log, small_ref, realtime, inflight, step_keys):
+    L = small_log
+    s = make_server(P, L, max_inflight_steps=inflight, max_step_keys=step_keys, tile_keys=256)
+    d_payload, d_out = staged(L)
+    req = P.serving_requests(L, d_payload, d_out)
+    first = P.sbbf_server_replay(s, req, realtime=realtime)
+    assert first == 0
+    st = P.sbbf_server_stats(s)
+    assert st["requests_done"] == L.num_requests
+    assert st["keys_done"] == int(L.key_off[-1])
+    assert 0 < st["p50_us"] <= st["p99_us"] <= st["max_us"]
+    if step_keys >= 65536:
+        assert st["steps"] < L.num_requests  # requests were batched
+    check(P, s, L, d_out, small_ref)
+    P.sbbf_server_destroy(s)
+
+
+def test_alone_equals_mix(P, small_log, small_ref):
+    """Every request submitted alone (the loop drained after each one, in log
+    order) gives the same bytes as the mixed replay and the oracle."""
+    L = small_log
+    s = make_server(P, L)
+    d_payload, d_out = staged(L)
+    ids = []
+    for r in range(L.num_requests):
+        h = d_payload[int(L.key_off[r]):int(L.key_off[r + 1])]
+        out = d_out[int(L.out_off[r]):int(L.out_off[r + 1])] if L.op[r] == 1 else None
+        ids.append(P.sbbf_server_submit(s, int(L.filter[r]), int(L.op[r]), h, out))
+        P.sbbf_server_drain(s)
+    assert ids == list(range(L.num_requests))
+    done = []
+    while True:
+        got = P.sbbf_server_poll(s, 1024)
+        if not got:
+            break
+        done += got
+    assert sorted(done) == ids
+    assert P.sbbf_server_stats(s)["steps"] == L.num_requests
+    check(P, s, L, d_out, small_ref)
+    P.sbbf_server_destroy(s)
+
+
+def test_admission_by_budget(P):
+    budget = 1 << 20  # 1 MiB of filters
+    s = P.sbbf_server_create(dict(hbm_budget_bytes=budget))
+    ids = []
+    with pytest.raises(P.SbbfError) as e:
+        while True:
+            ids.append(P.sbbf_server_add_filter(s, 3000))  # 96,000 bytes each (rounded to 96,000)
+    assert e.value.status == P.SBBF_EBUDGET
+    used, reserved = P.sbbf_server_arena_usage(s)
+    assert len(ids) == budget // 96000 and used <= budget and reserved <= budget
+    # a filter is admitted again once memory is released
+    P.sbbf_server_remove_filter(s, ids[3])
+    fid = P.sbbf_server_add_filter(s, 3000)
+    assert fid == ids[3]
+    with pytest.raises(P.SbbfError):
+        P.sbbf_server_add_filter(s, 3000)
+    # the re-admitted filter starts empty and works
+    h = torch.arange(1, 5001, dtype=torch.int64, device="cuda") * 0x9E3779B97F4A7C15 % (1 << 62)
+    out = torch.empty(5000, dtype=torch.uint8, device="cuda")
+    P.sbbf_server_submit(s, fid, 0, h)
+    P.sbbf_server_submit(s, fid, 1, h, out)
+    P.sbbf_server_drain(s)
+    assert bool(out.all())
+    P.sbbf_server_destroy(s)
+
+
+def test_checkpoint_and_resume(P, small_log, small_ref):
+    """Snapshot every filter half way through the log, tear the server down,
+    restore the snapshots into a new server and replay the rest: the final
+    filters and outputs equal an uninterrupted run."""
+    L = small_log
+    half = L.num_requests // 2
+    d_payload, d_out = staged(L)
+    req = P.serving_requests(L, d_payload, d_out)
+    s = make_server(P, L)
+    P.sbbf_server_replay(s, req[:half], realtime=False)
+    snaps = snapshot_all(P, s, L)
+    P.sbbf_server_destroy(s)
+    s2 = make_server(P, L)
+    for f, words in enumerate(snaps):
+        P.sbbf_server_restore(s2, f, torch.from_numpy(words.view(np.int32)))
+    tail = req[half:].copy()
+    tail["arrival_ns"] -= tail["arrival_ns"][0]
+    P.sbbf_server_replay(s2, tail, realtime=False)
+    check(P, s2, L, d_out, small_ref)
+    P.sbbf_server_destroy(s2)
+
+
+def test_serving_workload_scale(P):
+    """4,096 resident filters sized like the grouped workload and 20,000
+    requests (sizes log-uniform in 1..65,536, 20 % inserts) replayed in real
+    time: all outputs and all final filters equal the oracle's replay."""
+    L = serving_log(num_filters=4096, num_requests=20_000, rate_per_s=2e5)
+    ref = oracle.replay_requests(L.blocks, L.filter, L.op, L.key_off, L.payload, L.out_off)
+    s = make_server(P, L)
+    d_payload, d_out = staged(L)
+    P.sbbf_server_replay(s, P.serving_requests(L, d_payload, d_out), realtime=True)
+    st = P.sbbf_server_stats(s)
+    print("serving stats:", st)
+    assert st["requests_done"] == L.num_requests
+    check(P, s, L, d_out, ref)
+    P.sbbf_server_destroy(s)

@@ -98,3 +98,37 @@ def test_grouped_workload_layout_and_backends():
         # every member looked up exactly once, the rest are not members
         assert np.array_equal(np.sort(look[mem]), np.sort(ins))
         assert not np.isin(look[~mem], ins).any()
+
+
+def test_serving_log_recipe():
+    from synth.serving import serving_log
+
+    L = serving_log(num_filters=64, num_requests=3000, rate_per_s=1e6, max_size=1024, log10_min=2.0, log10_max=3.5)
+    assert np.all(np.diff(L.arrival_ns.astype(np.int64)) >= 0)
+    # Poisson arrivals: mean gap 1 us
+    assert abs(float(L.arrival_ns[-1]) / L.num_requests - 1000.0) < 100.0
+    assert abs((L.op == 0).mean() - 0.2) < 0.03
+    assert L.n.min() >= 1 and L.n.max() <= 1024
+    assert np.array_equal(np.diff(L.key_off), L.n)
+    assert L.out_off[-1] == L.n[L.op == 1].sum()
+    assert np.bincount(L.filter, minlength=64).min() > 0
+    # lookups draw about a quarter of their keys from earlier inserts of their filter
+    seen = {}
+    hits = total = 0
+    for r in range(L.num_requests):
+        f = int(L.filter[r])
+        keys = L.payload[L.key_off[r]:L.key_off[r + 1]]
+        if L.op[r] == 0:
+            seen.setdefault(f, set()).update(keys.tolist())
+        elif f in seen:
+            s = seen[f]
+            hits += sum(k in s for k in keys.tolist())
+            total += keys.size
+    assert abs(hits / total - 0.25) < 0.02
+
+
+def test_serving_log_stream_positions():
+    from synth.serving import _stream_at
+
+    pos = np.array([0, 1, 17, 999, 123456], dtype=np.int64)
+    assert np.array_equal(_stream_at(11, pos), splitmix64_stream(11, 123457)[pos])
