@@ -9,10 +9,13 @@ is the 100M-key geometry of the paper's evaluation table: 4,194,304 blocks
 synthetic SplitMix64 hashes resident in device memory before timing starts.
 
 Prints one JSON line. ``value`` is total keys (inserts + lookups) per second
-over the timed steps; per-kernel rates, the roofline of the dominant kernel
-(from HIP events recorded on the launch stream around every kernel in the
-timed region), the measured gather / atomic / streaming ceilings and the CPU
-oracle's rate on a bounded sample are reported beside it.
+over the timed steps; per-operation rates, the roofline of the dominant
+operation (from HIP events recorded on the launch stream around every library
+call in the timed region; an operation may be several kernels), the measured
+gather / atomic / streaming ceilings and the CPU oracle's rate on a bounded
+sample are reported beside it, then the grouped workload (2,048 filters, one
+graph launch against one plain launch per filter) and the serving workload
+(4,096 resident filters, Poisson request stream, p50/p99 latency).
 """
 
 from __future__ import annotations
@@ -143,6 +146,105 @@ def _ceilings(P, torch, w, look_launch, ins_launch, reps=5):
     return res
 
 
+def _grouped(P, torch, autotune=True, reps=5):
+    """The grouped workload: 2,048 filters with key counts log-uniform in
+    [1e3, 1e6], 10.5 bits per key, four lookups per inserted key at a 25 %
+    member rate; one graph launch against one plain launch per filter per
+    operation, same data, identical results (digest of every filter and every
+    output byte)."""
+    from synth import grouped_workload
+
+    w = grouped_workload(num_filters=2048, backend="torch", device="cuda")
+    filters = [P.Filter(int(b)) for b in w.blocks]
+    g = P.Group(filters, w.ins_off, w.look_off)
+    out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
+    tuned = g.autotune(w.inserts, w.lookups, out, reps=3) if autotune else g.config()
+
+    def timed(fn, n):
+        ts = []
+        for k in range(n + 1):
+            g.clear()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if k:
+                ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    graph_ms = timed(lambda: g.run(w.inserts, w.lookups, out), reps)
+    d_graph = g.digest(out)
+    per_ms = timed(lambda: g.run_per_filter(w.inserts, w.lookups, out), max(2, reps // 2))
+    d_per = g.digest(out)
+    keys = int(w.ins_off[-1] + w.look_off[-1])
+    res = {
+        "workload": "2,048 filters, key counts log-uniform in [1e3, 1e6] (SplitMix64 seed 4), 10.5 bits/key, "
+                    f"{int(w.ins_off[-1]):,} inserts and {int(w.look_off[-1]):,} lookups (25 % members)",
+        "graph_ms": graph_ms,
+        "per_filter_ms": per_ms,
+        "speedup_vs_per_filter": per_ms / graph_ms,
+        "gkeys_per_s": keys / graph_ms / 1e6,
+        "per_filter_gkeys_per_s": keys / per_ms / 1e6,
+        "identical_results": d_graph == d_per,
+        "config": tuned,
+    }
+    g.close()
+    del filters, out, w
+    torch.cuda.empty_cache()
+    return res
+
+
+def _serving(P, torch, num_requests=50_000):
+    """The serving workload: 4,096 resident filters sized like the grouped
+    workload (seed 5), Poisson arrivals, 20 % insert / 80 % lookup requests of
+    log-uniform size 1..65,536, uniform filter choice; capacity with every
+    request queued at once, then latency at 25 / 50 / 90 % of that capacity."""
+    import numpy as np
+
+    from synth.serving import serving_log
+
+    base_rate = 1e6
+    L = serving_log(num_filters=4096, num_requests=num_requests, rate_per_s=base_rate)
+    d_payload = torch.from_numpy(L.payload.view(np.int64)).to("cuda")
+    d_out = torch.empty(int(L.out_off[-1]), dtype=torch.uint8, device="cuda")
+    cfg = dict(max_step_keys=16 << 20, max_step_requests=16384)
+
+    def run(rate):
+        s = P.sbbf_server_create(cfg)
+        for b in L.blocks.tolist():
+            P.sbbf_server_add_filter(s, b)
+        req = P.serving_requests(L, d_payload, d_out)
+        if rate:
+            req["arrival_ns"] = (L.arrival_ns.astype(np.float64) * (base_rate / rate)).astype(np.uint64)
+        torch.cuda.synchronize()
+        P.sbbf_server_replay(s, req, realtime=bool(rate))
+        st = P.sbbf_server_stats(s)
+        P.sbbf_server_destroy(s)
+        return st
+
+    cap = run(0)
+    mean_keys = float(L.n.mean())
+    points = []
+    for frac in (0.25, 0.5, 0.9):
+        rate = frac * cap["gkeys_per_s"] * 1e9 / mean_keys
+        st = run(rate)
+        points.append({"load": frac, "requests_per_s": rate, "offered_gkeys_per_s": rate * mean_keys / 1e9,
+                       "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
+                       "sustained_gkeys_per_s": st["gkeys_per_s"], "steps": st["steps"]})
+    half = points[1]
+    return {
+        "workload": f"4,096 filters ({int(L.blocks.sum()) * 32 / 2**20:.1f} MiB resident), {num_requests:,} requests "
+                    f"({int(L.key_off[-1]):,} keys), 20 % inserts, sizes log-uniform 1..65,536",
+        "capacity_gkeys_per_s": cap["gkeys_per_s"],
+        "p50_us": half["p50_us"],
+        "p99_us": half["p99_us"],
+        "at_load": points,
+        "config": cfg,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +259,9 @@ def main(argv=None):
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
+    ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the steps, copy this many MiB once with a plain device copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -287,8 +392,14 @@ def main(argv=None):
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(w)
         result["speedup_vs_cpu_baseline"] = result["value"] / result["cpu_baseline"]["value"]
-    print(json.dumps(result), flush=True)
     f.close()
+    del w, out, f
+    torch.cuda.empty_cache()
+    if not a.no_grouped:
+        result["grouped"] = _grouped(P, torch)
+    if not a.no_serving:
+        result["serving"] = _serving(P, torch, a.serving_requests)
+    print(json.dumps(result), flush=True)
     return 0
 
 
