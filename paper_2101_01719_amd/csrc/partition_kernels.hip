@@ -7,12 +7,15 @@
 // cut into G contiguous chunks, one per partitioning workgroup. Kernels:
 //
 //   count     workgroup g counts the keys of chunk g per slice -> hist[g][s]
+//   colsum    column sums of hist over blocks of 256 rows
 //   colscan   start[g][s] = sum of hist[< g][s]; tot[s] = sum over g
-//   offsets   offsets[s] = sum of tot[< s]: where slice s begins
+//   offsets   offsets[s] = sum of round4(tot[< s]): slice s's keys begin at a
+//             multiple of four keys (32 bytes)
 //   scatter   workgroup g walks chunk g in tiles, sorts each tile by slice in
 //             LDS and writes each slice's run with consecutive lanes at the
 //             slice cursor offsets[s] + start[g][s] + (keys already written);
-//             for lookups it also records pos[i], where key i went
+//             for lookups it also records pos[i], where key i's result sits
+//             among the chunk's results
 //   slice     one workgroup per slice loads the slice into LDS; insert ORs the
 //             slice's keys into it and stores it back with plain stores,
 //             lookup tests the slice's keys against it and writes one result
@@ -24,8 +27,8 @@
 // No global atomics touch the filter or the partition. The partition order
 // is deterministic up to the order of equal-slice keys inside one tile, and a
 // filter is the OR of all masks, so inserts never depend on it; lookups are
-// pure and return to input order through pos. Positions are 32-bit: one
-// launch handles fewer than 2^32 keys (the C ABI splits larger batches).
+// pure and return to input order through pos. Lookup chunks hold at most
+// 65,536 keys, so positions are 16-bit.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,54 +38,60 @@
 namespace sbbf {
 namespace {
 
-constexpr uint32_t kPartThreads = 1024;                          // count, scan, slice and unpermute kernels
-constexpr uint32_t kScatterThreads = 512;
-constexpr uint32_t kScatterPerThread = 8;
-constexpr uint32_t kTile = kScatterThreads * kScatterPerThread;  // keys per scatter tile
-constexpr int kSliceUnroll = 8;                                  // 64-key chunks per wave per iteration
-constexpr uint32_t kColsPerScanBlock = 64;
+constexpr uint32_t kPartThreads = 1024;    // count, scan, slice and unpermute kernels
+constexpr uint32_t kScatterThreads = 1024;  // at least partition_max_slices() / 8
+constexpr uint32_t kScatterPer = 7;        // keys per thread per scatter tile
+constexpr uint32_t kTile = kScatterThreads * kScatterPer;
+constexpr uint32_t kScanRows = 256;    // rows per colsum/colscan workgroup (16 segments of 16)
+constexpr uint32_t kScanCols = 64;     // columns per colsum/colscan workgroup
+constexpr uint32_t kSliceSteps = 2;    // 256-key steps per wave per slice-loop iteration
 // Lookup chunks are at most this many keys so that one chunk's result bytes
-// fit one workgroup's LDS in the unpermute kernel.
-constexpr uint32_t kLookupChunk = 128u * 1024u;
+// fit one workgroup's LDS in the unpermute kernel and positions fit 16 bits.
+constexpr uint32_t kLookupChunk = 65536u;
 
 __device__ __forceinline__ uint32_t slice_of(uint64_t h, uint32_t num_blocks, uint32_t slice_shift) {
   return block_of((uint32_t)(h >> 32), num_blocks) >> slice_shift;
 }
 
-// Exclusive prefix sum of in[0..count) into out[0..count) by the whole
-// workgroup (blockDim.x a multiple of 64, at most 1024). `wsum` holds 16
-// words of LDS scratch. Contains barriers: every thread must call it.
-__device__ void block_exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t count, uint32_t *wsum) {
-  const uint32_t per = (count + blockDim.x - 1) / blockDim.x;
-  const uint32_t b = threadIdx.x * per;
-  const uint32_t e = min(b + per, count);
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// and stores stay in flight across it (no global data is shared between the
+// threads of a partition workgroup).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts
+// (Hillis-Steele inside each row of 16 lanes) and the two row broadcasts.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+  return x;
+}
+
+// Exclusive prefix over a workgroup of T threads (a multiple of 64, at most
+// 1024), thread t holding the R consecutive entries t*R .. t*R+R-1 in c[]:
+// returns the sum of all entries before its first. `wsum` is 16 words of LDS;
+// contains one barrier, and wsum may be rewritten only after a further
+// barrier.
+template <int R, uint32_t T = kPartThreads>
+__device__ __forceinline__ uint32_t block_scan_owned(const uint32_t (&c)[R], uint32_t *wsum) {
   uint32_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += in[i];
-  const uint32_t lane = threadIdx.x & 63u;
-  uint32_t x = sum;  // inclusive scan over the wave
-  for (uint32_t d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wsum[threadIdx.x >> 6] = x;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const uint32_t nw = blockDim.x >> 6;
-    const uint32_t v = threadIdx.x < nw ? wsum[threadIdx.x] : 0u;
-    uint32_t z = v;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(z, d, 64);
-      if (lane >= d) z += y;
-    }
-    if (threadIdx.x < nw) wsum[threadIdx.x] = z - v;  // exclusive over waves
-  }
-  __syncthreads();
-  uint32_t run = wsum[threadIdx.x >> 6] + x - sum;
-  for (uint32_t i = b; i < e; ++i) {
-    out[i] = run;
-    run += in[i];
-  }
-  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) sum += c[r];
+  const uint32_t incl = wave_inclusive_scan(sum);
+  const uint32_t wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 63u) wsum[wave] = incl;
+  lds_barrier();
+  uint32_t before = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < T / 64u; ++w) before += w < wave ? wsum[w] : 0u;
+  return before + incl - sum;
 }
 
 __device__ __forceinline__ void chunk_range(uint32_t g, uint32_t chunk, uint32_t n, uint32_t *b, uint32_t *e) {
@@ -108,259 +117,436 @@ part_count_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chun
   for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) row[i] = hist[i];
 }
 
-// Column prefix sums of hist[groups][num_slices]. A workgroup handles 64
-// columns with 16 threads per column, each summing a contiguous run of rows.
+// Column prefix sums of hist[groups][num_slices], two kernels over a grid of
+// (column blocks of 64) x (row blocks of 256). In both, thread (seg, c) of a
+// workgroup handles column c over the 16 rows of segment seg.
+__device__ __forceinline__ uint32_t segment_sum(const uint32_t *__restrict__ hist, uint32_t groups,
+                                                uint32_t num_slices, uint32_t r0, uint32_t col) {
+  uint32_t v[16];
+#pragma unroll
+  for (uint32_t k = 0; k < 16u; ++k) {
+    const uint32_t r = r0 + k;
+    v[k] = (r < groups && col < num_slices) ? hist[(uint64_t)r * num_slices + col] : 0u;
+  }
+  uint32_t s = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 16u; ++k) s += v[k];
+  return s;
+}
+
+// blocksum[rb][col] = sum of hist over the 256 rows of row block rb.
 __global__ void __launch_bounds__(kPartThreads)
-part_colscan_kernel(const uint32_t *__restrict__ hist, uint32_t groups, uint32_t num_slices,
-                    uint32_t *__restrict__ start, uint32_t *__restrict__ tot) {
-  __shared__ uint32_t seg_sum[kPartThreads / kColsPerScanBlock][kColsPerScanBlock];
-  constexpr uint32_t kSegs = kPartThreads / kColsPerScanBlock;
-  const uint32_t c = threadIdx.x % kColsPerScanBlock;
-  const uint32_t seg = threadIdx.x / kColsPerScanBlock;
-  const uint32_t col = blockIdx.x * kColsPerScanBlock + c;
-  const uint32_t rows = (groups + kSegs - 1) / kSegs;
-  const uint32_t r0 = min(seg * rows, groups);
-  const uint32_t r1 = min(r0 + rows, groups);
-  uint32_t sum = 0;
-  if (col < num_slices)
-    for (uint32_t r = r0; r < r1; ++r) sum += hist[(uint64_t)r * num_slices + col];
-  seg_sum[seg][c] = sum;
+part_colsum_kernel(const uint32_t *__restrict__ hist, uint32_t groups, uint32_t num_slices,
+                   uint32_t *__restrict__ blocksum) {
+  __shared__ uint32_t seg_sum[16][kScanCols];
+  const uint32_t c = threadIdx.x % kScanCols, seg = threadIdx.x / kScanCols;
+  const uint32_t col = blockIdx.x * kScanCols + c;
+  seg_sum[seg][c] = segment_sum(hist, groups, num_slices, blockIdx.y * kScanRows + seg * 16u, col);
   __syncthreads();
-  uint32_t run = 0;
-  for (uint32_t k = 0; k < seg; ++k) run += seg_sum[k][c];
-  if (col < num_slices) {
-    for (uint32_t r = r0; r < r1; ++r) {
-      start[(uint64_t)r * num_slices + col] = run;
-      run += hist[(uint64_t)r * num_slices + col];
-    }
-    if (seg == kSegs - 1) tot[col] = run;
+  if (seg == 0 && col < num_slices) {
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 16u; ++k) s += seg_sum[k][c];
+    blocksum[(uint64_t)blockIdx.y * num_slices + col] = s;
   }
 }
 
-// One workgroup: offsets[s] = sum of tot[< s]; offsets[num_slices] = total.
+// start[r][col] = sum of hist[< r][col]; the last row block also writes tot.
+__global__ void __launch_bounds__(kPartThreads)
+part_colscan_kernel(const uint32_t *__restrict__ hist, uint32_t groups, uint32_t num_slices,
+                    const uint32_t *__restrict__ blocksum, uint32_t *__restrict__ start,
+                    uint32_t *__restrict__ tot) {
+  __shared__ uint32_t seg_sum[16][kScanCols];
+  __shared__ uint32_t carry[kScanCols];
+  const uint32_t c = threadIdx.x % kScanCols, seg = threadIdx.x / kScanCols;
+  const uint32_t col = blockIdx.x * kScanCols + c;
+  const uint32_t r0 = blockIdx.y * kScanRows + seg * 16u;
+  seg_sum[seg][c] = segment_sum(hist, groups, num_slices, r0, col);
+  if (seg == 0) {
+    uint32_t s = 0;
+    if (col < num_slices)
+      for (uint32_t rb = 0; rb < blockIdx.y; ++rb) s += blocksum[(uint64_t)rb * num_slices + col];
+    carry[c] = s;
+  }
+  __syncthreads();
+  uint32_t run = carry[c];
+  for (uint32_t k = 0; k < seg; ++k) run += seg_sum[k][c];
+  if (col >= num_slices) return;
+#pragma unroll
+  for (uint32_t k = 0; k < 16u; ++k) {
+    const uint32_t r = r0 + k;
+    if (r < groups) {
+      start[(uint64_t)r * num_slices + col] = run;
+      run += hist[(uint64_t)r * num_slices + col];
+    }
+  }
+  if (blockIdx.y == gridDim.y - 1u && seg == 15u) tot[col] = run;
+}
+
+// One workgroup: offsets[s] = sum of round4(tot[< s]); offsets[num_slices] is
+// the padded total. Thread t owns slices 4t .. 4t+3 (num_slices <= 4096).
 __global__ void __launch_bounds__(kPartThreads)
 part_offsets_kernel(const uint32_t *__restrict__ tot, uint32_t num_slices, uint32_t *__restrict__ offsets) {
   __shared__ uint32_t wsum[16];
-  // block_exclusive_scan reads `in` from any memory; offsets[] is the output.
-  block_exclusive_scan(tot, offsets, num_slices, wsum);
-  if (threadIdx.x == 0) offsets[num_slices] = offsets[num_slices - 1] + tot[num_slices - 1];
+  uint32_t c[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t s = threadIdx.x * 4u + r;
+    c[r] = s < num_slices ? (tot[s] + 3u) & ~3u : 0u;
+  }
+  uint32_t run = block_scan_owned<4>(c, wsum);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t s = threadIdx.x * 4u + r;
+    if (s < num_slices) offsets[s] = run;
+    run += c[r];
+    if (s + 1u == num_slices) offsets[num_slices] = run;
+  }
 }
 
-constexpr size_t scatter_lds_bytes(uint32_t num_slices) {
-  return (size_t)kTile * 8u + (size_t)kTile * 2u + (size_t)num_slices * 16u + 64u;
+constexpr size_t scatter_lds_bytes(uint32_t num_slices, bool with_pos) {
+  return (size_t)kTile * 8u + (size_t)num_slices * 4u * (with_pos ? 4u : 3u) + 64u;
+}
+
+// LDS of one scatter workgroup.
+struct ScatterLds {
+  uint64_t *stage;  // [kTile] keys of the tile, sorted by slice
+  uint32_t *hist;   // [P] keys per slice in the tile (ranks come from it)
+  uint32_t *loff;   // [P] where slice s starts in the sorted tile
+  uint32_t *delta;  // [P] global index of sorted position k is k + delta[s]
+  uint32_t *pdelta; // [P] (lookups) chunk result position of sorted position k is k + pdelta[s]
+  uint32_t *wsum;   // [16]
+};
+
+// Hashes of tile t0 for this thread: index t0 + t * kScatterThreads + thread,
+// clamped to the chunk's last key so loads never branch.
+__device__ __forceinline__ void load_tile(const uint64_t *__restrict__ hashes, uint32_t t0, uint32_t e,
+                                          uint64_t (&h)[kScatterPer]) {
+#pragma unroll
+  for (uint32_t t = 0; t < kScatterPer; ++t) {
+    const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
+    h[t] = load_hash<0>(hashes + (i < e ? i : e - 1u));
+  }
+}
+
+// One tile of the scatter: rank every key within its slice (LDS atomics),
+// scan the slice counts, stage the keys sorted by slice, write the runs. The
+// thread owning slices own .. own+R-1 keeps their cursors in registers.
+// kFull: the whole tile is inside the chunk (no per-key guards).
+template <bool kWithPos, int R, bool kFull>
+__device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
+                                             uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices,
+                                             const ScatterLds &L, uint32_t (&cursor)[R], uint32_t (&pbase)[R],
+                                             uint64_t *__restrict__ out_keys, uint16_t *__restrict__ out_pos) {
+  uint32_t s[kScatterPer], rank[kScatterPer];
+#pragma unroll
+  for (uint32_t t = 0; t < kScatterPer; ++t) {
+    const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
+    s[t] = slice_of(h[t], num_blocks, slice_shift);
+    rank[t] = __hip_atomic_fetch_add(L.hist + s[t], (kFull || i < e) ? 1u : 0u, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  lds_barrier();
+  const uint32_t own = threadIdx.x * R;
+  uint32_t c[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t sl = own + r;
+    c[r] = sl < num_slices ? L.hist[sl] : 0u;
+    if (sl < num_slices) L.hist[sl] = 0u;  // ready for the next tile (ranked after two more barriers)
+  }
+  uint32_t run = block_scan_owned<R, kScatterThreads>(c, L.wsum);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t sl = own + r;
+    if (sl < num_slices) {
+      L.loff[sl] = run;
+      L.delta[sl] = cursor[r] - run;
+      if constexpr (kWithPos) L.pdelta[sl] = pbase[r] - run;
+    }
+    cursor[r] += c[r];
+    if constexpr (kWithPos) pbase[r] += c[r];
+    run += c[r];
+  }
+  lds_barrier();
+#pragma unroll
+  for (uint32_t t = 0; t < kScatterPer; ++t) {
+    const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
+    if (kFull || i < e) {
+      const uint32_t k = L.loff[s[t]] + rank[t];
+      L.stage[k] = h[t];
+      if constexpr (kWithPos) out_pos[i] = (uint16_t)(k + L.pdelta[s[t]]);
+    }
+  }
+  lds_barrier();
+  const uint32_t count = kFull ? kTile : min(kTile, e - t0);
+#pragma unroll
+  for (uint32_t t = 0; t < kScatterPer; ++t) {
+    const uint32_t k = t * kScatterThreads + threadIdx.x;
+    if (kFull || k < count) {
+      const uint64_t key = L.stage[k];
+      out_keys[k + L.delta[slice_of(key, num_blocks, slice_shift)]] = key;
+    }
+  }
+  // The next tile's first barrier orders these reads of stage and delta
+  // before they are rewritten.
 }
 
 // Workgroup g partitions chunk g. For lookups it also writes, for every key i
-// of the chunk, its position inside the chunk's own results (the chunk's runs
-// of all slices laid end to end in slice order), which is what the unpermute
-// kernel reads back from LDS.
-template <bool kWithPos>
+// of the chunk, the 16-bit position of its result inside the chunk's own
+// results (the chunk's runs of all slices laid end to end in slice order),
+// which is what the unpermute kernel reads back from LDS.
+template <bool kWithPos, int R>
 __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t num_blocks,
                     uint32_t slice_shift, uint32_t num_slices, const uint32_t *__restrict__ offsets,
                     const uint32_t *__restrict__ start, const uint32_t *__restrict__ hist_rows,
-                    uint64_t *__restrict__ out_keys, uint32_t *__restrict__ out_pos) {
+                    uint64_t *__restrict__ out_keys, uint16_t *__restrict__ out_pos) {
   extern __shared__ unsigned long long smem[];
-  unsigned long long *stage_keys = smem;                                    // [kTile]
-  uint16_t *stage_slice = reinterpret_cast<uint16_t *>(stage_keys + kTile);  // [kTile]
-  uint32_t *cursor = reinterpret_cast<uint32_t *>(stage_slice + kTile);      // [num_slices]
-  uint32_t *hist = cursor + num_slices;                                      // [num_slices]
-  uint32_t *loff = hist + num_slices;                                        // [num_slices]
-  uint32_t *local = loff + num_slices;                                       // [num_slices] (lookups)
-  uint32_t *wsum = local + num_slices;                                       // [16]
+  ScatterLds L;
+  L.stage = reinterpret_cast<uint64_t *>(smem);
+  L.hist = reinterpret_cast<uint32_t *>(L.stage + kTile);
+  L.loff = L.hist + num_slices;
+  L.delta = L.loff + num_slices;
+  L.pdelta = L.delta + num_slices;
+  L.wsum = kWithPos ? L.pdelta + num_slices : L.pdelta;
 
-  const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
-  for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) cursor[i] = offsets[i] + my_start[i];
-  if constexpr (kWithPos) {
-    // local[s]: where slice s's run starts among this chunk's results; then
-    // turned into local[s] - (first cursor of s), so that a key's position in
-    // the chunk's results is local[s] + cursor[s] + rank.
-    block_exclusive_scan(hist_rows + (uint64_t)blockIdx.x * num_slices, local, num_slices, wsum);
-    for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) local[i] -= cursor[i];
-  }
   uint32_t b, e;
   chunk_range(blockIdx.x, chunk, n, &b, &e);
-  // Indices past the chunk are clamped to its last key so loads never branch;
-  // such lanes add 0 to the histogram and write nothing.
-  uint64_t h[kScatterPerThread];
+  if (b >= e) return;  // whole workgroup
+
+  const uint32_t own = threadIdx.x * R;
+  const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
+  const uint32_t *my_hist = hist_rows + (uint64_t)blockIdx.x * num_slices;
+  uint32_t cursor[R], pbase[R], c[R];
 #pragma unroll
-  for (uint32_t t = 0; t < kScatterPerThread; ++t) {
-    const uint32_t i = b + t * blockDim.x + threadIdx.x;
-    h[t] = load_hash<0>(hashes + (i < e ? i : e - 1u));
+  for (int r = 0; r < R; ++r) {
+    const uint32_t sl = own + r;
+    cursor[r] = sl < num_slices ? offsets[sl] + my_start[sl] : 0u;
+    c[r] = sl < num_slices ? my_hist[sl] : 0u;
+    if (sl < num_slices) L.hist[sl] = 0u;
   }
-  for (uint32_t tile0 = b; tile0 < e; tile0 += kTile) {
-    for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
-    uint32_t s[kScatterPerThread], rank[kScatterPerThread];
+  if constexpr (kWithPos) {
+    uint32_t run = block_scan_owned<R, kScatterThreads>(c, L.wsum);
 #pragma unroll
-    for (uint32_t t = 0; t < kScatterPerThread; ++t) {
-      const uint32_t i = tile0 + t * blockDim.x + threadIdx.x;
-      s[t] = slice_of(h[t], num_blocks, slice_shift);
-      rank[t] = __hip_atomic_fetch_add(hist + s[t], i < e ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int r = 0; r < R; ++r) {
+      pbase[r] = run;
+      run += c[r];
     }
-    // Load the next tile now, so the loads overlap the scan, staging and writes.
-    uint64_t next[kScatterPerThread];
-#pragma unroll
-    for (uint32_t t = 0; t < kScatterPerThread; ++t) {
-      const uint32_t i = tile0 + kTile + t * blockDim.x + threadIdx.x;
-      next[t] = load_hash<0>(hashes + (i < e ? i : e - 1u));
-    }
-    __syncthreads();
-    block_exclusive_scan(hist, loff, num_slices, wsum);
-#pragma unroll
-    for (uint32_t t = 0; t < kScatterPerThread; ++t) {
-      const uint32_t i = tile0 + t * blockDim.x + threadIdx.x;
-      if (i < e) {
-        const uint32_t k = loff[s[t]] + rank[t];
-        stage_keys[k] = h[t];
-        stage_slice[k] = (uint16_t)s[t];
-        if constexpr (kWithPos) out_pos[i] = local[s[t]] + cursor[s[t]] + rank[t];
-      }
-    }
-    __syncthreads();
-    const uint32_t count = min(kTile, e - tile0);
-    uint32_t sl[kScatterPerThread];
-    unsigned long long key[kScatterPerThread];
-#pragma unroll
-    for (uint32_t t = 0; t < kScatterPerThread; ++t) {
-      const uint32_t k = t * blockDim.x + threadIdx.x;
-      sl[t] = k < count ? stage_slice[k] : 0u;
-      key[t] = stage_keys[k];
-    }
-#pragma unroll
-    for (uint32_t t = 0; t < kScatterPerThread; ++t) {
-      const uint32_t k = t * blockDim.x + threadIdx.x;
-      const uint32_t dst = cursor[sl[t]] + (k - loff[sl[t]]);
-      if (k < count) out_keys[dst] = key[t];
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) cursor[i] += hist[i];
-    // (the barrier at the top of the next tile orders these updates)
-#pragma unroll
-    for (uint32_t t = 0; t < kScatterPerThread; ++t) h[t] = next[t];
+  }
+  lds_barrier();
+
+  // Tiles alternate between two register sets so the next tile's loads are
+  // issued before this tile's stores and need no register copies.
+  const uint32_t nfull = (e - b) / kTile;
+  uint64_t ha[kScatterPer], hb[kScatterPer];
+  load_tile(hashes, b, e, ha);
+  uint32_t t0 = b, k = 0;
+  for (; k + 2u <= nfull; k += 2u) {
+    load_tile(hashes, t0 + kTile, e, hb);
+    scatter_tile<kWithPos, R, true>(ha, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
+                                    out_pos);
+    t0 += kTile;
+    load_tile(hashes, t0 + kTile, e, ha);
+    scatter_tile<kWithPos, R, true>(hb, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
+                                    out_pos);
+    t0 += kTile;
+  }
+  if (k < nfull) {
+    load_tile(hashes, t0 + kTile, e, hb);
+    scatter_tile<kWithPos, R, true>(ha, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
+                                    out_pos);
+    t0 += kTile;
+    if (t0 < e)
+      scatter_tile<kWithPos, R, false>(hb, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
+                                       out_pos);
+  } else if (t0 < e) {
+    scatter_tile<kWithPos, R, false>(ha, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
+                                     out_pos);
   }
 }
 
 __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *words, uint32_t b0, uint32_t nb) {
   const uint4 *src4 = reinterpret_cast<const uint4 *>(words + (uint64_t)b0 * 8u);
-  for (uint32_t i = threadIdx.x; i < nb * 2u; i += blockDim.x) lds4[i] = src4[i];
+  for (uint32_t i = threadIdx.x; i < nb * 2u; i += kPartThreads) lds4[i] = src4[i];
 }
 
-// Slice kernels use four lanes per key: lane l owns words 2q and 2q+1
-// (q = l % 4) of the block as one 64-bit LDS word. In pass p (0..3) the four
-// lanes of group g (lanes 4g..4g+3) take key 4g + p of a 64-key chunk and
-// load its hash directly (the four lanes read the same address), so a chunk
-// needs four loads and four 64-bit LDS operations per lane. Lanes past the
-// slice's last key load that last key instead (a real key of the slice, so
-// every LDS index stays in range); inserting it again changes nothing, and
-// lookup results of those lanes are not written. This keeps the loops free of
-// branches so all loads, then all LDS accesses, are issued back to back.
-template <int U>
-__device__ __forceinline__ void load_pass_hashes(const uint64_t *__restrict__ keys, uint32_t n, uint32_t base,
-                                                 uint32_t group4, uint64_t (&h)[U][4]) {
+// Slice kernels: one lane per key, four keys per lane per step. Slice s's
+// keys start 32-byte aligned (offsets are multiples of four keys), so a lane
+// reads its four hashes with two 16-byte loads. Wave w takes steps of 256
+// keys; lane l of a step takes keys 4l .. 4l+3. A lane whose group starts
+// past the slice's last key reads the last group instead (in bounds: the
+// padded run ends at a multiple of four keys), and keys at or past the
+// slice's count are masked: inserts OR a zero mask; lookups write a group's
+// result word in place when the group starts inside the slice and to a spare
+// word past the last run otherwise. Padding hashes
+// are arbitrary, so block indices are clamped into the slice before any LDS
+// access.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
+// Index of this wave in its workgroup, as a wave-uniform (scalar) value so
+// that loops over it compile to scalar branches.
+__device__ __forceinline__ uint32_t wave_index() {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
+// Hashes of one loop step for this lane: kSliceSteps groups of four keys
+// (steps of 256 keys), each group index clamped to the slice's last group.
+struct SliceStep {
+  uint64_t h[kSliceSteps][4];
+};
+
+__device__ __forceinline__ void load_step(const uint64_t *__restrict__ keys, uint32_t base, uint32_t last,
+                                          SliceStep &s) {
+  const uint32_t lane = lane_id();
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
+  for (uint32_t u = 0; u < kSliceSteps; ++u) {
+    const u64x2 *p = reinterpret_cast<const u64x2 *>(keys + min(base + 256u * u + 4u * lane, last));
+    const u64x2 a = __builtin_nontemporal_load(p);
+    const u64x2 b = __builtin_nontemporal_load(p + 1);
+    s.h[u][0] = a.x;
+    s.h[u][1] = a.y;
+    s.h[u][2] = b.x;
+    s.h[u][3] = b.y;
+  }
+}
+
+// OR the masks of one step's keys into the slice in LDS.
+__device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, uint32_t ns, uint32_t num_blocks,
+                                            uint32_t b0, uint32_t nb, unsigned long long *lds2) {
+  const uint32_t lane = lane_id();
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const uint32_t i = base + 64u * u + group4 + p;
-      h[u][p] = load_hash<0>(keys + (i < n ? i : n - 1u));
+  for (uint32_t u = 0; u < kSliceSteps; ++u) {
+    const uint32_t at = base + 256u * u + 4u * lane;
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+      const uint64_t h = s.h[u][k];
+      const uint32_t x = (uint32_t)h;
+      const uint32_t bl = min(block_of((uint32_t)(h >> 32), num_blocks) - b0, nb - 1u);
+      const uint32_t one = at + k < ns ? 1u : 0u;
+      unsigned long long *blk = lds2 + (uint64_t)bl * 4u;
+      __hip_atomic_fetch_or(blk + 0, (unsigned long long)(one << bit_of(kSeed0, x)) |
+                                         ((unsigned long long)(one << bit_of(kSeed1, x)) << 32),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_or(blk + 1, (unsigned long long)(one << bit_of(kSeed2, x)) |
+                                         ((unsigned long long)(one << bit_of(kSeed3, x)) << 32),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_or(blk + 2, (unsigned long long)(one << bit_of(kSeed4, x)) |
+                                         ((unsigned long long)(one << bit_of(kSeed5, x)) << 32),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_or(blk + 3, (unsigned long long)(one << bit_of(kSeed6, x)) |
+                                         ((unsigned long long)(one << bit_of(kSeed7, x)) << 32),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
 
-template <int U>
+// Test one step's keys against the slice in LDS and write one result word
+// (four result bytes) per group.
+__device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, uint32_t ns, uint32_t num_blocks,
+                                            uint32_t b0, uint32_t nb, const uint4 *lds4, uint32_t begin,
+                                            uint32_t spare, uint32_t *__restrict__ res4) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t u = 0; u < kSliceSteps; ++u) {
+    const uint32_t at = base + 256u * u + 4u * lane;
+    uint4 w[4][2];
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+      const uint32_t bl = min(block_of((uint32_t)(s.h[u][k] >> 32), num_blocks) - b0, nb - 1u);
+      w[k][0] = lds4[2u * bl];
+      w[k][1] = lds4[2u * bl + 1u];
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+      const uint32_t x = (uint32_t)s.h[u][k];
+      const uint32_t t = (w[k][0].x >> bit_of(kSeed0, x)) & (w[k][0].y >> bit_of(kSeed1, x)) &
+                         (w[k][0].z >> bit_of(kSeed2, x)) & (w[k][0].w >> bit_of(kSeed3, x)) &
+                         (w[k][1].x >> bit_of(kSeed4, x)) & (w[k][1].y >> bit_of(kSeed5, x)) &
+                         (w[k][1].z >> bit_of(kSeed6, x)) & (w[k][1].w >> bit_of(kSeed7, x)) & 1u;
+      r |= t << (8u * k);
+    }
+    res4[at < ns ? (begin + at) / 4u : spare] = r;
+  }
+}
+
+// Steps alternate between two register sets, so the next step's hashes are
+// in flight while this step is processed and need no register copies. Both
+// halves of an iteration always run (a step past the slice's keys is all
+// masked), so there is no branch the compiler could sink the prefetch into;
+// the scheduling barriers keep it above the step. Loads past the slice are
+// clamped, so the prefetch never leaves it.
+#define SBBF_SLICE_LOOP(STEP)                                               \
+  do {                                                                      \
+    constexpr uint32_t stride = waves * 256u * kSliceSteps;                 \
+    uint32_t base = wave_index() * 256u * kSliceSteps;                      \
+    const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u; \
+    SliceStep sa, sb;                                                       \
+    load_step(keys, base, last, sa);                                        \
+    for (uint32_t it = 0; it < steps; it += 2u) {                           \
+      load_step(keys, base + stride, last, sb);                             \
+      __builtin_amdgcn_sched_barrier(0);                                    \
+      STEP(sa, base);                                                       \
+      base += stride;                                                       \
+      load_step(keys, base + stride, last, sa);                             \
+      __builtin_amdgcn_sched_barrier(0);                                    \
+      STEP(sb, base);                                                       \
+      base += stride;                                                       \
+    }                                                                       \
+  } while (0)
+
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
-                         uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift) {
+                         const uint32_t *__restrict__ tot, uint32_t *__restrict__ words, uint32_t num_blocks,
+                         uint32_t slice_shift) {
   extern __shared__ uint4 lds4[];
   unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
   const uint32_t slice = blockIdx.x;
+  const uint32_t ns = tot[slice];
+  if (ns == 0) return;  // whole workgroup: the slice is unchanged
   const uint32_t b0 = slice << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
   load_slice_to_lds(lds4, words, b0, nb);
   __syncthreads();
 
-  const uint32_t begin = offsets[slice];
-  const uint32_t n = offsets[slice + 1] - begin;
-  const uint64_t *keys = part + begin;
-  const uint32_t lane = lane_id();
-  const uint32_t q = lane & 3u;
-  const uint32_t group4 = lane & ~3u;
-  const uint32_t seed_lo = seed_of_word(2u * q);
-  const uint32_t seed_hi = seed_of_word(2u * q + 1u);
-  const uint32_t waves = blockDim.x / kWave;
-  constexpr uint32_t kChunk = 64u * U;
-  for (uint32_t base = (threadIdx.x / kWave) * kChunk; base < n; base += waves * kChunk) {
-    uint64_t h[U][4];
-    load_pass_hashes<U>(keys, n, base, group4, h);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const uint32_t b = block_of((uint32_t)(h[u][p] >> 32), num_blocks) - b0;
-        const uint32_t x = (uint32_t)h[u][p];
-        const unsigned long long m = (unsigned long long)(1u << bit_of(seed_lo, x)) |
-                                     ((unsigned long long)(1u << bit_of(seed_hi, x)) << 32);
-        __hip_atomic_fetch_or(lds2 + b * 4u + q, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-    }
-  }
+  const uint64_t *keys = part + offsets[slice];
+  const uint32_t last = ((ns + 3u) & ~3u) - 4u;
+  constexpr uint32_t waves = kPartThreads / kWave;
+#define SBBF_INSERT_STEP(S, BASE) insert_step(S, BASE, ns, num_blocks, b0, nb, lds2)
+  SBBF_SLICE_LOOP(SBBF_INSERT_STEP);
+#undef SBBF_INSERT_STEP
   __syncthreads();
   uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * 8u);
-  for (uint32_t i = threadIdx.x; i < nb * 2u; i += blockDim.x) dst4[i] = lds4[i];
+  for (uint32_t i = threadIdx.x; i < nb * 2u; i += kPartThreads) dst4[i] = lds4[i];
 }
 
-template <int U>
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
-                         const uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift,
-                         uint8_t *__restrict__ res) {
+                         const uint32_t *__restrict__ tot, const uint32_t *__restrict__ words, uint32_t num_blocks,
+                         uint32_t slice_shift, uint8_t *__restrict__ res) {
   extern __shared__ uint4 lds4[];
-  const unsigned long long *lds2 = reinterpret_cast<const unsigned long long *>(lds4);
   const uint32_t slice = blockIdx.x;
+  const uint32_t ns = tot[slice];
+  if (ns == 0) return;  // whole workgroup
   const uint32_t b0 = slice << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
   load_slice_to_lds(lds4, words, b0, nb);
   __syncthreads();
 
   const uint32_t begin = offsets[slice];
-  const uint32_t n = offsets[slice + 1] - begin;
   const uint64_t *keys = part + begin;
-  uint8_t *out = res + begin;
-  const uint32_t lane = lane_id();
-  const uint32_t q = lane & 3u;
-  const uint32_t group4 = lane & ~3u;
-  const uint32_t seed_lo = seed_of_word(2u * q);
-  const uint32_t seed_hi = seed_of_word(2u * q + 1u);
-  const uint32_t waves = blockDim.x / kWave;
-  constexpr uint32_t kChunk = 64u * U;
-  for (uint32_t base = (threadIdx.x / kWave) * kChunk; base < n; base += waves * kChunk) {
-    uint64_t h[U][4];
-    load_pass_hashes<U>(keys, n, base, group4, h);
-    unsigned long long w[U][4];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int p = 0; p < 4; ++p) w[u][p] = lds2[(block_of((uint32_t)(h[u][p] >> 32), num_blocks) - b0) * 4u + q];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      uint64_t r = 0;
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const uint32_t x = (uint32_t)h[u][p];
-        const uint32_t hit = (uint32_t)(w[u][p] >> bit_of(seed_lo, x)) & (uint32_t)(w[u][p] >> (32u + bit_of(seed_hi, x))) & 1u;
-        // Byte g of ballot p holds (in its bits 4g..4g+3) the four tests of key 4g + p.
-        const uint64_t m = ballot(hit != 0u);
-        uint64_t t = m & (m >> 2);
-        t &= t >> 1;
-        r |= (t & 0x1111111111111111ull) << p;
-      }
-      const uint32_t i = base + 64u * u + lane;
-      if (i < n) out[i] = (uint8_t)((r >> lane) & 1u);
-    }
-  }
+  uint32_t *res4 = reinterpret_cast<uint32_t *>(res);  // begin and the padded total are multiples of 4
+  // Lanes whose group starts past the slice write their word to the spare
+  // word after the last slice's run (never read), so stores need no branch.
+  const uint32_t spare = offsets[gridDim.x] / 4u;
+  const uint32_t last = ((ns + 3u) & ~3u) - 4u;
+  constexpr uint32_t waves = kPartThreads / kWave;
+#define SBBF_LOOKUP_STEP(S, BASE) lookup_step(S, BASE, ns, num_blocks, b0, nb, lds4, begin, spare, res4)
+  SBBF_SLICE_LOOP(SBBF_LOOKUP_STEP);
+#undef SBBF_LOOKUP_STEP
 }
+#undef SBBF_SLICE_LOOP
 
 // Workgroup g restores input order for chunk g: it copies the chunk's result
 // run of every slice (res[offsets[s] + start[g][s] ...], hist[g][s] bytes)
@@ -368,7 +554,7 @@ part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
 // the chunk, as bytes or packed bits (LSB-first).
 template <bool kBits>
 __global__ void __launch_bounds__(kPartThreads)
-part_unpermute_kernel(const uint32_t *__restrict__ pos, const uint8_t *__restrict__ res,
+part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint8_t *__restrict__ res,
                       const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
                       const uint32_t *__restrict__ hist_rows, uint32_t num_slices, uint32_t n, uint32_t chunk,
                       uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
@@ -378,7 +564,23 @@ part_unpermute_kernel(const uint32_t *__restrict__ pos, const uint8_t *__restric
   uint8_t *vals = reinterpret_cast<uint8_t *>(wsum + 16);  // [chunk]
   const uint32_t *row = hist_rows + (uint64_t)blockIdx.x * num_slices;
   const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
-  block_exclusive_scan(row, local, num_slices, wsum);
+  {
+    // local[s]: where slice s's run starts among the chunk's results.
+    uint32_t c[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t s = threadIdx.x * 4u + r;
+      c[r] = s < num_slices ? row[s] : 0u;
+    }
+    uint32_t run = block_scan_owned<4>(c, wsum);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t s = threadIdx.x * 4u + r;
+      if (s < num_slices) local[s] = run;
+      run += c[r];
+    }
+  }
+  __syncthreads();
   // Phase 1: thread t copies the runs of slices t, t + blockDim.x, ... with
   // aligned 4-byte loads (res has at least 4 bytes of padding after its last
   // byte, so the last word of a run is always inside the workspace).
@@ -411,9 +613,9 @@ part_unpermute_kernel(const uint32_t *__restrict__ pos, const uint8_t *__restric
     const bool aligned4 = ((uintptr_t)out8 & 3u) == 0;
     for (uint32_t i = b + 4u * threadIdx.x; i < e; i += 4u * blockDim.x) {
       if (i + 4u <= e) {
-        const uint4 p4 = *reinterpret_cast<const uint4 *>(pos + i);
-        const uint32_t word = (uint32_t)vals[p4.x] | ((uint32_t)vals[p4.y] << 8) | ((uint32_t)vals[p4.z] << 16) |
-                              ((uint32_t)vals[p4.w] << 24);
+        const uint2 p2 = *reinterpret_cast<const uint2 *>(pos + i);
+        const uint32_t word = (uint32_t)vals[p2.x & 0xffffu] | ((uint32_t)vals[p2.x >> 16] << 8) |
+                              ((uint32_t)vals[p2.y & 0xffffu] << 16) | ((uint32_t)vals[p2.y >> 16] << 24);
         if (aligned4) {
           *reinterpret_cast<uint32_t *>(out8 + i) = word;
         } else {
@@ -437,36 +639,43 @@ part_unpermute_kernel(const uint32_t *__restrict__ pos, const uint8_t *__restric
   }
 }
 
-// Workspace sections (each 256-byte aligned): hist[G][P], start[G][P], tot[P],
-// offsets[P + 1] (u32), keys[n] (u64) and, for lookups, pos[n] (u32), res[n] (u8).
+// Workspace sections (each 256-byte aligned): hist[G][P], start[G][P],
+// blocksum[RB][P], tot[P], offsets[P + 1] (u32), keys (u64) and, for
+// lookups, pos[n] (u16) and res (u8). Keys and results are laid out with
+// every slice's run padded to a multiple of four, at most n + 3P entries.
 struct PartitionLayout {
-  uint32_t *hist, *start, *tot, *offsets;
+  uint32_t *hist, *start, *blocksum, *tot, *offsets;
   uint64_t *keys;
-  uint32_t *pos;
+  uint16_t *pos;
   uint8_t *res;
   uint64_t bytes;
 };
 
+uint32_t row_blocks(uint32_t groups) { return (groups + kScanRows - 1u) / kScanRows; }
+
 PartitionLayout layout(void *workspace, uint64_t n, uint32_t num_slices, uint32_t groups, bool lookup) {
   auto up = [](uint64_t v) { return (v + 255u) & ~(uint64_t)255u; };
   char *base = static_cast<char *>(workspace);
+  const uint64_t padded = n + 3u * (uint64_t)num_slices;
   uint64_t off = 0;
   PartitionLayout L{};
   L.hist = reinterpret_cast<uint32_t *>(base + off);
   off += up((uint64_t)groups * num_slices * 4u);
   L.start = reinterpret_cast<uint32_t *>(base + off);
   off += up((uint64_t)groups * num_slices * 4u);
+  L.blocksum = reinterpret_cast<uint32_t *>(base + off);
+  off += up((uint64_t)row_blocks(groups) * num_slices * 4u);
   L.tot = reinterpret_cast<uint32_t *>(base + off);
   off += up((uint64_t)num_slices * 4u);
   L.offsets = reinterpret_cast<uint32_t *>(base + off);
   off += up(((uint64_t)num_slices + 1u) * 4u);
   L.keys = reinterpret_cast<uint64_t *>(base + off);
-  off += up(n * 8u);
+  off += up(padded * 8u);
   if (lookup) {
-    L.pos = reinterpret_cast<uint32_t *>(base + off);
-    off += up(n * 4u);
+    L.pos = reinterpret_cast<uint16_t *>(base + off);
+    off += up(n * 2u);
     L.res = reinterpret_cast<uint8_t *>(base + off);
-    off += up(n + 4u);  // 4 bytes of padding for the unpermute kernel's word loads
+    off += up(padded + 4u);  // 4 bytes of padding for the unpermute kernel's word loads
   }
   L.bytes = off;
   return L;
@@ -486,37 +695,58 @@ void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uin
   if (*groups == 0) *groups = 1;
 }
 
+template <bool kWithPos, int R>
+hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
+                          uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L, hipStream_t stream) {
+  const size_t lds = scatter_lds_bytes(num_slices, kWithPos);
+  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R>), dim3(groups), dim3(kScatterThreads), lds, stream, hashes, n,
+                     chunk, num_blocks, slice_shift, num_slices, L.offsets, L.start, L.hist, L.keys,
+                     kWithPos ? L.pos : nullptr);
+  return hipGetLastError();
+}
+
+// Slices per owning thread: the smallest power of two R with R * threads >= P.
+template <bool kWithPos>
+hipError_t launch_scatter_r(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups,
+                            uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L,
+                            hipStream_t stream) {
+  if (num_slices <= kScatterThreads)
+    return launch_scatter<kWithPos, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  if (num_slices <= 2u * kScatterThreads)
+    return launch_scatter<kWithPos, 2>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  if (num_slices <= 4u * kScatterThreads)
+    return launch_scatter<kWithPos, 4>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  return launch_scatter<kWithPos, 8>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+}
+
 hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, uint32_t slice_shift,
                      uint32_t num_slices, uint32_t chunk, uint32_t groups, const PartitionLayout &L, bool with_pos,
                      hipStream_t stream) {
   hipError_t e;
   const dim3 blk(kPartThreads);
-  const size_t sc_lds = scatter_lds_bytes(num_slices);
   // Dynamic LDS above the default needs the per-kernel limit raised; an error
   // here shows up at launch.
   (void)hipFuncSetAttribute((const void *)part_count_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(num_slices * 4u));
-  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sc_lds);
-  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sc_lds);
   (void)hipGetLastError();
   hipLaunchKernelGGL(part_count_kernel, dim3(groups), blk, num_slices * 4u, stream, hashes, n, chunk, num_blocks,
                      slice_shift, num_slices, L.hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(part_colscan_kernel, dim3((num_slices + kColsPerScanBlock - 1) / kColsPerScanBlock), blk, 0,
-                     stream, L.hist, groups, num_slices, L.start, L.tot);
+  const dim3 scan_grid((num_slices + kScanCols - 1) / kScanCols, row_blocks(groups));
+  if (scan_grid.y > 1) {  // one row block needs no carries
+    hipLaunchKernelGGL(part_colsum_kernel, scan_grid, blk, 0, stream, L.hist, groups, num_slices, L.blocksum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(part_colscan_kernel, scan_grid, blk, 0, stream, L.hist, groups, num_slices, L.blocksum, L.start,
+                     L.tot);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(part_offsets_kernel, dim3(1), blk, 0, stream, L.tot, num_slices, L.offsets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const dim3 sblk(kScatterThreads);
-  if (with_pos)
-    hipLaunchKernelGGL(part_scatter_kernel<true>, dim3(groups), sblk, sc_lds, stream, hashes, n, chunk, num_blocks,
-                       slice_shift, num_slices, L.offsets, L.start, L.hist, L.keys, L.pos);
-  else
-    hipLaunchKernelGGL(part_scatter_kernel<false>, dim3(groups), sblk, sc_lds, stream, hashes, n, chunk, num_blocks,
-                       slice_shift, num_slices, L.offsets, L.start, L.hist, L.keys, nullptr);
-  return hipGetLastError();
+  if (with_pos) return launch_scatter_r<true>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  return launch_scatter_r<false>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
 }
 
 uint32_t slices_of(uint32_t num_blocks, uint32_t slice_shift) {
@@ -525,7 +755,7 @@ uint32_t slices_of(uint32_t num_blocks, uint32_t slice_shift) {
 
 }  // namespace
 
-uint32_t partition_max_slices() { return 4096; }
+uint32_t partition_max_slices() { return 4u * kPartThreads; }
 uint64_t partition_max_keys() { return 1ull << 31; }
 
 uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup) {
@@ -546,11 +776,11 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, false, stream);
   if (e != hipSuccess) return e;
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
-  (void)hipFuncSetAttribute((const void *)part_slice_insert_kernel<kSliceUnroll>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  (void)hipFuncSetAttribute((const void *)part_slice_insert_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(part_slice_insert_kernel<kSliceUnroll>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream,
-                     L.keys, L.offsets, words, num_blocks, slice_shift);
+  hipLaunchKernelGGL(part_slice_insert_kernel, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
+                     L.offsets, L.tot, words, num_blocks, slice_shift);
   return hipGetLastError();
 }
 
@@ -566,11 +796,11 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
   hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, true, stream);
   if (e != hipSuccess) return e;
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
-  (void)hipFuncSetAttribute((const void *)part_slice_lookup_kernel<kSliceUnroll>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  (void)hipFuncSetAttribute((const void *)part_slice_lookup_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(part_slice_lookup_kernel<kSliceUnroll>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream,
-                     L.keys, L.offsets, words, num_blocks, slice_shift, L.res);
+  hipLaunchKernelGGL(part_slice_lookup_kernel, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
+                     L.offsets, L.tot, words, num_blocks, slice_shift, L.res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t u_lds = (size_t)num_slices * 4u + 64u + chunk;
   (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
