@@ -39,8 +39,10 @@ namespace sbbf {
 namespace {
 
 constexpr uint32_t kPartThreads = 1024;    // count, scan, slice and unpermute kernels
-constexpr uint32_t kScatterThreads = 1024;  // at least partition_max_slices() / 8
+constexpr uint32_t kMaxSlices = 4096;       // slices per partitioned filter
+constexpr uint32_t kScatterThreads = 1024;
 constexpr uint32_t kScatterPer = 7;        // keys per thread per scatter tile
+constexpr uint32_t kScatterGroup = 8;      // keys per aligned group written by the scatter (64 bytes)
 constexpr uint32_t kTile = kScatterThreads * kScatterPer;
 constexpr uint32_t kScanRows = 256;    // rows per colsum/colscan workgroup (16 segments of 16)
 constexpr uint32_t kScanCols = 64;     // columns per colsum/colscan workgroup
@@ -76,11 +78,12 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
 
 // Exclusive prefix over a workgroup of T threads (a multiple of 64, at most
 // 1024), thread t holding the R consecutive entries t*R .. t*R+R-1 in c[]:
-// returns the sum of all entries before its first. `wsum` is 16 words of LDS;
-// contains one barrier, and wsum may be rewritten only after a further
-// barrier.
+// returns the sum of all entries before its first (and the sum of all in
+// *total). `wsum` is 16 words of LDS; contains one barrier, and wsum may be
+// rewritten only after a further barrier.
 template <int R, uint32_t T = kPartThreads>
-__device__ __forceinline__ uint32_t block_scan_owned(const uint32_t (&c)[R], uint32_t *wsum) {
+__device__ __forceinline__ uint32_t block_scan_owned(const uint32_t (&c)[R], uint32_t *wsum,
+                                                     uint32_t *total = nullptr) {
   uint32_t sum = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) sum += c[r];
@@ -88,9 +91,14 @@ __device__ __forceinline__ uint32_t block_scan_owned(const uint32_t (&c)[R], uin
   const uint32_t wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63u) == 63u) wsum[wave] = incl;
   lds_barrier();
-  uint32_t before = 0;
+  uint32_t before = 0, all = 0;
 #pragma unroll
-  for (uint32_t w = 0; w < T / 64u; ++w) before += w < wave ? wsum[w] : 0u;
+  for (uint32_t w = 0; w < T / 64u; ++w) {
+    const uint32_t v = wsum[w];
+    before += w < wave ? v : 0u;
+    all += v;
+  }
+  if (total) *total = all;
   return before + incl - sum;
 }
 
@@ -204,17 +212,21 @@ part_offsets_kernel(const uint32_t *__restrict__ tot, uint32_t num_slices, uint3
   }
 }
 
-constexpr size_t scatter_lds_bytes(uint32_t num_slices, bool with_pos) {
-  return (size_t)kTile * 8u + (size_t)num_slices * 4u * (with_pos ? 4u : 3u) + 64u;
+// Scatter LDS for groups of L keys (L = 1: no carry). The stage holds one
+// tile's keys sorted by slice, each slice's run preceded by the keys carried
+// over from the previous tile, so its size is kTile + (L - 1) * (slices).
+constexpr uint32_t stage_keys(uint32_t L) { return kTile + (L - 1u) * kScatterThreads; }
+
+constexpr size_t scatter_lds_bytes(uint32_t num_slices, bool with_pos, uint32_t L) {
+  return (size_t)stage_keys(L) * 8u + (size_t)num_slices * (with_pos ? 20u : 16u) + 64u;
 }
 
-// LDS of one scatter workgroup.
 struct ScatterLds {
-  uint64_t *stage;  // [kTile] keys of the tile, sorted by slice
+  uint64_t *stage;  // [stage_keys(L)] keys sorted by slice
+  uint2 *info;      // [P] staged position k < info.y of slice s goes to k + info.x
   uint32_t *hist;   // [P] keys per slice in the tile (ranks come from it)
-  uint32_t *loff;   // [P] where slice s starts in the sorted tile
-  uint32_t *delta;  // [P] global index of sorted position k is k + delta[s]
-  uint32_t *pdelta; // [P] (lookups) chunk result position of sorted position k is k + pdelta[s]
+  uint32_t *sbase;  // [P] staged position of the tile's first key of slice s
+  uint32_t *pdelta; // [P] (lookups) chunk result position of staged position k is k + pdelta[s]
   uint32_t *wsum;   // [16]
 };
 
@@ -229,66 +241,99 @@ __device__ __forceinline__ void load_tile(const uint64_t *__restrict__ hashes, u
   }
 }
 
+// Per-slice state of one scatter workgroup, kept by the thread that owns the
+// slice: where the chunk's next key of the slice goes, how many of its keys
+// came before (lookups), and the keys carried over from the previous tile
+// (fewer than L, the tail of a group of L keys that is not yet complete).
+template <int R>
+struct SliceCursor {
+  uint32_t cursor[R], pbase[R], carry[R], carry_at[R];
+};
+
 // One tile of the scatter: rank every key within its slice (LDS atomics),
-// scan the slice counts, stage the keys sorted by slice, write the runs. The
-// thread owning slices own .. own+R-1 keeps their cursors in registers.
-// kFull: the whole tile is inside the chunk (no per-key guards).
-template <bool kWithPos, int R, bool kFull>
+// scan the slice counts (plus carried keys), stage the keys sorted by slice
+// behind each slice's carried keys, and write every complete, aligned group
+// of L keys with consecutive lanes; the incomplete tail of each slice's run
+// stays in the stage as the next tile's carry. kFull: the whole tile is
+// inside the chunk (no per-key guards).
+template <bool kWithPos, int R, uint32_t L, bool kFull>
 __device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
                                              uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices,
-                                             const ScatterLds &L, uint32_t (&cursor)[R], uint32_t (&pbase)[R],
-                                             uint64_t *__restrict__ out_keys, uint16_t *__restrict__ out_pos) {
+                                             const ScatterLds &S, SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
+                                             uint16_t *__restrict__ out_pos) {
+  static_assert(L == 1u || R == 1, "carried groups need one slice per thread");
+  constexpr uint32_t kCarryMax = L > 1u ? L - 1u : 1u;
   uint32_t s[kScatterPer], rank[kScatterPer];
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
     s[t] = slice_of(h[t], num_blocks, slice_shift);
-    rank[t] = __hip_atomic_fetch_add(L.hist + s[t], (kFull || i < e) ? 1u : 0u, __ATOMIC_RELAXED,
+    rank[t] = __hip_atomic_fetch_add(S.hist + s[t], (kFull || i < e) ? 1u : 0u, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   lds_barrier();
   const uint32_t own = threadIdx.x * R;
-  uint32_t c[R];
+  uint32_t c[R], m[R];
+  uint64_t carried[R][kCarryMax];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t sl = own + r;
-    c[r] = sl < num_slices ? L.hist[sl] : 0u;
-    if (sl < num_slices) L.hist[sl] = 0u;  // ready for the next tile (ranked after two more barriers)
-  }
-  uint32_t run = block_scan_owned<R, kScatterThreads>(c, L.wsum);
+    c[r] = sl < num_slices ? S.hist[sl] : 0u;
+    if (sl < num_slices) S.hist[sl] = 0u;  // ready for the next tile (ranked after two more barriers)
+    if constexpr (L > 1u) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t sl = own + r;
-    if (sl < num_slices) {
-      L.loff[sl] = run;
-      L.delta[sl] = cursor[r] - run;
-      if constexpr (kWithPos) L.pdelta[sl] = pbase[r] - run;
+      for (uint32_t j = 0; j < kCarryMax; ++j) carried[r][j] = j < C.carry[r] ? S.stage[C.carry_at[r] + j] : 0ull;
     }
-    cursor[r] += c[r];
-    if constexpr (kWithPos) pbase[r] += c[r];
-    run += c[r];
+    m[r] = C.carry[r] + c[r];
+  }
+  uint32_t total;
+  // Every thread has read its carried keys before the barrier inside the scan,
+  // so the stage can be rewritten after it.
+  uint32_t run = block_scan_owned<R, kScatterThreads>(m, S.wsum, &total);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t sl = own + r;
+    if constexpr (L > 1u) {
+#pragma unroll
+      for (uint32_t j = 0; j < kCarryMax; ++j)
+        if (j < C.carry[r]) S.stage[run + j] = carried[r][j];
+    }
+    const uint32_t first = C.cursor[r] - C.carry[r];  // global position of staged position `run`
+    const uint32_t end = C.cursor[r] + c[r];
+    const uint32_t aligned = end & ~(L - 1u);
+    const uint32_t wlen = aligned > first ? aligned - first : 0u;  // keys written by this tile
+    if (sl < num_slices) {
+      S.info[sl] = make_uint2(first - run, run + wlen);
+      S.sbase[sl] = run + C.carry[r];
+      if constexpr (kWithPos) S.pdelta[sl] = C.pbase[r] - (run + C.carry[r]);
+    }
+    C.carry[r] = m[r] - wlen;
+    C.carry_at[r] = run + wlen;
+    C.cursor[r] = end;
+    C.pbase[r] += c[r];
+    run += m[r];
   }
   lds_barrier();
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
     if (kFull || i < e) {
-      const uint32_t k = L.loff[s[t]] + rank[t];
-      L.stage[k] = h[t];
-      if constexpr (kWithPos) out_pos[i] = (uint16_t)(k + L.pdelta[s[t]]);
+      const uint32_t k = S.sbase[s[t]] + rank[t];
+      S.stage[k] = h[t];
+      if constexpr (kWithPos) out_pos[i] = (uint16_t)(k + S.pdelta[s[t]]);
     }
   }
   lds_barrier();
-  const uint32_t count = kFull ? kTile : min(kTile, e - t0);
 #pragma unroll
-  for (uint32_t t = 0; t < kScatterPer; ++t) {
+  for (uint32_t t = 0; t < kScatterPer + L - 1u; ++t) {
     const uint32_t k = t * kScatterThreads + threadIdx.x;
-    if (kFull || k < count) {
-      const uint64_t key = L.stage[k];
-      out_keys[k + L.delta[slice_of(key, num_blocks, slice_shift)]] = key;
+    if ((L == 1u && kFull) || k < total) {
+      const uint64_t key = S.stage[k];
+      const uint2 in = S.info[slice_of(key, num_blocks, slice_shift)];
+      if (L == 1u || k < in.y) out_keys[k + in.x] = key;
     }
   }
-  // The next tile's first barrier orders these reads of stage and delta
+  // The next tile's first barrier orders these reads of stage and info
   // before they are rewritten.
 }
 
@@ -296,20 +341,20 @@ __device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], u
 // of the chunk, the 16-bit position of its result inside the chunk's own
 // results (the chunk's runs of all slices laid end to end in slice order),
 // which is what the unpermute kernel reads back from LDS.
-template <bool kWithPos, int R>
+template <bool kWithPos, int R, uint32_t L>
 __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t num_blocks,
                     uint32_t slice_shift, uint32_t num_slices, const uint32_t *__restrict__ offsets,
                     const uint32_t *__restrict__ start, const uint32_t *__restrict__ hist_rows,
                     uint64_t *__restrict__ out_keys, uint16_t *__restrict__ out_pos) {
   extern __shared__ unsigned long long smem[];
-  ScatterLds L;
-  L.stage = reinterpret_cast<uint64_t *>(smem);
-  L.hist = reinterpret_cast<uint32_t *>(L.stage + kTile);
-  L.loff = L.hist + num_slices;
-  L.delta = L.loff + num_slices;
-  L.pdelta = L.delta + num_slices;
-  L.wsum = kWithPos ? L.pdelta + num_slices : L.pdelta;
+  ScatterLds S;
+  S.stage = reinterpret_cast<uint64_t *>(smem);
+  S.info = reinterpret_cast<uint2 *>(S.stage + stage_keys(L));
+  S.hist = reinterpret_cast<uint32_t *>(S.info + num_slices);
+  S.sbase = S.hist + num_slices;
+  S.pdelta = S.sbase + num_slices;
+  S.wsum = kWithPos ? S.pdelta + num_slices : S.pdelta;
 
   uint32_t b, e;
   chunk_range(blockIdx.x, chunk, n, &b, &e);
@@ -318,19 +363,23 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   const uint32_t own = threadIdx.x * R;
   const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
   const uint32_t *my_hist = hist_rows + (uint64_t)blockIdx.x * num_slices;
-  uint32_t cursor[R], pbase[R], c[R];
+  SliceCursor<R> C;
+  uint32_t c[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t sl = own + r;
-    cursor[r] = sl < num_slices ? offsets[sl] + my_start[sl] : 0u;
+    C.cursor[r] = sl < num_slices ? offsets[sl] + my_start[sl] : 0u;
+    C.carry[r] = 0u;
+    C.carry_at[r] = 0u;
+    C.pbase[r] = 0u;
     c[r] = sl < num_slices ? my_hist[sl] : 0u;
-    if (sl < num_slices) L.hist[sl] = 0u;
+    if (sl < num_slices) S.hist[sl] = 0u;
   }
   if constexpr (kWithPos) {
-    uint32_t run = block_scan_owned<R, kScatterThreads>(c, L.wsum);
+    uint32_t run = block_scan_owned<R, kScatterThreads>(c, S.wsum);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      pbase[r] = run;
+      C.pbase[r] = run;
       run += c[r];
     }
   }
@@ -344,25 +393,27 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   uint32_t t0 = b, k = 0;
   for (; k + 2u <= nfull; k += 2u) {
     load_tile(hashes, t0 + kTile, e, hb);
-    scatter_tile<kWithPos, R, true>(ha, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
-                                    out_pos);
+    scatter_tile<kWithPos, R, L, true>(ha, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
     t0 += kTile;
     load_tile(hashes, t0 + kTile, e, ha);
-    scatter_tile<kWithPos, R, true>(hb, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
-                                    out_pos);
+    scatter_tile<kWithPos, R, L, true>(hb, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
     t0 += kTile;
   }
   if (k < nfull) {
     load_tile(hashes, t0 + kTile, e, hb);
-    scatter_tile<kWithPos, R, true>(ha, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
-                                    out_pos);
+    scatter_tile<kWithPos, R, L, true>(ha, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
     t0 += kTile;
     if (t0 < e)
-      scatter_tile<kWithPos, R, false>(hb, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
-                                       out_pos);
+      scatter_tile<kWithPos, R, L, false>(hb, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
   } else if (t0 < e) {
-    scatter_tile<kWithPos, R, false>(ha, t0, e, num_blocks, slice_shift, num_slices, L, cursor, pbase, out_keys,
-                                     out_pos);
+    scatter_tile<kWithPos, R, L, false>(ha, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
+  }
+  // The last incomplete group of every slice: its keys are still in the
+  // stage (nothing rewrites it after the last tile's staging barrier).
+  if constexpr (L > 1u) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      for (uint32_t j = 0; j < C.carry[r]; ++j) out_keys[C.cursor[r] - C.carry[r] + j] = S.stage[C.carry_at[r] + j];
   }
 }
 
@@ -581,26 +632,23 @@ part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint8_t *__restric
     }
   }
   __syncthreads();
-  // Phase 1: thread t copies the runs of slices t, t + blockDim.x, ... with
-  // aligned 4-byte loads (res has at least 4 bytes of padding after its last
-  // byte, so the last word of a run is always inside the workspace).
-  for (uint32_t sl = threadIdx.x; sl < num_slices; sl += blockDim.x) {
+  // Phase 1: each group of 16 lanes copies one slice's run at a time with
+  // aligned 8-byte loads (128 bytes per pass; res has at least 8 bytes of
+  // padding after its last byte, so the last word of a run is always inside
+  // the workspace) and byte stores into LDS.
+  const uint64_t *res8 = reinterpret_cast<const uint64_t *>(res);
+  const uint32_t lane16 = threadIdx.x & 15u;
+  for (uint32_t sl = threadIdx.x >> 4; sl < num_slices; sl += kPartThreads / 16u) {
     const uint32_t len = row[sl];
     const uint32_t src = offsets[sl] + my_start[sl];  // byte index into res
     uint8_t *dst = vals + local[sl];
-    const uint32_t w_begin = src >> 2, w_end = (src + len + 3u) >> 2;
-    const uint32_t *res4 = reinterpret_cast<const uint32_t *>(res);
-    for (uint32_t w0 = w_begin; w0 < w_end; w0 += 8u) {
-      uint32_t v[8];
+    const uint32_t w_end = (src + len + 7u) >> 3;
+    for (uint32_t w = (src >> 3) + lane16; w < w_end; w += 16u) {
+      const uint64_t v = res8[w];
 #pragma unroll
-      for (uint32_t k = 0; k < 8u; ++k) v[k] = w0 + k < w_end ? res4[w0 + k] : 0u;
-#pragma unroll
-      for (uint32_t k = 0; k < 8u; ++k) {
-#pragma unroll
-        for (uint32_t by = 0; by < 4u; ++by) {
-          const uint32_t at = (w0 + k) * 4u + by;  // byte index into res
-          if (at >= src && at < src + len) dst[at - src] = (uint8_t)(v[k] >> (8u * by));
-        }
+      for (uint32_t by = 0; by < 8u; ++by) {
+        const uint32_t at = w * 8u + by;  // byte index into res
+        if (at >= src && at < src + len) dst[at - src] = (uint8_t)(v >> (8u * by));
       }
     }
   }
@@ -609,20 +657,31 @@ part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint8_t *__restric
   chunk_range(blockIdx.x, chunk, n, &b, &e);
   const uint32_t lane = threadIdx.x & 63u;
   if constexpr (!kBits) {
-    // Phase 2 (bytes): four consecutive positions per thread; b is a multiple of 4.
+    // Phase 2 (bytes): four consecutive positions per thread and step, four
+    // steps per iteration; b is a multiple of 4.
     const bool aligned4 = ((uintptr_t)out8 & 3u) == 0;
-    for (uint32_t i = b + 4u * threadIdx.x; i < e; i += 4u * blockDim.x) {
-      if (i + 4u <= e) {
-        const uint2 p2 = *reinterpret_cast<const uint2 *>(pos + i);
-        const uint32_t word = (uint32_t)vals[p2.x & 0xffffu] | ((uint32_t)vals[p2.x >> 16] << 8) |
-                              ((uint32_t)vals[p2.y & 0xffffu] << 16) | ((uint32_t)vals[p2.y >> 16] << 24);
-        if (aligned4) {
-          *reinterpret_cast<uint32_t *>(out8 + i) = word;
+    constexpr uint32_t kStep = 4u * kPartThreads;
+    for (uint32_t i0 = b + 4u * threadIdx.x; i0 < e; i0 += 4u * kStep) {
+      uint2 p2[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4u; ++u) {
+        const uint32_t i = i0 + u * kStep;
+        p2[u] = i + 4u <= e ? *reinterpret_cast<const uint2 *>(pos + i) : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < 4u; ++u) {
+        const uint32_t i = i0 + u * kStep;
+        if (i + 4u <= e) {
+          const uint32_t word = (uint32_t)vals[p2[u].x & 0xffffu] | ((uint32_t)vals[p2[u].x >> 16] << 8) |
+                                ((uint32_t)vals[p2[u].y & 0xffffu] << 16) | ((uint32_t)vals[p2[u].y >> 16] << 24);
+          if (aligned4) {
+            *reinterpret_cast<uint32_t *>(out8 + i) = word;
+          } else {
+            for (uint32_t k = 0; k < 4u; ++k) out8[i + k] = (uint8_t)(word >> (8u * k));
+          }
         } else {
-          for (uint32_t k = 0; k < 4u; ++k) out8[i + k] = (uint8_t)(word >> (8u * k));
+          for (uint32_t k = i; k < e; ++k) out8[k] = vals[pos[k]];
         }
-      } else {
-        for (uint32_t k = i; k < e; ++k) out8[k] = vals[pos[k]];
       }
     }
   } else {
@@ -675,7 +734,7 @@ PartitionLayout layout(void *workspace, uint64_t n, uint32_t num_slices, uint32_
     L.pos = reinterpret_cast<uint16_t *>(base + off);
     off += up(n * 2u);
     L.res = reinterpret_cast<uint8_t *>(base + off);
-    off += up(padded + 4u);  // 4 bytes of padding for the unpermute kernel's word loads
+    off += up(padded + 8u);  // 8 bytes of padding for the unpermute kernel's word loads
   }
   L.bytes = off;
   return L;
@@ -695,31 +754,33 @@ void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uin
   if (*groups == 0) *groups = 1;
 }
 
-template <bool kWithPos, int R>
+template <bool kWithPos, int R, uint32_t L>
 hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
-                          uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L, hipStream_t stream) {
-  const size_t lds = scatter_lds_bytes(num_slices, kWithPos);
-  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R>,
+                          uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L_, hipStream_t stream) {
+  const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L);
+  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R, L>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
-  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R>), dim3(groups), dim3(kScatterThreads), lds, stream, hashes, n,
-                     chunk, num_blocks, slice_shift, num_slices, L.offsets, L.start, L.hist, L.keys,
-                     kWithPos ? L.pos : nullptr);
+  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L>), dim3(groups), dim3(kScatterThreads), lds, stream, hashes,
+                     n, chunk, num_blocks, slice_shift, num_slices, L_.offsets, L_.start, L_.hist, L_.keys,
+                     kWithPos ? L_.pos : nullptr);
   return hipGetLastError();
 }
 
 // Slices per owning thread: the smallest power of two R with R * threads >= P.
+// With one slice per thread, runs are written in aligned groups of
+// kScatterGroup keys (the incomplete tail carried to the next tile).
 template <bool kWithPos>
 hipError_t launch_scatter_r(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups,
                             uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L,
                             hipStream_t stream) {
   if (num_slices <= kScatterThreads)
-    return launch_scatter<kWithPos, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+    return launch_scatter<kWithPos, 1, kScatterGroup>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L,
+                                                      stream);
   if (num_slices <= 2u * kScatterThreads)
-    return launch_scatter<kWithPos, 2>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
-  if (num_slices <= 4u * kScatterThreads)
-    return launch_scatter<kWithPos, 4>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
-  return launch_scatter<kWithPos, 8>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+    return launch_scatter<kWithPos, 2, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  static_assert(4u * kScatterThreads >= kMaxSlices, "four slices per thread cover every filter");
+  return launch_scatter<kWithPos, 4, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
 }
 
 hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, uint32_t slice_shift,
@@ -755,7 +816,7 @@ uint32_t slices_of(uint32_t num_blocks, uint32_t slice_shift) {
 
 }  // namespace
 
-uint32_t partition_max_slices() { return 4u * kPartThreads; }
+uint32_t partition_max_slices() { return kMaxSlices; }
 uint64_t partition_max_keys() { return 1ull << 31; }
 
 uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup) {
