@@ -258,11 +258,28 @@ struct SliceCursor {
 // inside the chunk (no per-key guards).
 template <bool kWithPos, int R, uint32_t L, bool kFull>
 __device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
-                                             uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices,
-                                             const ScatterLds &S, SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
+                                             const uint32_t *__restrict__ new_chunk_hist, uint32_t num_blocks,
+                                             uint32_t slice_shift, uint32_t num_slices, const ScatterLds &S,
+                                             SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
                                              uint16_t *__restrict__ out_pos) {
   static_assert(L == 1u || R == 1, "carried groups need one slice per thread");
   constexpr uint32_t kCarryMax = L > 1u ? L - 1u : 1u;
+  const uint32_t own = threadIdx.x * R;
+  if constexpr (kWithPos) {
+    // First tile of a new chunk: positions restart at that chunk's slice
+    // prefix (new_chunk_hist is its count row; it is uniform).
+    if (new_chunk_hist != nullptr) {
+      uint32_t c0[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) c0[r] = own + r < num_slices ? new_chunk_hist[own + r] : 0u;
+      uint32_t run0 = block_scan_owned<R, kScatterThreads>(c0, S.wsum);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C.pbase[r] = run0;
+        run0 += c0[r];
+      }
+    }
+  }
   uint32_t s[kScatterPer], rank[kScatterPer];
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
@@ -272,7 +289,6 @@ __device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], u
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   lds_barrier();
-  const uint32_t own = threadIdx.x * R;
   uint32_t c[R], m[R];
   uint64_t carried[R][kCarryMax];
 #pragma unroll
@@ -343,10 +359,11 @@ __device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], u
 // which is what the unpermute kernel reads back from LDS.
 template <bool kWithPos, int R, uint32_t L>
 __global__ void __launch_bounds__(kScatterThreads)
-part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t num_blocks,
-                    uint32_t slice_shift, uint32_t num_slices, const uint32_t *__restrict__ offsets,
-                    const uint32_t *__restrict__ start, const uint32_t *__restrict__ hist_rows,
-                    uint64_t *__restrict__ out_keys, uint16_t *__restrict__ out_pos) {
+part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t chunks_per_group,
+                    uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices,
+                    const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
+                    const uint32_t *__restrict__ hist_rows, uint64_t *__restrict__ out_keys,
+                    uint16_t *__restrict__ out_pos) {
   extern __shared__ unsigned long long smem[];
   ScatterLds S;
   S.stage = reinterpret_cast<uint64_t *>(smem);
@@ -356,13 +373,15 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   S.pdelta = S.sbase + num_slices;
   S.wsum = kWithPos ? S.pdelta + num_slices : S.pdelta;
 
+  // This workgroup takes chunks u0 .. u0 + chunks_per_group - 1.
+  const uint32_t u0 = blockIdx.x * chunks_per_group;
   uint32_t b, e;
-  chunk_range(blockIdx.x, chunk, n, &b, &e);
+  chunk_range(blockIdx.x, chunk * chunks_per_group, n, &b, &e);
   if (b >= e) return;  // whole workgroup
 
   const uint32_t own = threadIdx.x * R;
-  const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
-  const uint32_t *my_hist = hist_rows + (uint64_t)blockIdx.x * num_slices;
+  const uint32_t *my_start = start + (uint64_t)u0 * num_slices;
+  const uint32_t *my_hist = hist_rows + (uint64_t)u0 * num_slices;
   SliceCursor<R> C;
   uint32_t c[R];
 #pragma unroll
@@ -391,23 +410,28 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   uint64_t ha[kScatterPer], hb[kScatterPer];
   load_tile(hashes, b, e, ha);
   uint32_t t0 = b, k = 0;
+#define SBBF_SCATTER_TILE(FULL, H)                                                                            \
+  scatter_tile<kWithPos, R, L, FULL>(H, t0, e, t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * \
+                                                                                   num_slices                  \
+                                                                             : nullptr,                        \
+                                     num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos)
   for (; k + 2u <= nfull; k += 2u) {
     load_tile(hashes, t0 + kTile, e, hb);
-    scatter_tile<kWithPos, R, L, true>(ha, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
+    SBBF_SCATTER_TILE(true, ha);
     t0 += kTile;
     load_tile(hashes, t0 + kTile, e, ha);
-    scatter_tile<kWithPos, R, L, true>(hb, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
+    SBBF_SCATTER_TILE(true, hb);
     t0 += kTile;
   }
   if (k < nfull) {
     load_tile(hashes, t0 + kTile, e, hb);
-    scatter_tile<kWithPos, R, L, true>(ha, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
+    SBBF_SCATTER_TILE(true, ha);
     t0 += kTile;
-    if (t0 < e)
-      scatter_tile<kWithPos, R, L, false>(hb, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
+    if (t0 < e) SBBF_SCATTER_TILE(false, hb);
   } else if (t0 < e) {
-    scatter_tile<kWithPos, R, L, false>(ha, t0, e, num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos);
+    SBBF_SCATTER_TILE(false, ha);
   }
+#undef SBBF_SCATTER_TILE
   // The last incomplete group of every slice: its keys are still in the
   // stage (nothing rewrites it after the last tile's staging barrier).
   if constexpr (L > 1u) {
@@ -417,9 +441,24 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   }
 }
 
+// Copy of a slice (nb blocks from block b0) into LDS: eight 16-byte loads
+// per thread issued back to back, then the LDS stores.
 __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *words, uint32_t b0, uint32_t nb) {
   const uint4 *src4 = reinterpret_cast<const uint4 *>(words + (uint64_t)b0 * 8u);
-  for (uint32_t i = threadIdx.x; i < nb * 2u; i += kPartThreads) lds4[i] = src4[i];
+  const uint32_t count = nb * 2u;
+  for (uint32_t base = 0; base < count; base += 8u * kPartThreads) {
+    uint4 v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8u; ++u) {
+      const uint32_t i = base + u * kPartThreads + threadIdx.x;
+      v[u] = i < count ? src4[i] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 8u; ++u) {
+      const uint32_t i = base + u * kPartThreads + threadIdx.x;
+      if (i < count) lds4[i] = v[u];
+    }
+  }
 }
 
 // Slice kernels: one lane per key, four keys per lane per step. Slice s's
@@ -604,57 +643,81 @@ part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
 // into LDS end to end in slice order, then writes out[i] = lds[pos[i]] for
 // the chunk, as bytes or packed bits (LSB-first).
 template <bool kBits>
-__global__ void __launch_bounds__(kPartThreads)
+__global__ void __launch_bounds__(kPartThreads, 8)  // 8 waves per SIMD: two workgroups per CU
 part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint8_t *__restrict__ res,
                       const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
                       const uint32_t *__restrict__ hist_rows, uint32_t num_slices, uint32_t n, uint32_t chunk,
                       uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
   extern __shared__ uint32_t usmem[];
-  uint32_t *local = usmem;                                 // [num_slices]
-  uint32_t *wsum = local + num_slices;                     // [16]
+  uint32_t *local = usmem;                                 // [num_slices] run start among the chunk's results
+  uint32_t *src = local + num_slices;                      // [num_slices] run start in res (byte index)
+  uint32_t *wsum = src + num_slices;                       // [16]
   uint8_t *vals = reinterpret_cast<uint8_t *>(wsum + 16);  // [chunk]
   const uint32_t *row = hist_rows + (uint64_t)blockIdx.x * num_slices;
   const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
   {
-    // local[s]: where slice s's run starts among the chunk's results.
-    uint32_t c[4];
+    uint32_t c[4], at[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint32_t s = threadIdx.x * 4u + r;
       c[r] = s < num_slices ? row[s] : 0u;
+      at[r] = s < num_slices ? offsets[s] + my_start[s] : 0u;
     }
     uint32_t run = block_scan_owned<4>(c, wsum);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const uint32_t s = threadIdx.x * 4u + r;
-      if (s < num_slices) local[s] = run;
+      if (s < num_slices) {
+        local[s] = run;
+        src[s] = at[r];
+      }
       run += c[r];
     }
   }
   __syncthreads();
-  // Phase 1: each group of 16 lanes copies one slice's run at a time with
-  // aligned 8-byte loads (128 bytes per pass; res has at least 8 bytes of
-  // padding after its last byte, so the last word of a run is always inside
-  // the workspace) and byte stores into LDS.
+  // Phase 1: each group of 16 lanes copies the runs of slices q, q + 64, ...
+  // with aligned 8-byte loads and byte stores into LDS. The first 128 bytes
+  // of four runs are loaded back to back; the rest of a longer run (rare:
+  // runs average one result per block of the slice) follows in a loop. res
+  // has at least 8 bytes of padding after its last byte, so the last word
+  // of a run is always inside the workspace.
+  uint32_t b, e;
+  chunk_range(blockIdx.x, chunk, n, &b, &e);
+  const uint32_t chunk_keys = e - b;
   const uint64_t *res8 = reinterpret_cast<const uint64_t *>(res);
   const uint32_t lane16 = threadIdx.x & 15u;
-  for (uint32_t sl = threadIdx.x >> 4; sl < num_slices; sl += kPartThreads / 16u) {
-    const uint32_t len = row[sl];
-    const uint32_t src = offsets[sl] + my_start[sl];  // byte index into res
-    uint8_t *dst = vals + local[sl];
-    const uint32_t w_end = (src + len + 7u) >> 3;
-    for (uint32_t w = (src >> 3) + lane16; w < w_end; w += 16u) {
-      const uint64_t v = res8[w];
+  constexpr uint32_t kGroups = kPartThreads / 16u;
+  constexpr uint32_t kBatch = 4;
+  auto put = [&](uint64_t v, uint32_t w, uint32_t from, uint32_t len, uint8_t *dst) {
 #pragma unroll
-      for (uint32_t by = 0; by < 8u; ++by) {
-        const uint32_t at = w * 8u + by;  // byte index into res
-        if (at >= src && at < src + len) dst[at - src] = (uint8_t)(v >> (8u * by));
-      }
+    for (uint32_t by = 0; by < 8u; ++by) {
+      const uint32_t at = w * 8u + by;  // byte index into res
+      if (at >= from && at < from + len) dst[at - from] = (uint8_t)(v >> (8u * by));
+    }
+  };
+  for (uint32_t sl0 = threadIdx.x >> 4; sl0 < num_slices; sl0 += kBatch * kGroups) {
+    uint64_t v[kBatch];
+    uint32_t from[kBatch], len[kBatch], w[kBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) {
+      const uint32_t sl = sl0 + u * kGroups;
+      const bool ok = sl < num_slices;
+      from[u] = ok ? src[sl] : 0u;
+      len[u] = ok ? (sl + 1u < num_slices ? local[sl + 1u] : chunk_keys) - local[sl] : 0u;
+      w[u] = (from[u] >> 3) + lane16;
+      v[u] = w[u] < ((from[u] + len[u] + 7u) >> 3) ? res8[w[u]] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kBatch; ++u) {
+      const uint32_t sl = sl0 + u * kGroups;
+      if (sl >= num_slices) continue;
+      uint8_t *dst = vals + local[sl];
+      const uint32_t w_end = (from[u] + len[u] + 7u) >> 3;
+      if (w[u] < w_end) put(v[u], w[u], from[u], len[u], dst);
+      for (uint32_t ww = w[u] + 16u; ww < w_end; ww += 16u) put(res8[ww], ww, from[u], len[u], dst);
     }
   }
   __syncthreads();
-  uint32_t b, e;
-  chunk_range(blockIdx.x, chunk, n, &b, &e);
   const uint32_t lane = threadIdx.x & 63u;
   if constexpr (!kBits) {
     // Phase 2 (bytes): four consecutive positions per thread and step, four
@@ -708,6 +771,7 @@ struct PartitionLayout {
   uint16_t *pos;
   uint8_t *res;
   uint64_t bytes;
+  uint32_t scatter_groups;  // lookups: scatter workgroups to spread the chunks over
 };
 
 uint32_t row_blocks(uint32_t groups) { return (groups + kScanRows - 1u) / kScanRows; }
@@ -758,11 +822,15 @@ template <bool kWithPos, int R, uint32_t L>
 hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
                           uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L_, hipStream_t stream) {
   const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L);
+  // Several chunks per workgroup (lookups cut the batch finer than inserts):
+  // about two workgroups per compute unit.
+  const uint32_t per = kWithPos ? (groups + L_.scatter_groups - 1u) / L_.scatter_groups : 1u;
+  const uint32_t grid = (groups + per - 1u) / per;
   (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R, L>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
-  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L>), dim3(groups), dim3(kScatterThreads), lds, stream, hashes,
-                     n, chunk, num_blocks, slice_shift, num_slices, L_.offsets, L_.start, L_.hist, L_.keys,
+  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L>), dim3(grid), dim3(kScatterThreads), lds, stream, hashes,
+                     n, chunk, per, num_blocks, slice_shift, num_slices, L_.offsets, L_.start, L_.hist, L_.keys,
                      kWithPos ? L_.pos : nullptr);
   return hipGetLastError();
 }
@@ -833,7 +901,8 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
   uint32_t chunk, groups;
   chunking(n, max_groups, false, &chunk, &groups);
-  const PartitionLayout L = layout(workspace, n, num_slices, groups, false);
+  PartitionLayout L = layout(workspace, n, num_slices, groups, false);
+  L.scatter_groups = groups;
   hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, false, stream);
   if (e != hipSuccess) return e;
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
@@ -853,7 +922,8 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
   uint32_t chunk, groups;
   chunking(n, max_groups, true, &chunk, &groups);
-  const PartitionLayout L = layout(workspace, n, num_slices, groups, true);
+  PartitionLayout L = layout(workspace, n, num_slices, groups, true);
+  L.scatter_groups = max_groups ? max_groups : 1u;
   hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, true, stream);
   if (e != hipSuccess) return e;
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
@@ -863,7 +933,7 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
   hipLaunchKernelGGL(part_slice_lookup_kernel, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
                      L.offsets, L.tot, words, num_blocks, slice_shift, L.res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t u_lds = (size_t)num_slices * 4u + 64u + chunk;
+  const size_t u_lds = (size_t)num_slices * 8u + 64u + chunk;
   (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)u_lds);
   (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
