@@ -40,10 +40,15 @@ PAPER_CONTEXT = {"insert_Mps": 32, "lookup_Mps": 43, "hardware": "not stated (CP
                  "source": "evaluation table, 100M elements"}
 
 
+# Sources of the single-filter path's kernels and their launch choices: a
+# change to any of them invalidates committed hardware-counter traffic.
+PLAIN_SOURCES = ("sbbf_device.h", "internal.h", "plain_kernels.hip", "partition_kernels.hip", "api.cpp")
+
+
 def _kernel_source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2101_01719_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in PLAIN_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -60,6 +65,114 @@ def _traffic(kernel: str, workload: str):
     if t.get("kernel_source_digest") != _kernel_source_digest():
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def _short_kernel(name: str) -> str:
+    import re
+
+    name = name.replace("(anonymous namespace)::", "").replace("void ", "").replace("sbbf::", "")
+    return re.sub(r"\(.*$", "", name)
+
+
+def _counter_rows(path: str, counter: str):
+    """(dispatch id, kernel, grid, value in KiB) of one counter, in dispatch order."""
+    import csv
+
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_mib: int, commands) -> int:
+    """Turn two rocprofv3 --pmc runs of the same bench command (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch) into HBM bytes per insert and per lookup
+    call, each counter scaled by what it reads for the plain device copy of
+    copy_mib MiB that the command ran first (a kernel of known traffic)."""
+    fetch, write = _counter_rows(fetch_csv, "FETCH_SIZE"), _counter_rows(write_csv, "WRITE_SIZE")
+    if [r[:3] for r in fetch] != [r[:3] for r in write]:
+        raise SystemExit("the two counter runs did not dispatch the same kernels")
+    want_kib = copy_mib * 1024.0
+    copies = [i for i, r in enumerate(write) if "copy" in r[1].lower() and abs(r[3] - want_kib) < 0.05 * want_kib]
+    if not copies:
+        raise SystemExit(f"no copy dispatch writing about {copy_mib} MiB found")
+    ci = copies[0]
+    f_fetch, f_write = want_kib / fetch[ci][3], want_kib / write[ci][3]
+    # Library dispatches after the copy: fill (clear), then the insert
+    # kernels, then the lookup kernels, step after step.
+    ops = {"insert": [], "lookup": []}
+    cur, cur_op = [], "insert"
+    for i in range(ci + 1, len(fetch)):
+        name = _short_kernel(fetch[i][1])
+        if not name.startswith(("part_", "insert_", "lookup_kernel", "fill_kernel")):
+            continue
+        if name.startswith("fill_kernel"):
+            cur, cur_op = [], "insert"
+            continue
+        cur.append((name, fetch[i][3], write[i][3]))
+        if name.startswith(("part_slice_insert", "insert_")):
+            ops["insert"].append(cur)
+            cur, cur_op = [], "lookup"
+        elif name.startswith(("part_unpermute", "lookup_kernel")):
+            ops["lookup"].append(cur)
+            cur = []
+    out = {}
+    for op, calls in ops.items():
+        if not calls:
+            continue
+        per_kernel = {}
+        for call in calls:
+            for name, fk, wk in call:
+                d = per_kernel.setdefault(name, [0.0, 0.0, 0])
+                d[0] += fk
+                d[1] += wk
+                d[2] += 1
+        kernels = {k: {"fetch_kib_per_call": v[0] / len(calls), "write_kib_per_call": v[1] / len(calls),
+                       "dispatches_per_call": v[2] / len(calls)} for k, v in per_kernel.items()}
+        hbm = sum(1024.0 * (k["fetch_kib_per_call"] * f_fetch + k["write_kib_per_call"] * f_write)
+                  for k in kernels.values())
+        out[op] = {
+            "workload": workload,
+            "operation": op,
+            "calls_averaged": len(calls),
+            "hbm_bytes_per_launch": int(round(hbm)),
+            "kernels": kernels,
+            "calibration": {"copy_mib": copy_mib, "copy_fetch_kib": fetch[ci][3], "copy_write_kib": write[ci][3],
+                            "fetch_scale": f_fetch, "write_scale": f_write},
+            "commands": list(commands),
+            "kernel_source_digest": _kernel_source_digest(),
+        }
+        path = os.path.join(ROOT, "profiles", f"traffic_{op}_{workload}.json")
+        with open(path, "w") as fh:
+            json.dump(out[op], fh, indent=1)
+            fh.write("\n")
+    print(json.dumps({op: v["hbm_bytes_per_launch"] for op, v in out.items()}))
+    return 0
+
+
+def _kernel_summary(stats_csv: str, out_md: str, title: str, command: str) -> int:
+    """Short markdown table of the library's kernels from a rocprofv3
+    kernel_stats.csv."""
+    import csv
+
+    lines = [f"# {title}", "", "Command (from the repository root, on one MI355X):", "", "```", command, "```", "",
+             "Source: rocprofv3 `kernel_stats.csv` of that run; library kernels only (the rest are torch kernels "
+             "of the input generator and the copy).", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | total (ms) |", "|---|---:|---:|---:|---:|---:|"]
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            if "sbbf" not in r["Name"]:
+                continue
+            lines.append(f"| `{_short_kernel(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                         f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
 
 
 def _ensure_built():
@@ -265,7 +378,21 @@ def main(argv=None):
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the steps, copy this many MiB once with a plain device copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_*.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "this script with --calibrate-copy-mib, then exit (no GPU use)")
+    ap.add_argument("--traffic-commands", nargs="*", default=[], help="the commands of those runs, recorded")
+    ap.add_argument("--kernel-summary", nargs=2, metavar=("STATS_CSV", "OUT_MD"),
+                    help="write a markdown kernel-time summary of a rocprofv3 kernel_stats.csv, then exit")
+    ap.add_argument("--summary-title", default="Kernel time summary")
+    ap.add_argument("--summary-command", default="")
     a = ap.parse_args(argv)
+
+    if a.traffic_from:
+        return _traffic_from_counters(a.traffic_from[0], a.traffic_from[1], a.workload,
+                                      a.calibrate_copy_mib or 1024, a.traffic_commands)
+    if a.kernel_summary:
+        return _kernel_summary(a.kernel_summary[0], a.kernel_summary[1], a.summary_title, a.summary_command)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only. Independent filters would shard across GPUs as whole "
