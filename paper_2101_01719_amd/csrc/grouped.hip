@@ -1,17 +1,24 @@
 // Grouped launches: inserts into and lookups in many filters of uneven sizes
-// in one launch (a HIP graph of three kernels), instead of one launch per
-// filter per operation.
+// in one launch (a HIP graph of three or four kernels), instead of one launch
+// per filter per operation.
 //
 // Every filter runs the same method as the single-filter path; the group only
 // changes how work is spread over the device:
 //
-//   insert  one persistent kernel over (filter, slice) tiles. A filter whose
-//           words fit the LDS threshold is one tile; a larger filter is cut
-//           into slices of 2^slice_shift blocks, one tile each. The workgroup
-//           of a tile loads its slice into LDS, streams all of the filter's
-//           insert keys, ORs the masks of the keys that fall in the slice, and
-//           stores the slice back with plain stores. Tiles are ordered by cost
-//           (keys streamed), largest first, and taken from one atomic queue.
+//   partition  for every filter larger than the LDS threshold (cut into at
+//           most 1,024 slices of 2^slice_shift blocks), one workgroup per chunk
+//           of 7,168 of its insert keys sorts the chunk by slice in LDS and
+//           appends one run per slice to that slice's run list, taking the
+//           room from the filter's region of a key array with one device
+//           atomic per run (key order inside a slice does not matter: a
+//           filter is the OR of all masks).
+//   insert  one persistent kernel over (filter, slice) tiles, largest first,
+//           from one atomic queue. The workgroup of a tile loads its slice into
+//           LDS, ORs in the masks of its keys and stores the slice back with
+//           plain stores. A filter within the LDS threshold is one tile that
+//           streams the filter's keys; a partitioned slice reads only its runs;
+//           a filter with more slices than that streams all of its keys for
+//           every slice and ORs those that fall in it.
 //   lookup  one persistent kernel over (filter, key range) tiles with the
 //           8-lane gather of the single-filter lookup. Tiles sit in eight
 //           queues, one per XCD (workgroups are dispatched to the XCDs round
@@ -42,6 +49,17 @@ namespace {
 
 constexpr int kQueues = 8;  // XCDs of the device (lookup queues)
 constexpr uint32_t kInsertThreads = 1024;
+constexpr uint32_t kPartPer = 7;                             // keys per thread of a partition chunk
+constexpr uint32_t kPartChunk = kInsertThreads * kPartPer;   // keys per partition chunk
+constexpr uint32_t kMaxLocalSlices = kInsertThreads;         // slices of one partitioned filter
+constexpr uint32_t kRunBatch = kInsertThreads;               // runs staged in LDS at a time
+constexpr uint32_t kStreamTile = 0xFFFFFFFFu;                // tile that streams its filter's keys
+// LDS of the partition kernel: stage [kPartChunk] u64, delta [kMaxLocalSlices]
+// u64, hist and loff [kMaxLocalSlices] u32, wsum [16].
+constexpr size_t kPartLds = (size_t)kPartChunk * 8u + (size_t)kMaxLocalSlices * 16u + 64u;
+// LDS after an insert tile's slice words: run prefix [kRunBatch + 1] u32,
+// run offsets [kRunBatch] u64, wsum [16].
+constexpr size_t kRunLds = (size_t)kRunBatch * 12u + 4u + 64u + 4u;
 
 struct GFilter {
   uint32_t *words;
@@ -51,9 +69,36 @@ struct GFilter {
 
 struct GInsTile {
   uint32_t filter;
-  uint32_t b0;  // first block of the tile's slice
-  uint32_t nb;  // blocks in the slice
+  uint32_t b0;     // first block of the tile's slice
+  uint32_t nb;     // blocks in the slice
+  uint32_t slice;  // global id of a partitioned filter's slice, or kStreamTile
+};
+
+// A filter whose insert keys are partitioned by slice before the insert tiles
+// run: each slice's keys end up as runs in the partitioned key array.
+struct GPart {
+  uint64_t base;        // first index of its keys in the partitioned key array
+  uint32_t filter;
+  uint32_t slice_base;  // global id of its first slice
+  uint32_t nslices;
+  uint32_t shift;       // slice = block >> shift
+};
+
+struct GChunk {
+  uint64_t begin;  // first insert key (index into the insert hash array)
+  uint32_t count;  // keys, at most kPartChunk
+  uint32_t part;
+};
+
+struct GRun {
+  uint64_t start;  // first key in the partitioned key array
+  uint32_t count;
   uint32_t pad;
+};
+
+struct GSlice {
+  uint32_t run_off;  // first entry of its run list
+  uint32_t run_cap;  // entries (one per chunk of its filter)
 };
 
 struct GLookTile {
@@ -62,7 +107,7 @@ struct GLookTile {
   uint32_t filter;
 };
 
-// Device-side plan: pointers into one allocation.
+// Device-side plan: pointers into one allocation (part_keys is a second one).
 struct GPlanDev {
   const GFilter *filters;
   const uint64_t *ins_off;   // [F + 1]
@@ -70,25 +115,128 @@ struct GPlanDev {
   const GLookTile *look_tiles;
   const uint32_t *queue_begin;  // [kQueues + 1] tile ranges per queue
   uint32_t *counters;           // [1 + kQueues]: insert queue, lookup queues
+  const GPart *parts;           // [n_parts]
+  const GChunk *chunks;         // [n_chunks]
+  const GSlice *slices;         // [n_slices]
+  GRun *runs;                   // run lists, GSlice::run_off / run_cap
+  uint32_t *nruns;              // [n_slices] runs written so far
+  unsigned long long *tops;     // [n_parts] next free index of each part's region
+  uint64_t *part_keys;          // partitioned insert keys
   uint32_t n_ins_tiles;
+  uint32_t n_parts;
+  uint32_t n_slices;
   uint32_t pad;
 };
 
 // ---- insert -----------------------------------------------------------------
 
+// OR the mask of one key into the slice [b0, b0 + nb) of a filter of B blocks
+// held in LDS (four 64-bit words per block): four 64-bit LDS ORs. A key
+// outside the slice, or an invalid lane, ORs a zero mask into block 0.
+__device__ __forceinline__ void or_key(unsigned long long *lds2, uint64_t h, bool valid, uint32_t B, uint32_t b0,
+                                       uint32_t nb) {
+  const uint32_t rel = block_of((uint32_t)(h >> 32), B) - b0;
+  const bool in = valid && rel < nb;
+  const uint32_t one = in ? 1u : 0u;
+  const uint32_t x = (uint32_t)h;
+  unsigned long long *blk = lds2 + (uint64_t)(in ? rel : 0u) * 4u;
+  __hip_atomic_fetch_or(blk + 0, (unsigned long long)(one << bit_of(kSeed0, x)) |
+                                     ((unsigned long long)(one << bit_of(kSeed1, x)) << 32),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_or(blk + 1, (unsigned long long)(one << bit_of(kSeed2, x)) |
+                                     ((unsigned long long)(one << bit_of(kSeed3, x)) << 32),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_or(blk + 2, (unsigned long long)(one << bit_of(kSeed4, x)) |
+                                     ((unsigned long long)(one << bit_of(kSeed5, x)) << 32),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_fetch_or(blk + 3, (unsigned long long)(one << bit_of(kSeed6, x)) |
+                                     ((unsigned long long)(one << bit_of(kSeed7, x)) << 32),
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Partition of one chunk of a partitioned filter's insert keys by slice: rank
+// every key within its slice (LDS atomics), scan the counts, take room for
+// each slice's run from the filter's region (one device atomic per slice of
+// the chunk), record the run in the slice's run list, stage the keys sorted
+// by slice in LDS and write the runs with consecutive lanes. Key order inside
+// a slice is irrelevant (a filter is the OR of all masks).
 __global__ void __launch_bounds__(kInsertThreads)
-grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes) {
+grouped_part_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes) {
+  extern __shared__ unsigned long long psm[];
+  uint64_t *stage = reinterpret_cast<uint64_t *>(psm);  // [kPartChunk]
+  unsigned long long *delta = psm + kPartChunk;         // [kMaxLocalSlices]
+  uint32_t *hist = reinterpret_cast<uint32_t *>(delta + kMaxLocalSlices);
+  uint32_t *loff = hist + kMaxLocalSlices;
+  uint32_t *wsum = loff + kMaxLocalSlices;
+  const GChunk ch = plan.chunks[blockIdx.x];
+  const GPart pt = plan.parts[ch.part];
+  const uint32_t B = plan.filters[pt.filter].num_blocks;
+  const uint32_t ns = pt.nslices, n = ch.count;
+  if (threadIdx.x < ns) hist[threadIdx.x] = 0u;
+  uint64_t h[kPartPer];
+#pragma unroll
+  for (uint32_t t = 0; t < kPartPer; ++t) {
+    const uint32_t i = t * kInsertThreads + threadIdx.x;
+    h[t] = load_hash<0>(hashes + ch.begin + (i < n ? i : n - 1u));
+  }
+  __syncthreads();
+  uint32_t s[kPartPer], rank[kPartPer];
+#pragma unroll
+  for (uint32_t t = 0; t < kPartPer; ++t) {
+    const uint32_t i = t * kInsertThreads + threadIdx.x;
+    s[t] = block_of((uint32_t)(h[t] >> 32), B) >> pt.shift;
+    rank[t] = __hip_atomic_fetch_add(hist + s[t], i < n ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __syncthreads();
+  const uint32_t c[1] = {threadIdx.x < ns ? hist[threadIdx.x] : 0u};
+  const uint32_t run = block_scan_owned<1, kInsertThreads>(c, wsum);
+  if (threadIdx.x < ns) {
+    loff[threadIdx.x] = run;
+    if (c[0] > 0u) {
+      const unsigned long long at = __hip_atomic_fetch_add(plan.tops + ch.part, (unsigned long long)c[0],
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t slice = pt.slice_base + threadIdx.x;
+      const uint32_t k = __hip_atomic_fetch_add(plan.nruns + slice, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      plan.runs[plan.slices[slice].run_off + k] = GRun{at, c[0], 0u};
+      delta[threadIdx.x] = at - run;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t t = 0; t < kPartPer; ++t) {
+    const uint32_t i = t * kInsertThreads + threadIdx.x;
+    if (i < n) stage[loff[s[t]] + rank[t]] = h[t];
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t t = 0; t < kPartPer; ++t) {
+    const uint32_t k = t * kInsertThreads + threadIdx.x;
+    if (k < n) {
+      const uint64_t key = stage[k];
+      plan.part_keys[k + delta[block_of((uint32_t)(key >> 32), B) >> pt.shift]] = key;
+    }
+  }
+}
+
+// Insert tiles, taken from one queue: the workgroup loads its slice into LDS,
+// ORs in the masks of its keys and stores the slice back with plain stores.
+// A stream tile reads all insert keys of its filter and ORs those that fall
+// in the slice (a whole small filter, or a slice of a filter with more slices
+// than one partition chunk can sort); a partitioned tile reads exactly its
+// slice's runs, handled as one sequence of keys.
+__global__ void __launch_bounds__(kInsertThreads)
+grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint32_t words_lds_bytes) {
   extern __shared__ uint4 lds4[];
   unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
+  uint32_t *pre = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(lds4) + words_lds_bytes);  // [kRunBatch + 1]
+  unsigned long long *off = reinterpret_cast<unsigned long long *>(pre + kRunBatch + 2u);           // [kRunBatch]
+  uint32_t *wsum = reinterpret_cast<uint32_t *>(off + kRunBatch);                                   // [16]
   __shared__ uint32_t tile_id;
   const uint32_t lane = lane_id();
-  const uint32_t q = lane & 3u;
-  const uint32_t group4 = lane & ~3u;
-  const uint32_t seed_lo = seed_of_word(2u * q);
-  const uint32_t seed_hi = seed_of_word(2u * q + 1u);
-  const uint32_t waves = blockDim.x / kWave;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  constexpr uint32_t waves = kInsertThreads / kWave;
   constexpr uint32_t U = 4;
-  constexpr uint32_t kChunk = 64u * U;
+  constexpr uint32_t kStep = 64u * U;
 
   for (;;) {
     if (threadIdx.x == 0)
@@ -100,41 +248,62 @@ grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes) {
     const GInsTile tile = plan.ins_tiles[t];
     const GFilter flt = plan.filters[tile.filter];
     const uint4 *src4 = reinterpret_cast<const uint4 *>(flt.words + (uint64_t)tile.b0 * 8u);
-    for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += blockDim.x) lds4[i] = src4[i];
+    for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += kInsertThreads) lds4[i] = src4[i];
     __syncthreads();
-    const uint64_t kb = plan.ins_off[tile.filter];
-    const uint32_t n = (uint32_t)(plan.ins_off[tile.filter + 1] - kb);
-    const uint64_t *keys = hashes + kb;
-    // Four lanes per key (64-bit LDS words), keys loaded directly per group
-    // (tail lanes re-read the last key; OR-ing a mask twice changes nothing).
-    // Keys outside the slice OR a zero mask into word 0, also a no-op.
-    for (uint32_t base = (threadIdx.x / kWave) * kChunk; base < n; base += waves * kChunk) {
-      uint64_t h[U][4];
+    if (tile.slice == kStreamTile) {
+      const uint64_t kb = plan.ins_off[tile.filter];
+      const uint32_t n = (uint32_t)(plan.ins_off[tile.filter + 1] - kb);
+      const uint64_t *keys = hashes + kb;
+      for (uint32_t base = wave * kStep; base < n; base += waves * kStep) {
+        uint64_t hv[U];
 #pragma unroll
-      for (uint32_t u = 0; u < U; ++u) {
-#pragma unroll
-        for (uint32_t p = 0; p < 4; ++p) {
-          const uint32_t i = base + 64u * u + group4 + p;
-          h[u][p] = load_hash<0>(keys + (i < n ? i : n - 1u));
+        for (uint32_t u = 0; u < U; ++u) {
+          const uint32_t i = base + 64u * u + lane;
+          hv[u] = load_hash<0>(keys + (i < n ? i : n - 1u));
         }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+          or_key(lds2, hv[u], base + 64u * u + lane < n, flt.num_blocks, tile.b0, tile.nb);
       }
-#pragma unroll
-      for (uint32_t u = 0; u < U; ++u) {
-#pragma unroll
-        for (uint32_t p = 0; p < 4; ++p) {
-          const uint32_t rel = block_of((uint32_t)(h[u][p] >> 32), flt.num_blocks) - tile.b0;
-          const bool in = rel < tile.nb;
-          const uint32_t x = (uint32_t)h[u][p];
-          const unsigned long long m = (unsigned long long)(1u << bit_of(seed_lo, x)) |
-                                       ((unsigned long long)(1u << bit_of(seed_hi, x)) << 32);
-          __hip_atomic_fetch_or(lds2 + (in ? rel : 0u) * 4u + q, in ? m : 0ull, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      const uint32_t nr = plan.nruns[tile.slice];
+      const GRun *runs = plan.runs + plan.slices[tile.slice].run_off;
+      for (uint32_t r0 = 0; r0 < nr; r0 += kRunBatch) {
+        // Runs r0 .. r0 + m - 1 as one sequence: pre[k] is where run k starts
+        // in it and key j of the sequence is part_keys[off[k] + j].
+        const uint32_t m = min(kRunBatch, nr - r0);
+        const uint32_t k = threadIdx.x;
+        const GRun rn = k < m ? runs[r0 + k] : GRun{0ull, 0u, 0u};
+        const uint32_t cnt[1] = {rn.count};
+        uint32_t total;
+        const uint32_t at = block_scan_owned<1, kInsertThreads>(cnt, wsum, &total);
+        if (k < m) {
+          pre[k] = at;
+          off[k] = rn.start - at;
         }
+        if (k == 0) pre[m] = total;
+        __syncthreads();
+        uint32_t rw = 0;  // run of the wave's first key (wave-uniform)
+        for (uint32_t base = wave * kStep; base < total; base += waves * kStep) {
+          while (pre[rw + 1u] <= base) ++rw;
+          uint64_t hv[U];
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t j = min(base + 64u * u + lane, total - 1u);
+            uint32_t r = rw;
+            while (pre[r + 1u] <= j) ++r;
+            hv[u] = load_hash<0>(plan.part_keys + off[r] + j);
+          }
+#pragma unroll
+          for (uint32_t u = 0; u < U; ++u)
+            or_key(lds2, hv[u], base + 64u * u + lane < total, flt.num_blocks, tile.b0, tile.nb);
+        }
+        __syncthreads();  // pre and off are rewritten by the next batch
       }
     }
     __syncthreads();
     uint4 *dst4 = reinterpret_cast<uint4 *>(flt.words + (uint64_t)tile.b0 * 8u);
-    for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += blockDim.x) dst4[i] = lds4[i];
+    for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += kInsertThreads) dst4[i] = lds4[i];
     __syncthreads();  // LDS is reused by the next tile
   }
 }
@@ -202,10 +371,17 @@ grouped_lookup_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint8_
   }
 }
 
-// Clears the queue counters (a kernel rather than a memset so the graph holds
-// kernel nodes only).
-__global__ void grouped_reset_kernel(uint32_t *counters, uint32_t n) {
-  if (threadIdx.x < n) counters[threadIdx.x] = 0u;
+// Resets the queue counters, and for the insert phase each part's region
+// cursor and each slice's run count (a kernel rather than memsets so the
+// graph holds kernel nodes only). what: 1 insert phase, 2 lookup phase.
+__global__ void grouped_reset_kernel(GPlanDev plan, uint32_t what) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (what & 1u) {
+    if (i == 0) plan.counters[0] = 0u;
+    if (i < plan.n_parts) plan.tops[i] = plan.parts[i].base;
+    if (i < plan.n_slices) plan.nruns[i] = 0u;
+  }
+  if ((what & 2u) && i < (uint32_t)kQueues) plan.counters[1 + i] = 0u;
 }
 
 // Order-sensitive 64-bit digest of device words, for comparing autotune
@@ -247,14 +423,15 @@ struct GroupedPlanHost {
   std::vector<uint64_t> ins_off, look_off;
   sbbf_grouped_config cfg;
   bool planned = false;
-  uint32_t n_ins_tiles = 0, n_look_tiles = 0;
-  size_t insert_lds = 0;
-  void *dev = nullptr;  // device allocation holding the plan tables
+  uint32_t n_ins_tiles = 0, n_look_tiles = 0, n_chunks = 0;
+  size_t insert_lds = 0;   // LDS of the largest insert slice
+  void *dev = nullptr;     // device allocation holding the plan tables
+  void *keys = nullptr;    // device allocation of the partitioned insert keys
   GPlanDev pd{};
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t n_reset = nullptr, n_ins = nullptr, n_look = nullptr;
+  hipGraphNode_t n_reset = nullptr, n_part = nullptr, n_ins = nullptr, n_look = nullptr;
   const void *g_ins = nullptr, *g_look = nullptr;
   void *g_out = nullptr;
 };
@@ -275,9 +452,12 @@ void free_plan(GroupedPlanHost &p) {
   if (p.exec) (void)hipGraphExecDestroy(p.exec);
   if (p.graph) (void)hipGraphDestroy(p.graph);
   if (p.dev) (void)hipFree(p.dev);
+  if (p.keys) (void)hipFree(p.keys);
   p.exec = nullptr;
   p.graph = nullptr;
   p.dev = nullptr;
+  p.keys = nullptr;
+  p.n_part = nullptr;
   p.planned = false;
   p.g_ins = p.g_look = nullptr;
   p.g_out = nullptr;
@@ -327,6 +507,14 @@ const void *lookup_func(int unroll) {
   }
 }
 
+// Dynamic LDS of the insert kernel: the largest slice, then the run staging.
+static size_t insert_kernel_lds(const GroupedPlanHost &p) { return ((p.insert_lds + 31u) & ~(size_t)31u) + kRunLds; }
+
+static dim3 reset_grid(const GroupedPlanHost &p) {
+  const uint32_t n = std::max<uint32_t>({(uint32_t)kQueues, p.pd.n_parts, p.pd.n_slices, 1u});
+  return dim3((n + 255u) / 256u);
+}
+
 // Build tiles and queues for the group and copy them to the device.
 sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uint64_t *look_off,
                                const sbbf_grouped_config &cfg, const sbbf_device_info &info) {
@@ -343,12 +531,20 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   }
   p.cfg = cfg;
 
-  // Insert tiles: whole filter when it fits insert_lds_bytes, else slices.
+  // Insert tiles. A filter that fits insert_lds_bytes is one stream tile. A
+  // larger one is cut into slices of S blocks; with at most kMaxLocalSlices
+  // slices its keys are partitioned by slice (chunks of kPartChunk keys, one
+  // run per slice and chunk) and each slice is a partitioned tile, else each
+  // slice is a stream tile.
   struct Cost {
     uint64_t cost;
     GInsTile t;
   };
   std::vector<Cost> ins;
+  std::vector<GPart> parts;
+  std::vector<std::vector<GChunk>> part_chunks;
+  std::vector<GSlice> slices;
+  uint64_t part_keys = 0, run_total = 0;
   size_t max_lds = 32;
   const uint32_t S = 1u << cfg.insert_slice_shift;
   for (uint32_t f = 0; f < F; ++f) {
@@ -356,19 +552,52 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
     if (n == 0) continue;
     const uint32_t B = g->filters[f]->num_blocks;
     if ((uint64_t)B * 32u <= cfg.insert_lds_bytes) {
-      ins.push_back({n, {f, 0u, B, 0u}});
+      ins.push_back({n, {f, 0u, B, kStreamTile}});
       max_lds = std::max(max_lds, (size_t)B * 32u);
-    } else {
-      for (uint64_t b0 = 0; b0 < B; b0 += S) {
-        const uint32_t nb = (uint32_t)std::min<uint64_t>(S, B - b0);
-        ins.push_back({n, {f, (uint32_t)b0, nb, 0u}});
-        max_lds = std::max(max_lds, (size_t)nb * 32u);
+      continue;
+    }
+    const uint32_t ns = (uint32_t)(((uint64_t)B + S - 1u) / S);
+    const bool partition = ns <= kMaxLocalSlices;
+    if (partition) {
+      const uint32_t pi = (uint32_t)parts.size();
+      const uint32_t n_chunks = (uint32_t)((n + kPartChunk - 1u) / kPartChunk);
+      parts.push_back({part_keys, f, (uint32_t)slices.size(), ns, cfg.insert_slice_shift});
+      part_chunks.emplace_back();
+      for (uint64_t at = 0; at < n; at += kPartChunk)
+        part_chunks.back().push_back({p.ins_off[f] + at, (uint32_t)std::min<uint64_t>(kPartChunk, n - at), pi});
+      part_keys += n;
+      for (uint32_t k = 0; k < ns; ++k) {
+        slices.push_back({(uint32_t)run_total, n_chunks});
+        run_total += n_chunks;
       }
     }
+    for (uint32_t k = 0; k < ns; ++k) {
+      const uint64_t b0 = (uint64_t)k * S;
+      const uint32_t nb = (uint32_t)std::min<uint64_t>(S, B - b0);
+      if (partition)
+        ins.push_back({(n + ns - 1u) / ns, {f, (uint32_t)b0, nb, parts.back().slice_base + k}});
+      else
+        ins.push_back({n, {f, (uint32_t)b0, nb, kStreamTile}});
+      max_lds = std::max(max_lds, (size_t)nb * 32u);
+    }
   }
+  if (run_total > 0xFFFFFFFFull) return set_error(SBBF_EUNSUPPORTED, "too many insert keys in partitioned filters");
   std::stable_sort(ins.begin(), ins.end(), [](const Cost &a, const Cost &b) { return a.cost > b.cost; });
   p.n_ins_tiles = (uint32_t)ins.size();
   p.insert_lds = max_lds;
+  // Chunks of different filters interleaved, so that workgroups running at
+  // the same time mostly take room from different filters' regions.
+  std::vector<GChunk> chunks;
+  for (size_t k = 0;; ++k) {
+    bool any = false;
+    for (auto &pc : part_chunks)
+      if (k < pc.size()) {
+        chunks.push_back(pc[k]);
+        any = true;
+      }
+    if (!any) break;
+  }
+  p.n_chunks = (uint32_t)chunks.size();
 
   // Lookup tiles, filters assigned to queues greedily by work (largest first).
   std::vector<uint32_t> order(F);
@@ -403,25 +632,41 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   std::vector<GFilter> ft(F);
   for (uint32_t f = 0; f < F; ++f) ft[f] = {g->filters[f]->words, g->filters[f]->num_blocks, 0u};
 
-  // One device allocation: filters | ins_off | ins tiles | look tiles | queue_begin | counters.
+  // One device allocation: filters | ins_off | ins tiles | look tiles |
+  // queue_begin | counters | parts | chunks | slices | runs | nruns | tops;
+  // the partitioned keys are a second one.
   auto up = [](size_t v) { return (v + 255u) & ~(size_t)255u; };
+  auto at_least1 = [](size_t v) { return std::max<size_t>(1, v); };
   const size_t o_f = 0;
   const size_t o_io = o_f + up(F * sizeof(GFilter));
   const size_t o_it = o_io + up((F + 1) * sizeof(uint64_t));
-  const size_t o_lt = o_it + up(std::max<size_t>(1, ins.size()) * sizeof(GInsTile));
-  const size_t o_qb = o_lt + up(std::max<size_t>(1, look.size()) * sizeof(GLookTile));
+  const size_t o_lt = o_it + up(at_least1(ins.size()) * sizeof(GInsTile));
+  const size_t o_qb = o_lt + up(at_least1(look.size()) * sizeof(GLookTile));
   const size_t o_c = o_qb + up((kQueues + 1) * sizeof(uint32_t));
-  const size_t total = o_c + up((1 + kQueues) * sizeof(uint32_t));
-  std::vector<char> host(total, 0);
+  const size_t o_pt = o_c + up((1 + kQueues) * sizeof(uint32_t));
+  const size_t o_ch = o_pt + up(at_least1(parts.size()) * sizeof(GPart));
+  const size_t o_sl = o_ch + up(at_least1(chunks.size()) * sizeof(GChunk));
+  const size_t o_rn = o_sl + up(at_least1(slices.size()) * sizeof(GSlice));
+  const size_t o_nr = o_rn + up(at_least1(run_total) * sizeof(GRun));
+  const size_t o_tp = o_nr + up(at_least1(slices.size()) * sizeof(uint32_t));
+  const size_t total = o_tp + up(at_least1(parts.size()) * sizeof(unsigned long long));
+  std::vector<char> host(o_rn, 0);  // runs, nruns and tops are written on the device
   memcpy(host.data() + o_f, ft.data(), F * sizeof(GFilter));
   memcpy(host.data() + o_io, p.ins_off.data(), (F + 1) * sizeof(uint64_t));
   for (size_t i = 0; i < ins.size(); ++i) memcpy(host.data() + o_it + i * sizeof(GInsTile), &ins[i].t, sizeof(GInsTile));
   if (!look.empty()) memcpy(host.data() + o_lt, look.data(), look.size() * sizeof(GLookTile));
   memcpy(host.data() + o_qb, qbegin.data(), (kQueues + 1) * sizeof(uint32_t));
+  if (!parts.empty()) memcpy(host.data() + o_pt, parts.data(), parts.size() * sizeof(GPart));
+  if (!chunks.empty()) memcpy(host.data() + o_ch, chunks.data(), chunks.size() * sizeof(GChunk));
+  if (!slices.empty()) memcpy(host.data() + o_sl, slices.data(), slices.size() * sizeof(GSlice));
   hipError_t e = hipMalloc(&p.dev, total);
   if (e != hipSuccess) return hip_error(e, "hipMalloc(grouped plan)");
-  e = hipMemcpy(p.dev, host.data(), total, hipMemcpyHostToDevice);
+  e = hipMemcpy(p.dev, host.data(), o_rn, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_error(e, "hipMemcpy(grouped plan)");
+  if (part_keys) {
+    e = hipMalloc(&p.keys, part_keys * sizeof(uint64_t));
+    if (e != hipSuccess) return hip_error(e, "hipMalloc(grouped partitioned keys)");
+  }
   char *d = static_cast<char *>(p.dev);
   p.pd.filters = reinterpret_cast<const GFilter *>(d + o_f);
   p.pd.ins_off = reinterpret_cast<const uint64_t *>(d + o_io);
@@ -429,9 +674,20 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   p.pd.look_tiles = reinterpret_cast<const GLookTile *>(d + o_lt);
   p.pd.queue_begin = reinterpret_cast<const uint32_t *>(d + o_qb);
   p.pd.counters = reinterpret_cast<uint32_t *>(d + o_c);
+  p.pd.parts = reinterpret_cast<const GPart *>(d + o_pt);
+  p.pd.chunks = reinterpret_cast<const GChunk *>(d + o_ch);
+  p.pd.slices = reinterpret_cast<const GSlice *>(d + o_sl);
+  p.pd.runs = reinterpret_cast<GRun *>(d + o_rn);
+  p.pd.nruns = reinterpret_cast<uint32_t *>(d + o_nr);
+  p.pd.tops = reinterpret_cast<unsigned long long *>(d + o_tp);
+  p.pd.part_keys = static_cast<uint64_t *>(p.keys);
   p.pd.n_ins_tiles = p.n_ins_tiles;
+  p.pd.n_parts = (uint32_t)parts.size();
+  p.pd.n_slices = (uint32_t)slices.size();
   (void)hipFuncSetAttribute((const void *)grouped_insert_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)p.insert_lds);
+                            (int)insert_kernel_lds(p));
+  (void)hipFuncSetAttribute((const void *)grouped_part_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kPartLds);
   (void)hipGetLastError();
   p.planned = true;
   return SBBF_OK;
@@ -446,20 +702,27 @@ static dim3 lookup_grid(const sbbf_device_info &info, const GroupedPlanHost &p) 
   return dim3(std::max<uint32_t>(kQueues, std::min<uint32_t>(want, std::max<uint32_t>(p.n_look_tiles, kQueues))));
 }
 
+static uint32_t insert_words_lds(const GroupedPlanHost &p) { return (uint32_t)((p.insert_lds + 31u) & ~(size_t)31u); }
+
 sbbf_status grouped_insert_phase(sbbf_group *g, const uint64_t *d_ins, hipStream_t s, const sbbf_device_info &info) {
   GroupedPlanHost &p = g->plan;
-  hipLaunchKernelGGL(grouped_reset_kernel, dim3(1), dim3(64), 0, s, p.pd.counters, 1u);
+  hipLaunchKernelGGL(grouped_reset_kernel, reset_grid(p), dim3(256), 0, s, p.pd, 1u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "grouped reset");
+  if (p.n_chunks) {
+    hipLaunchKernelGGL(grouped_part_kernel, dim3(p.n_chunks), dim3(kInsertThreads), kPartLds, s, p.pd, d_ins);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "grouped partition");
+  }
   if (p.n_ins_tiles == 0) return SBBF_OK;
-  hipLaunchKernelGGL(grouped_insert_kernel, insert_grid(info, p), dim3(kInsertThreads), p.insert_lds, s, p.pd, d_ins);
+  hipLaunchKernelGGL(grouped_insert_kernel, insert_grid(info, p), dim3(kInsertThreads), insert_kernel_lds(p), s, p.pd,
+                     d_ins, insert_words_lds(p));
   return hip_error(hipGetLastError(), "grouped insert");
 }
 
 sbbf_status grouped_lookup_phase(sbbf_group *g, const uint64_t *d_look, uint8_t *d_out, hipStream_t s,
                                  const sbbf_device_info &info) {
   GroupedPlanHost &p = g->plan;
-  hipLaunchKernelGGL(grouped_reset_kernel, dim3(1), dim3(64), 0, s, p.pd.counters + 1, (uint32_t)kQueues);
+  hipLaunchKernelGGL(grouped_reset_kernel, reset_grid(p), dim3(256), 0, s, p.pd, 2u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(e, "grouped reset");
   if (p.n_look_tiles == 0) return SBBF_OK;
@@ -468,32 +731,43 @@ sbbf_status grouped_lookup_phase(sbbf_group *g, const uint64_t *d_look, uint8_t 
                    "grouped lookup");
 }
 
-// The graph: reset counters -> insert -> lookup (kernel nodes only).
-static sbbf_status build_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
-                               const sbbf_device_info &info) {
-  GroupedPlanHost &p = g->plan;
-  hipError_t e = hipGraphCreate(&p.graph, 0);
-  if (e != hipSuccess) return hip_error(e, "hipGraphCreate");
-  static uint32_t all_counters = 1u + kQueues;
-  // Kernel parameters are copied into the graph when a node is added or updated.
-  void *reset_args[] = {(void *)&p.pd.counters, (void *)&all_counters};
+// The graph: reset -> partition (when the group has partitioned filters) ->
+// insert -> lookup (kernel nodes only). Kernel parameters are copied into the
+// graph when a node is added or updated.
+static sbbf_status set_insert_nodes(GroupedPlanHost &p, const uint64_t *d_ins, const sbbf_device_info &info,
+                                    bool add) {
   hipKernelNodeParams kp;
   memset(&kp, 0, sizeof(kp));
-  kp.func = (void *)grouped_reset_kernel;
-  kp.gridDim = dim3(1);
-  kp.blockDim = dim3(64);
-  kp.kernelParams = reset_args;
-  e = hipGraphAddKernelNode(&p.n_reset, p.graph, nullptr, 0, &kp);
-  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(reset)");
+  hipError_t e;
   const uint64_t *ins_arg = d_ins;
-  void *ins_args[] = {(void *)&p.pd, (void *)&ins_arg};
+  hipGraphNode_t prev = p.n_reset;
+  if (p.n_chunks) {
+    void *part_args[] = {(void *)&p.pd, (void *)&ins_arg};
+    kp.func = (void *)grouped_part_kernel;
+    kp.gridDim = dim3(p.n_chunks);
+    kp.blockDim = dim3(kInsertThreads);
+    kp.sharedMemBytes = (unsigned)kPartLds;
+    kp.kernelParams = part_args;
+    e = add ? hipGraphAddKernelNode(&p.n_part, p.graph, &prev, 1, &kp) : hipGraphExecKernelNodeSetParams(p.exec, p.n_part, &kp);
+    if (e != hipSuccess) return hip_error(e, "graph node (partition)");
+    prev = p.n_part;
+  }
+  uint32_t words_lds = insert_words_lds(p);
+  void *ins_args[] = {(void *)&p.pd, (void *)&ins_arg, (void *)&words_lds};
   kp.func = (void *)grouped_insert_kernel;
   kp.gridDim = insert_grid(info, p);
   kp.blockDim = dim3(kInsertThreads);
-  kp.sharedMemBytes = (unsigned)p.insert_lds;
+  kp.sharedMemBytes = (unsigned)insert_kernel_lds(p);
   kp.kernelParams = ins_args;
-  e = hipGraphAddKernelNode(&p.n_ins, p.graph, &p.n_reset, 1, &kp);
-  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(insert)");
+  e = add ? hipGraphAddKernelNode(&p.n_ins, p.graph, &prev, 1, &kp) : hipGraphExecKernelNodeSetParams(p.exec, p.n_ins, &kp);
+  if (e != hipSuccess) return hip_error(e, "graph node (insert)");
+  return SBBF_OK;
+}
+
+static sbbf_status set_lookup_node(GroupedPlanHost &p, const uint64_t *d_look, uint8_t *d_out,
+                                   const sbbf_device_info &info, bool add) {
+  hipKernelNodeParams kp;
+  memset(&kp, 0, sizeof(kp));
   const uint64_t *look_arg = d_look;
   uint8_t *out_arg = d_out;
   void *look_args[] = {(void *)&p.pd, (void *)&look_arg, (void *)&out_arg};
@@ -502,8 +776,29 @@ static sbbf_status build_graph(sbbf_group *g, const uint64_t *d_ins, const uint6
   kp.blockDim = dim3(p.cfg.lookup_threads);
   kp.sharedMemBytes = 0;
   kp.kernelParams = look_args;
-  e = hipGraphAddKernelNode(&p.n_look, p.graph, &p.n_ins, 1, &kp);
-  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(lookup)");
+  const hipError_t e = add ? hipGraphAddKernelNode(&p.n_look, p.graph, &p.n_ins, 1, &kp)
+                           : hipGraphExecKernelNodeSetParams(p.exec, p.n_look, &kp);
+  return e == hipSuccess ? SBBF_OK : hip_error(e, "graph node (lookup)");
+}
+
+static sbbf_status build_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
+                               const sbbf_device_info &info) {
+  GroupedPlanHost &p = g->plan;
+  hipError_t e = hipGraphCreate(&p.graph, 0);
+  if (e != hipSuccess) return hip_error(e, "hipGraphCreate");
+  uint32_t what = 3u;
+  void *reset_args[] = {(void *)&p.pd, (void *)&what};
+  hipKernelNodeParams kp;
+  memset(&kp, 0, sizeof(kp));
+  kp.func = (void *)grouped_reset_kernel;
+  kp.gridDim = reset_grid(p);
+  kp.blockDim = dim3(256);
+  kp.kernelParams = reset_args;
+  e = hipGraphAddKernelNode(&p.n_reset, p.graph, nullptr, 0, &kp);
+  if (e != hipSuccess) return hip_error(e, "hipGraphAddKernelNode(reset)");
+  sbbf_status st = set_insert_nodes(p, d_ins, info, true);
+  if (st != SBBF_OK) return st;
+  if ((st = set_lookup_node(p, d_look, d_out, info, true)) != SBBF_OK) return st;
   e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_error(e, "hipGraphInstantiate");
   p.g_ins = d_ins;
@@ -515,27 +810,9 @@ static sbbf_status build_graph(sbbf_group *g, const uint64_t *d_ins, const uint6
 static sbbf_status update_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
                                 const sbbf_device_info &info) {
   GroupedPlanHost &p = g->plan;
-  hipKernelNodeParams kp;
-  memset(&kp, 0, sizeof(kp));
-  const uint64_t *ins_arg = d_ins;
-  void *ins_args[] = {(void *)&p.pd, (void *)&ins_arg};
-  kp.func = (void *)grouped_insert_kernel;
-  kp.gridDim = insert_grid(info, p);
-  kp.blockDim = dim3(kInsertThreads);
-  kp.sharedMemBytes = (unsigned)p.insert_lds;
-  kp.kernelParams = ins_args;
-  hipError_t e = hipGraphExecKernelNodeSetParams(p.exec, p.n_ins, &kp);
-  if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams(insert)");
-  const uint64_t *look_arg = d_look;
-  uint8_t *out_arg = d_out;
-  void *look_args[] = {(void *)&p.pd, (void *)&look_arg, (void *)&out_arg};
-  kp.func = (void *)lookup_func(p.cfg.lookup_unroll);
-  kp.gridDim = lookup_grid(info, p);
-  kp.blockDim = dim3(p.cfg.lookup_threads);
-  kp.sharedMemBytes = 0;
-  kp.kernelParams = look_args;
-  e = hipGraphExecKernelNodeSetParams(p.exec, p.n_look, &kp);
-  if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams(lookup)");
+  sbbf_status st = set_insert_nodes(p, d_ins, info, false);
+  if (st != SBBF_OK) return st;
+  if ((st = set_lookup_node(p, d_look, d_out, info, false)) != SBBF_OK) return st;
   p.g_ins = d_ins;
   p.g_look = d_look;
   p.g_out = d_out;

@@ -114,4 +114,51 @@ __device__ __forceinline__ uint64_t fold_pass(uint64_t m, int p) {
   return (t & 0x0101010101010101ull) << p;
 }
 
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// and stores stay in flight across it. For workgroups whose threads share
+// data through LDS only.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts
+// (Hillis-Steele inside each row of 16 lanes) and the two row broadcasts.
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+  return x;
+}
+
+// Exclusive prefix over a workgroup of T threads (a multiple of 64, at most
+// 1024), thread t holding the R consecutive entries t*R .. t*R+R-1 in c[]:
+// returns the sum of all entries before its first (and the sum of all in
+// *total). `wsum` is 16 words of LDS; contains one barrier, and wsum may be
+// rewritten only after a further barrier.
+template <int R, uint32_t T = 1024>
+__device__ __forceinline__ uint32_t block_scan_owned(const uint32_t (&c)[R], uint32_t *wsum,
+                                                     uint32_t *total = nullptr) {
+  uint32_t sum = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) sum += c[r];
+  const uint32_t incl = wave_inclusive_scan(sum);
+  const uint32_t wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 63u) wsum[wave] = incl;
+  lds_barrier();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < T / 64u; ++w) {
+    const uint32_t v = wsum[w];
+    before += w < wave ? v : 0u;
+    all += v;
+  }
+  if (total) *total = all;
+  return before + incl - sum;
+}
+
 }  // namespace sbbf

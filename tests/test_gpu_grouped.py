@@ -141,7 +141,17 @@ def test_grouped_autotune(P, small, tmp_path):
     g.close()
 
 
-def test_grouped_edge_cases(P):
+EDGE_CONFIGS = [
+    None,
+    # 64-block slices: the 9,000-block filter is partitioned into 141 slices,
+    # the 70,000-block one has 1,094 slices (more than one partition chunk can
+    # sort) and is inserted by stream tiles
+    dict(insert_lds_bytes=2048, insert_slice_shift=6),
+]
+
+
+@pytest.mark.parametrize("cfg", EDGE_CONFIGS, ids=["default", "small-slices"])
+def test_grouped_edge_cases(P, cfg):
     # empty filters (no inserts, no lookups), a single huge-but-sparse filter,
     # and filters whose counts are not multiples of anything
     blocks = np.array([1, 5000, 9000, 3, 70000], dtype=np.int64)
@@ -153,7 +163,7 @@ def test_grouped_edge_cases(P):
     look = splitmix64_stream(701, int(look_off[-1]))
     look[:3] = ins[:3]
     filters = [P.Filter(int(b)) for b in blocks]
-    g = P.Group(filters, ins_off, look_off)
+    g = P.Group(filters, ins_off, look_off, cfg)
     out = torch.empty(int(look_off[-1]), dtype=torch.uint8, device="cuda")
     g.run(dev(ins), dev(look), out)
     torch.cuda.synchronize()
@@ -189,4 +199,29 @@ def test_grouped_full_workload(P):
     torch.cuda.synchronize()
     assert torch.equal(out, out2)
     assert g.digest(out2) == digest
+    g.close()
+
+
+def test_grouped_many_runs_per_slice(P):
+    """A partitioned filter with more insert chunks than one batch of runs a
+    slice tile stages at a time (7,400,000 keys: 1,033 chunks of 7,168, so
+    every slice has more than 1,024 runs), next to a small filter."""
+    blocks = np.array([300_000, 40], dtype=np.int64)
+    n_ins = np.array([7_400_000, 1_000], dtype=np.int64)
+    n_look = np.array([50_000, 3_000], dtype=np.int64)
+    ins_off = np.concatenate([[0], np.cumsum(n_ins)])
+    look_off = np.concatenate([[0], np.cumsum(n_look)])
+    ins = splitmix64_stream(710, int(ins_off[-1]))
+    look = splitmix64_stream(711, int(look_off[-1]))
+    look[:1000] = ins[:1000]
+    filters = [P.Filter(int(b)) for b in blocks]
+    g = P.Group(filters, ins_off, look_off)
+    out = torch.empty(int(look_off[-1]), dtype=torch.uint8, device="cuda")
+    g.run(dev(ins), dev(look), out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    for f, B in enumerate(blocks.tolist()):
+        ref = oracle.build_filter(B, ins[ins_off[f]:ins_off[f + 1]])
+        assert np.array_equal(filters[f].words.cpu().numpy().view(np.uint32), ref), f
+        assert np.array_equal(res[look_off[f]:look_off[f + 1]], oracle.lookup(ref, B, look[look_off[f]:look_off[f + 1]]))
     g.close()
