@@ -183,6 +183,28 @@ def _ensure_built():
         build.build()
 
 
+def _select(P, torch, f, lookups, ref_out, launch, reps=5):
+    """Lookup with stream compaction over the step's lookups (the filter as
+    the last step left it): time per call, and the indices must equal the
+    positions of the byte lookup's ones."""
+    n = lookups.numel()
+    idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    P.sbbf_lookup_select(f.handle, lookups, idx, cnt, launch=launch)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        P.sbbf_lookup_select(f.handle, lookups, idx, cnt, launch=launch)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    c = int(cnt.item())
+    ref = torch.nonzero(ref_out).flatten()
+    ok = c == ref.numel() and bool(torch.equal(idx[:c].to(torch.int64), ref))
+    return {"keys": n, "selected": c, "ms": ms, "gkeys_per_s": n / (ms / 1e3) / 1e9, "matches_lookup": ok}
+
+
 def _cpu_baseline(w):
     """The oracle, untuned, on the host: all inserts into the full-size filter,
     then the first half of the lookups. One thread."""
@@ -373,6 +395,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -459,6 +482,7 @@ def main(argv=None):
     fp = int(out[~w.is_member].sum().item())
     members_ok = bool(out[w.is_member].all().item())
     n_non = int((~w.is_member).sum().item())
+    select = None if a.no_select else _select(P, torch, f, w.lookups, out, look_launch)
 
     ins_gbps = INSERT_BYTES_PER_KEY * n_ins / (insert_ms / 1e3) / 1e9
     look_gbps = LOOKUP_BYTES_PER_KEY * n_look / (lookup_ms / 1e3) / 1e9
@@ -510,6 +534,8 @@ def main(argv=None):
         "paper_context": PAPER_CONTEXT,
         "kernel_source_digest": _kernel_source_digest(),
     }
+    if select is not None:
+        result["select"] = select
     if not a.no_ceilings:
         c = _ceilings(P, torch, w, look_launch, ins_launch)
         c["lookup_frac_of_gather"] = result["lookup_gkeys_per_s"] / c["gather_gkeys_per_s"]

@@ -184,6 +184,20 @@ sbbf_status sbbf_lookup_batch_bits(const sbbf_filter *f, const uint64_t *d_hashe
 sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
                                  uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s);
 
+/* Lookup with stream compaction: writes, in ascending order, the indices i of
+ * the hashes the filter reports present (appendix figure, lookup routine) to
+ * d_indices[0 .. count) and count to *d_count. The paper names database
+ * engines as the filter's users (introduction; the discussion after the
+ * evaluation table); there a lookup decides which rows go on, and this entry
+ * point returns just those rows' indices. d_indices holds room for up to n
+ * indices (uint32, 4-byte aligned,
+ * caller-owned); d_count is one uint64 in device memory (8-byte aligned),
+ * written by the device (0 when n == 0). n < 2^32. cfg chooses the lookup
+ * strategy and launch shape as for sbbf_lookup_batch_ex (NULL = defaults).
+ * Uses a stream-ordered workspace of about n / 8 bytes. */
+sbbf_status sbbf_lookup_select(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint32_t *d_indices,
+                               uint64_t *d_count, const sbbf_launch *cfg, sbbf_stream s);
+
 /* ---- measurement kernels (same access pattern, no filter arithmetic) ------- */
 
 /* Random 32-byte gather ceiling: for each hash, read the 32-byte block

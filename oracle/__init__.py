@@ -141,6 +141,12 @@ def lookup_bits(words: np.ndarray, num_blocks: int, hashes) -> np.ndarray:
     return out
 
 
+def select(words: np.ndarray, num_blocks: int, hashes) -> np.ndarray:
+    """Ascending indices of the hashes the lookup reports present (the lookup
+    routine of the appendix figure, then the positions of its ones)."""
+    return np.flatnonzero(lookup(words, num_blocks, hashes)).astype(np.uint32)
+
+
 def popcount(words: np.ndarray) -> int:
     w = np.ascontiguousarray(words, dtype=np.uint32)
     return int(_load().sbbf_oracle_popcount(_ptr(w, _U32P), w.size))

@@ -223,6 +223,26 @@ def sbbf_lookup_batch_ex(f: int, hashes: torch.Tensor, out: torch.Tensor | None 
     return bits
 
 
+def sbbf_lookup_select(f: int, hashes: torch.Tensor, indices: torch.Tensor | None = None,
+                       count: torch.Tensor | None = None, launch=None, stream=None):
+    """Indices (int32 tensor of room n; entries [0, count) valid, ascending)
+    of the hashes the filter reports present, and count (one int64 on the
+    device). Nothing is synchronised."""
+    p, n = _hashes(hashes)
+    if indices is None:
+        indices = torch.empty(max(n, 1), dtype=torch.int32, device=hashes.device)
+    elif indices.dtype not in (torch.int32, torch.uint32) or not indices.is_cuda or not indices.is_contiguous() \
+            or indices.numel() < n:
+        raise ValueError("indices must be a contiguous int32 CUDA tensor of at least n entries")
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=hashes.device)
+    elif count.dtype != torch.int64 or not count.is_cuda or count.numel() < 1:
+        raise ValueError("count must be an int64 CUDA tensor")
+    _check(_L().sbbf_lookup_select(f, p, n, ctypes.c_void_p(indices.data_ptr()), ctypes.c_void_p(count.data_ptr()),
+                                   _launch(launch), _stream(stream)))
+    return indices, count
+
+
 # ---- measurement kernels ----------------------------------------------------------------
 
 def sbbf_bench_gather(buf: torch.Tensor, num_blocks: int, hashes: torch.Tensor, out: torch.Tensor,
@@ -452,6 +472,12 @@ class Filter:
     def lookup_bits(self, hashes, bits=None, launch=None, stream=None):
         return sbbf_lookup_batch_ex(self.handle, hashes, bits=bits if bits is not None else _out_bits(
             None, hashes.numel(), hashes.device), launch=launch, stream=stream)
+
+    def select(self, hashes, launch=None, stream=None):
+        """Ascending indices of the hashes reported present (synchronises to
+        read the count)."""
+        idx, cnt = sbbf_lookup_select(self.handle, hashes, launch=launch, stream=stream)
+        return idx[: int(cnt.item())]
 
     def clear(self, stream=None):
         sbbf_clear(self.handle, stream)

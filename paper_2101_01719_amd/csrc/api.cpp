@@ -429,6 +429,28 @@ sbbf_status sbbf_lookup_batch(const sbbf_filter *f, const uint64_t *d_hashes, si
   return sbbf_lookup_batch_ex(f, d_hashes, n, d_out, nullptr, nullptr, s);
 }
 
+sbbf_status sbbf_lookup_select(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint32_t *d_indices,
+                               uint64_t *d_count, const sbbf_launch *cfg, sbbf_stream s) {
+  sbbf_status st = check_batch(f, d_hashes, n, d_indices, "d_indices", 4);
+  if (st != SBBF_OK) return st;
+  if (!d_count) return set_error(SBBF_EINVAL, "d_count is NULL");
+  if (!aligned(d_count, 8)) return set_error(SBBF_EINVAL, "d_count must be 8-byte aligned");
+  if ((uint64_t)n > 0xFFFFFFFFull) return set_error(SBBF_EINVAL, "one call takes fewer than 2^32 keys");
+  hipStream_t stream = (hipStream_t)s;
+  if (n == 0) return hip_error(launch_fill(reinterpret_cast<uint32_t *>(d_count), 2, 0u, stream), "select count");
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  void *ws = nullptr;
+  hipError_t e = workspace_alloc(&ws, select_workspace_bytes(n), stream, info->device);
+  if (e != hipSuccess) return hip_error(e, "hipMallocAsync(select workspace)");
+  st = sbbf_lookup_batch_ex(f, d_hashes, n, nullptr, select_bits(ws), cfg, s);
+  if (st == SBBF_OK) st = hip_error(launch_select(n, ws, d_indices, reinterpret_cast<unsigned long long *>(d_count), stream),
+                                    "select");
+  const hipError_t e2 = hipFreeAsync(ws, stream);
+  if (st != SBBF_OK) return st;
+  return hip_error(e2, "hipFreeAsync(select workspace)");
+}
+
 sbbf_status sbbf_lookup_batch_bits(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint32_t *d_bits,
                                    sbbf_stream s) {
   return sbbf_lookup_batch_ex(f, d_hashes, n, nullptr, d_bits, nullptr, s);

@@ -66,6 +66,14 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
                                      uint32_t *out_bits, hipStream_t stream);
 
+// Stream compaction of a lookup bitmap (select.hip): the workspace starts
+// with the bitmap (ceil(n / 32) words, select_bits()) the lookup writes;
+// launch_select writes the ascending indices of set bits and their count.
+uint64_t select_workspace_bytes(uint64_t n);
+uint32_t *select_bits(void *workspace);
+hipError_t launch_select(uint64_t n, void *workspace, uint32_t *indices, unsigned long long *count,
+                         hipStream_t stream);
+
 // The grouped C ABI (sbbf_grouped_*) is implemented in grouped.hip.
 
 hipError_t launch_bench_gather(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n,

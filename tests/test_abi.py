@@ -83,6 +83,7 @@ def test_argument_errors_without_device(lib):
     assert lib.sbbf_destroy(None) == 1
     assert lib.sbbf_insert_batch(None, None, 10, None) == 1
     assert lib.sbbf_lookup_batch(None, None, 10, None, None) == 1
+    assert lib.sbbf_lookup_select(None, None, 10, None, None, None, None) == 1
     assert lib.sbbf_device_query(None) == 1
 
 

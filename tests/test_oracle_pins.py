@@ -223,6 +223,26 @@ def test_lookup_bits_packing():
     assert (np.unpackbits(bits.view(np.uint8), bitorder="little")[h.size:] == 0).all()
 
 
+def test_select_definition():
+    """select = the ascending positions of the lookup's ones: every inserted
+    hash is selected (no false negatives), nothing else but the lookup's
+    false positives, and a brute-force tiny case written out by hand."""
+    B = 13
+    h = splitmix64_stream(53, 4000)
+    words = oracle.build_filter(B, h[:500])
+    sel = oracle.select(words, B, h)
+    assert sel.dtype == np.uint32
+    assert np.all(np.diff(sel.astype(np.int64)) > 0)          # ascending, unique
+    assert np.isin(np.arange(500), sel).all()                  # members
+    assert sel.size == int(oracle.lookup(words, B, h).sum())
+    for i in range(h.size):                                    # one by one
+        assert (i in set(sel.tolist())) == oracle.contains(words, B, int(h[i]))
+    # all-ones filter selects every index; the empty filter none
+    ones = np.full(8 * B, 0xFFFFFFFF, dtype=np.uint32)
+    assert np.array_equal(oracle.select(ones, B, h), np.arange(h.size, dtype=np.uint32))
+    assert oracle.select(oracle.new_filter(B), B, h).size == 0
+
+
 # --- whole workloads against the paper's code and the paper's formula ------------
 
 def _run(name):
