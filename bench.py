@@ -205,6 +205,25 @@ def _select(P, torch, f, lookups, ref_out, launch, reps=5):
     return {"keys": n, "selected": c, "ms": ms, "gkeys_per_s": n / (ms / 1e3) / 1e9, "matches_lookup": ok}
 
 
+def _union(P, torch, f, reps=10):
+    """Union of the step's filter into a second filter of the same size:
+    time per call and HBM rate (two filters read, one written)."""
+    g = P.Filter(P.sbbf_num_blocks(f.handle))
+    g.union(f)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(g.words, f.words))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.union(f)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 3 * 32 * P.sbbf_num_blocks(f.handle)
+    g.close()
+    return {"filter_bytes": nbytes // 3, "ms": ms, "GBps": nbytes / (ms / 1e3) / 1e9, "correct": ok}
+
+
 def _cpu_baseline(w):
     """The oracle, untuned, on the host: all inserts into the full-size filter,
     then the first half of the lookups. One thread."""
@@ -395,7 +414,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
-    ap.add_argument("--no-select", action="store_true")
+    ap.add_argument("--no-select", action="store_true", help="skip the select and union measurements")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -483,6 +502,7 @@ def main(argv=None):
     members_ok = bool(out[w.is_member].all().item())
     n_non = int((~w.is_member).sum().item())
     select = None if a.no_select else _select(P, torch, f, w.lookups, out, look_launch)
+    union = None if a.no_select else _union(P, torch, f)
 
     ins_gbps = INSERT_BYTES_PER_KEY * n_ins / (insert_ms / 1e3) / 1e9
     look_gbps = LOOKUP_BYTES_PER_KEY * n_look / (lookup_ms / 1e3) / 1e9
@@ -536,6 +556,8 @@ def main(argv=None):
     }
     if select is not None:
         result["select"] = select
+    if union is not None:
+        result["union"] = union
     if not a.no_ceilings:
         c = _ceilings(P, torch, w, look_launch, ins_launch)
         c["lookup_frac_of_gather"] = result["lookup_gkeys_per_s"] / c["gather_gkeys_per_s"]

@@ -137,6 +137,16 @@ sbbf_status sbbf_device_query(sbbf_device_info *out);
 /* Blocks for n keys at bits_per_key bits each: max(1, ceil(n * bits_per_key / 256)).
  * Returns 0 when the result would exceed 2^32 - 1 or bits_per_key <= 0. */
 uint64_t sbbf_blocks_for(uint64_t n, double bits_per_key);
+/* The paper's false-positive model (analysis section, the Poisson-sum
+ * equation): F(a) = sum over i >= 0 of Poisson_a(i) * (1 - (31/32)^i)^8 for
+ * a mean of a = keys_per_block distinct hashes per block; computed in double. */
+double sbbf_fpr_model(double keys_per_block);
+/* Sizing from a target rate by inverting that model: the smallest number of
+ * blocks B >= 1 with F(n / B) <= fpr. Returns 0 (and sets sbbf_last_error)
+ * when fpr is not in (0, 1) or more than 2^32 - 1 blocks would be needed.
+ * The paper's useful band of rates is about 0.4 % to 19 % (introduction;
+ * analysis section). */
+uint64_t sbbf_blocks_for_fpr(uint64_t n, double fpr);
 
 /* ---- single filter --------------------------------------------------------- */
 
@@ -160,6 +170,27 @@ void *sbbf_device_words(const sbbf_filter *f);
  * with pinned memory the caller synchronises before touching host_dst. */
 sbbf_status sbbf_copy_words_to_host(const sbbf_filter *f, void *host_dst, sbbf_stream s);
 sbbf_status sbbf_copy_words_from_host(sbbf_filter *f, const void *host_src, sbbf_stream s);
+
+/* Union: dst |= src word by word, so dst then reports present every hash
+ * inserted into either (a filter is the OR of its keys' masks: appendix
+ * figure, insert routine). Both filters must have the same num_blocks
+ * (SBBF_EINVAL otherwise); dst == src is a no-op. Enqueued on the stream. */
+sbbf_status sbbf_union(sbbf_filter *dst, const sbbf_filter *src, sbbf_stream s);
+
+/* Serialized form of a filter: a 32-byte header (8 bytes "SBBF256\0",
+ * uint32 version 1, uint32 seed order 1 = word j uses seed j in the
+ * little-endian lane order of the appendix figure's constants, uint32
+ * num_blocks, uint32 word size 4, 8 reserved zero bytes; all little-endian),
+ * then the 32 * num_blocks bytes of the filter image. */
+uint64_t sbbf_serialized_bytes(uint32_t num_blocks);
+/* Write the serialized form to host memory of at least
+ * sbbf_serialized_bytes(num_blocks) bytes; waits for the stream (the image
+ * is the filter after all work enqueued before the call). */
+sbbf_status sbbf_serialize(const sbbf_filter *f, void *host_dst, size_t capacity, sbbf_stream s);
+/* A new library-owned filter from a serialized form of exactly `size` bytes.
+ * SBBF_EINVAL on a bad magic, size or block count, SBBF_EUNSUPPORTED on
+ * another version, word size or seed order. Synchronous. */
+sbbf_status sbbf_deserialize(const void *host_src, size_t size, sbbf_filter **out);
 
 /* The strategy SBBF_INSERT_AUTO / SBBF_LOOKUP_AUTO picks for a batch of n
  * hashes on this filter and the current device (0 on a bad argument). */

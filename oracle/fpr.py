@@ -9,8 +9,8 @@ present when all eight of its lane bits are set:
     F(a) = sum_{i >= 0} Poisson_a(i) * (1 - (31/32)**i)**8,   a = 256 n / m
 
 (n distinct hashes, m filter bits). All arithmetic is fp64. The Poisson sum is
-truncated once i exceeds a + 40 sqrt(a) + 50, where the remaining tail weight
-is far below fp64 resolution.
+taken over i within 40 sqrt(a) + 50 of a; the weight outside is far below fp64
+resolution.
 
 For comparison the standard Bloom filter with the same n and m and the best
 integer number of hash functions k has false-positive probability
@@ -23,11 +23,14 @@ import math
 
 
 def _poisson_terms(a: float):
-    """Yield (i, Poisson_a(i)) for i = 0 .. a + 40 sqrt(a) + 50."""
+    """Yield (i, Poisson_a(i)) for i within 40 sqrt(a) + 50 of a (the weight
+    of the terms outside is far below fp64 resolution)."""
     if a < 0:
         raise ValueError("load must be non-negative")
-    stop = int(math.ceil(a + 40.0 * math.sqrt(a) + 50.0))
-    for i in range(stop + 1):
+    w = 40.0 * math.sqrt(a) + 50.0
+    start = max(0, int(math.floor(a - w)))
+    stop = int(math.ceil(a + w))
+    for i in range(start, stop + 1):
         # log-space for stability at large a
         if a == 0.0:
             p = 1.0 if i == 0 else 0.0
@@ -90,3 +93,26 @@ def load_for_fpr(target: float, lo: float = 1e-3, hi: float = 256.0) -> float:
         else:
             hi = mid
     return 0.5 * (lo + hi)
+
+
+def blocks_for_fpr(n: int, fpr: float, max_blocks: int = 2**32 - 1) -> int:
+    """Smallest number of blocks B >= 1 with sbbf_fpr(n / B) <= fpr, by
+    bisection (F grows with the load n / B). 0 when even max_blocks is not
+    enough."""
+    if not (0.0 < fpr < 1.0):
+        raise ValueError("fpr must be in (0, 1)")
+    if n == 0:
+        return 1
+    if sbbf_fpr(n / max_blocks) > fpr:
+        return 0
+    if sbbf_fpr(float(n)) <= fpr:
+        return 1
+    lo, hi = 1, max_blocks
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if sbbf_fpr(n / mid) <= fpr:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+

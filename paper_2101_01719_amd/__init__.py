@@ -110,6 +110,17 @@ def sbbf_blocks_for(n: int, bits_per_key: float) -> int:
     return int(_L().sbbf_blocks_for(n, bits_per_key))
 
 
+def sbbf_fpr_model(keys_per_block: float) -> float:
+    return float(_L().sbbf_fpr_model(keys_per_block))
+
+
+def sbbf_blocks_for_fpr(n: int, fpr: float) -> int:
+    b = int(_L().sbbf_blocks_for_fpr(n, fpr))
+    if b == 0:
+        raise SbbfError(SBBF_EINVAL, _L().sbbf_last_error().decode())
+    return b
+
+
 # ---- single filter ------------------------------------------------------------------
 
 def sbbf_create(num_blocks: int) -> int:
@@ -154,6 +165,29 @@ def sbbf_copy_words_from_host(f: int, host: torch.Tensor, stream=None) -> None:
     if host.is_cuda or not host.is_contiguous() or host.numel() * host.element_size() != 32 * sbbf_num_blocks(f):
         raise ValueError("host buffer must be a contiguous CPU tensor of 32 * num_blocks bytes")
     _check(_L().sbbf_copy_words_from_host(f, ctypes.c_void_p(host.data_ptr()), _stream(stream)))
+
+
+def sbbf_union(dst: int, src: int, stream=None) -> None:
+    _check(_L().sbbf_union(dst, src, _stream(stream)))
+
+
+def sbbf_serialized_bytes(num_blocks: int) -> int:
+    return int(_L().sbbf_serialized_bytes(num_blocks))
+
+
+def sbbf_serialize(f: int, stream=None) -> bytes:
+    """The serialized form of the filter (header + byte image) as bytes."""
+    size = sbbf_serialized_bytes(sbbf_num_blocks(f))
+    buf = ctypes.create_string_buffer(size)
+    _check(_L().sbbf_serialize(f, ctypes.cast(buf, ctypes.c_void_p), size, _stream(stream)))
+    return buf.raw
+
+
+def sbbf_deserialize(data: bytes) -> int:
+    """A new library-owned filter handle from a serialized form."""
+    h = ctypes.c_void_p()
+    _check(_L().sbbf_deserialize(ctypes.c_char_p(data), len(data), ctypes.byref(h)))
+    return h.value
 
 
 def sbbf_auto_insert_strategy(f: int, n: int) -> int:
@@ -472,6 +506,14 @@ class Filter:
     def lookup_bits(self, hashes, bits=None, launch=None, stream=None):
         return sbbf_lookup_batch_ex(self.handle, hashes, bits=bits if bits is not None else _out_bits(
             None, hashes.numel(), hashes.device), launch=launch, stream=stream)
+
+    def union(self, other, stream=None):
+        """self |= other (same number of blocks)."""
+        sbbf_union(self.handle, other.handle, stream)
+        return self
+
+    def serialize(self, stream=None) -> bytes:
+        return sbbf_serialize(self.handle, stream)
 
     def select(self, hashes, launch=None, stream=None):
         """Ascending indices of the hashes reported present (synchronises to

@@ -94,6 +94,12 @@ SIGNATURES = {
     "sbbf_last_error": (ctypes.c_char_p, []),
     "sbbf_device_query": (c_int, [ctypes.POINTER(sbbf_device_info)]),
     "sbbf_blocks_for": (c_u64, [c_u64, ctypes.c_double]),
+    "sbbf_fpr_model": (ctypes.c_double, [ctypes.c_double]),
+    "sbbf_blocks_for_fpr": (c_u64, [c_u64, ctypes.c_double]),
+    "sbbf_union": (c_int, [c_vp, c_vp, c_vp]),
+    "sbbf_serialized_bytes": (c_u64, [c_u32]),
+    "sbbf_serialize": (c_int, [c_vp, c_vp, c_size, c_vp]),
+    "sbbf_deserialize": (c_int, [c_vp, c_size, ctypes.POINTER(c_vp)]),
     "sbbf_create": (c_int, [c_u32, ctypes.POINTER(c_vp)]),
     "sbbf_create_wrapped": (c_int, [c_vp, c_u32, ctypes.POINTER(c_vp)]),
     "sbbf_destroy": (c_int, [c_vp]),

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <new>
@@ -220,6 +221,117 @@ sbbf_status sbbf_clear(sbbf_filter *f, sbbf_stream s) {
 }
 
 uint32_t sbbf_num_blocks(const sbbf_filter *f) { return f ? f->num_blocks : 0; }
+
+// ---- sizing from a target false-positive rate, union, serialization --------
+
+// False-positive model of the analysis section: a block holding i hashes has
+// a given bit of a lane set with probability 1 - (31/32)^i, and a non-member
+// is reported present when all eight of its lane bits are set; with block
+// loads Poisson(a) distributed, F(a) = sum over i of Poisson_a(i) times
+// (1 - (31/32)^i)^8. Summed in double over i within 40 sqrt(a) + 50 of a,
+// outside which the Poisson weight is far below double resolution.
+static double fpr_of_load(double a) {
+  if (!(a > 0.0)) return 0.0;
+  const double w = 40.0 * std::sqrt(a) + 50.0;
+  const double lo = std::max(1.0, std::floor(a - w)), hi = std::ceil(a + w);
+  const double la = std::log(a), l = std::log(31.0 / 32.0);
+  double s = 0.0;
+  for (double i = lo; i <= hi; i += 1.0) {
+    const double p = std::exp(-a + i * la - std::lgamma(i + 1.0));
+    const double q = -std::expm1(i * l);  // 1 - (31/32)^i
+    const double q2 = q * q, q4 = q2 * q2;
+    s += p * (q4 * q4);
+  }
+  return s;
+}
+
+double sbbf_fpr_model(double keys_per_block) { return fpr_of_load(keys_per_block); }
+
+uint64_t sbbf_blocks_for_fpr(uint64_t n, double fpr) {
+  if (!(fpr > 0.0 && fpr < 1.0)) {
+    set_error(SBBF_EINVAL, "fpr must be in (0, 1)");
+    return 0;
+  }
+  if (n == 0) return 1;
+  const uint64_t max_b = 0xFFFFFFFFull;
+  if (fpr_of_load((double)n / (double)max_b) > fpr) {
+    set_error(SBBF_EINVAL, "the target rate needs more than 2^32 - 1 blocks for this many keys");
+    return 0;
+  }
+  if (fpr_of_load((double)n) <= fpr) return 1;
+  uint64_t lo = 1, hi = max_b;  // F(n / lo) > fpr >= F(n / hi); F grows with the load
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (fpr_of_load((double)n / (double)mid) <= fpr)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return hi;
+}
+
+sbbf_status sbbf_union(sbbf_filter *dst, const sbbf_filter *src, sbbf_stream s) {
+  if (!dst || !src) return set_error(SBBF_EINVAL, "filter is NULL");
+  if (dst->num_blocks != src->num_blocks) return set_error(SBBF_EINVAL, "filters differ in num_blocks");
+  if (dst->words == src->words) return SBBF_OK;
+  return hip_error(launch_union(dst->words, src->words, (uint64_t)dst->num_blocks * 8u, (hipStream_t)s), "union");
+}
+
+namespace {
+// Serialized filter: a 32-byte header, then the filter's byte image.
+struct SerialHeader {
+  char magic[8];        // "SBBF256" and a zero byte
+  uint32_t version;     // 1
+  uint32_t seed_order;  // 1: word j uses seed j of the little-endian lane order of the appendix figure's constants
+  uint32_t num_blocks;
+  uint32_t word_bytes;  // 4
+  uint64_t reserved;    // 0
+};
+static_assert(sizeof(SerialHeader) == 32, "header is 32 bytes");
+const char kMagic[8] = {'S', 'B', 'B', 'F', '2', '5', '6', '\0'};
+}  // namespace
+
+uint64_t sbbf_serialized_bytes(uint32_t num_blocks) { return 32u + (uint64_t)num_blocks * 32u; }
+
+sbbf_status sbbf_serialize(const sbbf_filter *f, void *host_dst, size_t capacity, sbbf_stream s) {
+  if (!f || !host_dst) return set_error(SBBF_EINVAL, "filter or host_dst is NULL");
+  if (capacity < sbbf_serialized_bytes(f->num_blocks)) return set_error(SBBF_EINVAL, "host_dst is too small");
+  SerialHeader h;
+  memcpy(h.magic, kMagic, 8);
+  h.version = 1;
+  h.seed_order = 1;
+  h.num_blocks = f->num_blocks;
+  h.word_bytes = 4;
+  h.reserved = 0;
+  memcpy(host_dst, &h, sizeof(h));
+  hipError_t e = hipMemcpyAsync(static_cast<char *>(host_dst) + sizeof(h), f->words, (size_t)f->num_blocks * 32u,
+                                hipMemcpyDeviceToHost, (hipStream_t)s);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(serialize)");
+  return hip_error(hipStreamSynchronize((hipStream_t)s), "hipStreamSynchronize(serialize)");
+}
+
+sbbf_status sbbf_deserialize(const void *host_src, size_t size, sbbf_filter **out) {
+  if (!host_src || !out) return set_error(SBBF_EINVAL, "host_src or out is NULL");
+  if (size < sizeof(SerialHeader)) return set_error(SBBF_EINVAL, "too short for a header");
+  SerialHeader h;
+  memcpy(&h, host_src, sizeof(h));
+  if (memcmp(h.magic, kMagic, 8) != 0) return set_error(SBBF_EINVAL, "not a serialized filter (magic)");
+  if (h.version != 1 || h.word_bytes != 4) return set_error(SBBF_EUNSUPPORTED, "unsupported format version");
+  if (h.seed_order != 1) return set_error(SBBF_EUNSUPPORTED, "filter written with another seed order");
+  if (h.num_blocks == 0) return set_error(SBBF_EINVAL, "num_blocks is 0");
+  if (size != sbbf_serialized_bytes(h.num_blocks)) return set_error(SBBF_EINVAL, "size does not match num_blocks");
+  sbbf_filter *f = nullptr;
+  sbbf_status st = sbbf_create(h.num_blocks, &f);
+  if (st != SBBF_OK) return st;
+  hipError_t e = hipMemcpy(f->words, static_cast<const char *>(host_src) + sizeof(h), (size_t)h.num_blocks * 32u,
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    sbbf_destroy(f);
+    return hip_error(e, "hipMemcpy(deserialize)");
+  }
+  *out = f;
+  return SBBF_OK;
+}
 
 sbbf_status sbbf_copy_words_to_host(const sbbf_filter *f, void *host_dst, sbbf_stream s) {
   if (!f || !host_dst) return set_error(SBBF_EINVAL, "filter or host_dst is NULL");

@@ -51,6 +51,8 @@ hipError_t launch_insert_atomic64(const uint64_t *hashes, uint64_t n, uint32_t *
 hipError_t launch_insert_lds(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                              const Shape &shape, hipStream_t stream);
 hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipStream_t stream);
+// dst[i] |= src[i] for i < num_words (a multiple of 8; both 32-byte aligned).
+hipError_t launch_union(uint32_t *dst, const uint32_t *src, uint64_t num_words, hipStream_t stream);
 
 // Partitioned insert and lookup (partition_kernels.hip). Slices hold
 // 2^slice_shift blocks (at most partition_max_slices() slices); one launch

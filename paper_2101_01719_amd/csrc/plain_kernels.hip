@@ -221,6 +221,16 @@ insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__r
 
 // ---- fill -------------------------------------------------------------------------
 
+// dst |= src over whole filters (both 32-byte aligned, num_words a multiple
+// of 8): 16-byte loads and stores, grid-stride.
+__global__ void __launch_bounds__(256) union_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, uint64_t n4) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const uint4 a = dst[i], b = src[i];
+    dst[i] = make_uint4(a.x | b.x, a.y | b.y, a.z | b.z, a.w | b.w);
+  }
+}
+
 __global__ void __launch_bounds__(256) fill_kernel(uint32_t *__restrict__ words, uint64_t num_words, uint32_t value) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t n4 = num_words / 4;
@@ -462,6 +472,16 @@ hipError_t launch_insert_atomic64(const uint64_t *hashes, uint64_t n, uint32_t *
 hipError_t launch_insert_lds(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                              const Shape &s, hipStream_t stream) {
   return insert_any(SBBF_INSERT_LDS, hashes, n, words, num_blocks, s, stream);
+}
+
+hipError_t launch_union(uint32_t *dst, const uint32_t *src, uint64_t num_words, hipStream_t stream) {
+  const uint64_t n4 = num_words / 4;
+  if (n4 == 0) return hipSuccess;
+  const uint64_t want = (n4 + 255) / 256;
+  const uint32_t grid = (uint32_t)(want < 8192 ? want : 8192);
+  hipLaunchKernelGGL(union_kernel, dim3(grid), dim3(256), 0, stream, reinterpret_cast<uint4 *>(dst),
+                     reinterpret_cast<const uint4 *>(src), n4);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill(uint32_t *words, uint64_t num_words, uint32_t value, hipStream_t stream) {

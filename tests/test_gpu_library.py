@@ -1,0 +1,101 @@
+"""Filter union and serialization against the oracle."""
+
+import struct
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from synth import splitmix64_stream  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2101_01719_amd as P
+
+    return P
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda")
+
+
+def words_of(f):
+    return f.words.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("B", [1, 7, 4096, 100_003])
+def test_union_is_the_filter_of_both_key_sets(P, B):
+    a_keys = splitmix64_stream(920, 3 * B)
+    b_keys = splitmix64_stream(921, 2 * B + 5)
+    fa, fb = P.Filter(B), P.Filter(B)
+    fa.insert(dev(a_keys))
+    fb.insert(dev(b_keys))
+    fa.union(fb)
+    torch.cuda.synchronize()
+    ref = oracle.build_filter(B, np.concatenate([a_keys, b_keys]))
+    assert np.array_equal(words_of(fa), ref)
+    assert np.array_equal(words_of(fb), oracle.build_filter(B, b_keys))  # src unchanged
+    fa.union(fa)  # self union: no-op
+    torch.cuda.synchronize()
+    assert np.array_equal(words_of(fa), ref)
+    fa.close()
+    fb.close()
+
+
+def test_union_full_size_and_errors(P):
+    B = 4_194_304
+    fa, fb = P.Filter(B), P.Filter(B)
+    fa.words.copy_(torch.randint(-2**31, 2**31 - 1, (8 * B,), dtype=torch.int32, device="cuda"))
+    fb.words.copy_(torch.randint(-2**31, 2**31 - 1, (8 * B,), dtype=torch.int32, device="cuda"))
+    ref = fa.words | fb.words
+    fa.union(fb)
+    torch.cuda.synchronize()
+    assert torch.equal(fa.words, ref)
+    small = P.Filter(5)
+    with pytest.raises(P.SbbfError):
+        fa.union(small)
+    for f in (fa, fb, small):
+        f.close()
+
+
+@pytest.mark.parametrize("B", [1, 33, 65_536])
+def test_serialize_round_trip(P, B):
+    keys = splitmix64_stream(930, 5 * B)
+    f = P.Filter(B)
+    f.insert(dev(keys))
+    blob = f.serialize()
+    assert len(blob) == P.sbbf_serialized_bytes(B) == 32 + 32 * B
+    magic, version, order, nb, wb, reserved = struct.unpack("<8sIIIIQ", blob[:32])
+    assert (magic, version, order, nb, wb, reserved) == (b"SBBF256\0", 1, 1, B, 4, 0)
+    ref = oracle.build_filter(B, keys)
+    assert np.array_equal(np.frombuffer(blob[32:], dtype="<u4"), ref)
+    h = P.sbbf_deserialize(blob)
+    assert P.sbbf_num_blocks(h) == B
+    probes = splitmix64_stream(931, 10_000)
+    m = min(100, keys.size)
+    probes[:m] = keys[:m]
+    got = P.sbbf_lookup_batch(h, dev(probes)).cpu().numpy()
+    assert np.array_equal(got, oracle.lookup(ref, B, probes))
+    P.sbbf_destroy(h)
+    f.close()
+
+
+def test_deserialize_rejects_bad_input(P):
+    f = P.Filter(3)
+    blob = bytearray(f.serialize())
+    f.close()
+    bad = [bytes(blob[:31]),                                  # short
+           b"XBBF256\0" + bytes(blob[8:]),                    # magic
+           bytes(blob[:8]) + struct.pack("<I", 2) + bytes(blob[12:]),   # version
+           bytes(blob[:12]) + struct.pack("<I", 2) + bytes(blob[16:]),  # seed order
+           bytes(blob[:16]) + struct.pack("<I", 0) + bytes(blob[20:]),  # zero blocks
+           bytes(blob[:16]) + struct.pack("<I", 4) + bytes(blob[20:]),  # size mismatch
+           bytes(blob) + b"\0"]                               # trailing byte
+    for b in bad:
+        with pytest.raises(P.SbbfError):
+            P.sbbf_deserialize(b)
