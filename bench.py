@@ -224,6 +224,37 @@ def _union(P, torch, f, reps=10):
     return {"filter_bytes": nbytes // 3, "ms": ms, "GBps": nbytes / (ms / 1e3) / 1e9, "correct": ok}
 
 
+def _keys(P, torch, f, w, ins_launch, look_launch, reps=5):
+    """The same step with the hashes taken as keys (hashed on the device as
+    they are loaded): clear, insert_keys, lookup_keys."""
+    out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    def step(rec):
+        f.clear()
+        if rec:
+            ev[0].record()
+        P.sbbf_insert_keys(f.handle, w.inserts, launch=ins_launch)
+        if rec:
+            ev[1].record()
+        P.sbbf_lookup_keys(f.handle, w.lookups, out, launch=look_launch)
+        if rec:
+            ev[2].record()
+
+    step(False)
+    torch.cuda.synchronize()
+    ins_ms = look_ms = 0.0
+    for _ in range(reps):
+        step(True)
+        torch.cuda.synchronize()
+        ins_ms += ev[0].elapsed_time(ev[1]) / reps
+        look_ms += ev[1].elapsed_time(ev[2]) / reps
+    members_ok = bool(out[w.is_member].all().item())
+    n = w.inserts.numel() + w.lookups.numel()
+    return {"insert_ms": ins_ms, "lookup_ms": look_ms, "gkeys_per_s": n / ((ins_ms + look_ms) / 1e3) / 1e9,
+            "members_all_found": members_ok}
+
+
 def _cpu_baseline(w):
     """The oracle, untuned, on the host: all inserts into the full-size filter,
     then the first half of the lookups. One thread."""
@@ -414,7 +445,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
-    ap.add_argument("--no-select", action="store_true", help="skip the select and union measurements")
+    ap.add_argument("--no-select", action="store_true", help="skip the select, union and key-hashing measurements")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -503,6 +534,7 @@ def main(argv=None):
     n_non = int((~w.is_member).sum().item())
     select = None if a.no_select else _select(P, torch, f, w.lookups, out, look_launch)
     union = None if a.no_select else _union(P, torch, f)
+    keys = None if a.no_select else _keys(P, torch, f, w, ins_launch, look_launch)
 
     ins_gbps = INSERT_BYTES_PER_KEY * n_ins / (insert_ms / 1e3) / 1e9
     look_gbps = LOOKUP_BYTES_PER_KEY * n_look / (lookup_ms / 1e3) / 1e9
@@ -558,6 +590,8 @@ def main(argv=None):
         result["select"] = select
     if union is not None:
         result["union"] = union
+    if keys is not None:
+        result["keys"] = keys
     if not a.no_ceilings:
         c = _ceilings(P, torch, w, look_launch, ins_launch)
         c["lookup_frac_of_gather"] = result["lookup_gkeys_per_s"] / c["gather_gkeys_per_s"]

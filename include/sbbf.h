@@ -215,6 +215,22 @@ sbbf_status sbbf_lookup_batch_bits(const sbbf_filter *f, const uint64_t *d_hashe
 sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
                                  uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s);
 
+/* ---- keys instead of hashes -------------------------------------------------
+ * The method hashes each key once to 64 bits and leaves the hash function
+ * open (construction paragraph). These entry points take 64-bit keys and
+ * hash them on the device as they are loaded, with sbbf_key_hash: the 64-bit
+ * finalizer of MurmurHash3 (A. Appleby), k ^= k >> 33; k *= 0xff51afd7ed558ccd;
+ * k ^= k >> 33; k *= 0xc4ceb9fe1a85ec53; k ^= k >> 33 (all mod 2^64), a
+ * bijection with full avalanche, so distinct keys give distinct hashes. The
+ * result is identical to inserting or looking up sbbf_key_hash(key). */
+uint64_t sbbf_key_hash(uint64_t key);
+/* As sbbf_insert_batch_ex on the hashes of n keys (cfg NULL = defaults). */
+sbbf_status sbbf_insert_keys(sbbf_filter *f, const uint64_t *d_keys, size_t n, const sbbf_launch *cfg,
+                             sbbf_stream s);
+/* As sbbf_lookup_batch_ex with d_out on the hashes of n keys. */
+sbbf_status sbbf_lookup_keys(const sbbf_filter *f, const uint64_t *d_keys, size_t n, uint8_t *d_out,
+                             const sbbf_launch *cfg, sbbf_stream s);
+
 /* Lookup with stream compaction: writes, in ascending order, the indices i of
  * the hashes the filter reports present (appendix figure, lookup routine) to
  * d_indices[0 .. count) and count to *d_count. The paper names database

@@ -58,6 +58,7 @@ def _load():
     lib.sbbf_oracle_conditional_fpr.restype = ctypes.c_double
     lib.sbbf_oracle_index_histogram.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _U64P]
     lib.sbbf_oracle_block_histogram.argtypes = [_U64P, ctypes.c_uint64, ctypes.c_uint32, _U64P]
+    lib.sbbf_oracle_key_hash.argtypes = [_U64P, ctypes.c_uint64, _U64P]
     _lib = lib
     return lib
 
@@ -169,6 +170,14 @@ def block_histogram(hashes, num_blocks: int) -> np.ndarray:
     count = np.zeros(int(num_blocks), dtype=np.uint64)
     _load().sbbf_oracle_block_histogram(_ptr(h, _U64P), h.size, num_blocks, _ptr(count, _U64P))
     return count
+
+
+def key_hash(keys) -> np.ndarray:
+    """The library's hash of 64-bit keys (the 64-bit finalizer of MurmurHash3)."""
+    k = _hashes(np.asarray(keys, dtype=np.uint64))
+    out = np.empty(k.size, dtype=np.uint64)
+    _load().sbbf_oracle_key_hash(_ptr(k, _U64P), k.size, _ptr(out, _U64P))
+    return out
 
 
 def build_filter(num_blocks: int, hashes) -> np.ndarray:

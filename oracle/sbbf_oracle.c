@@ -166,3 +166,20 @@ void sbbf_oracle_index_histogram(uint64_t x_begin, uint64_t x_end, uint64_t hist
 void sbbf_oracle_block_histogram(const uint64_t *hashes, uint64_t n, uint32_t num_blocks, uint64_t *count) {
   for (uint64_t i = 0; i < n; ++i) count[sbbf_oracle_block(hashes[i], num_blocks)] += 1;
 }
+
+/* Key hashing for the entry points that take keys (the method hashes each
+ * key once and leaves the function open; the library's choice is the 64-bit
+ * finalizer of MurmurHash3 by A. Appleby): out[i] = fmix64(keys[i]), where
+ * fmix64 xor-shifts right by 33, multiplies by 0xff51afd7ed558ccd, xor-shifts
+ * by 33, multiplies by 0xc4ceb9fe1a85ec53 and xor-shifts by 33 (mod 2^64). */
+void sbbf_oracle_key_hash(const uint64_t *keys, uint64_t n, uint64_t *out) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t k = keys[i];
+    k = k ^ (k >> 33);
+    k = k * UINT64_C(0xff51afd7ed558ccd);
+    k = k ^ (k >> 33);
+    k = k * UINT64_C(0xc4ceb9fe1a85ec53);
+    k = k ^ (k >> 33);
+    out[i] = k;
+  }
+}

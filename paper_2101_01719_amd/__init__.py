@@ -257,6 +257,23 @@ def sbbf_lookup_batch_ex(f: int, hashes: torch.Tensor, out: torch.Tensor | None 
     return bits
 
 
+def sbbf_key_hash(key: int) -> int:
+    return int(_L().sbbf_key_hash(key & 0xFFFFFFFFFFFFFFFF))
+
+
+def sbbf_insert_keys(f: int, keys: torch.Tensor, launch=None, stream=None) -> None:
+    p, n = _hashes(keys)
+    _check(_L().sbbf_insert_keys(f, p, n, _launch(launch), _stream(stream)))
+
+
+def sbbf_lookup_keys(f: int, keys: torch.Tensor, out: torch.Tensor | None = None, launch=None,
+                     stream=None) -> torch.Tensor:
+    p, n = _hashes(keys)
+    out = _out_bytes(out, n, keys.device)
+    _check(_L().sbbf_lookup_keys(f, p, n, ctypes.c_void_p(out.data_ptr()), _launch(launch), _stream(stream)))
+    return out
+
+
 def sbbf_lookup_select(f: int, hashes: torch.Tensor, indices: torch.Tensor | None = None,
                        count: torch.Tensor | None = None, launch=None, stream=None):
     """Indices (int32 tensor of room n; entries [0, count) valid, ascending)
@@ -506,6 +523,13 @@ class Filter:
     def lookup_bits(self, hashes, bits=None, launch=None, stream=None):
         return sbbf_lookup_batch_ex(self.handle, hashes, bits=bits if bits is not None else _out_bits(
             None, hashes.numel(), hashes.device), launch=launch, stream=stream)
+
+    def insert_keys(self, keys, launch=None, stream=None):
+        sbbf_insert_keys(self.handle, keys, launch, stream)
+        return self
+
+    def lookup_keys(self, keys, out=None, launch=None, stream=None):
+        return sbbf_lookup_keys(self.handle, keys, out, launch, stream)
 
     def union(self, other, stream=None):
         """self |= other (same number of blocks)."""

@@ -116,6 +116,9 @@ SIGNATURES = {
     "sbbf_lookup_batch_bits": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp]),
     "sbbf_lookup_batch_ex": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_lookup_select": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_key_hash": (c_u64, [c_u64]),
+    "sbbf_insert_keys": (c_int, [c_vp, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_lookup_keys": (c_int, [c_vp, c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_bench_gather": (c_int, [c_vp, c_u32, c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_bench_atomic": (c_int, [c_vp, c_u32, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_bench_stream": (c_int, [c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),

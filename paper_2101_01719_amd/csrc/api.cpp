@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "sbbf_device.h"
 #include "sbbf.h"
 
 namespace sbbf {
@@ -123,6 +124,7 @@ sbbf_status resolve_shape(const sbbf_launch *cfg, uint64_t n, uint32_t default_u
   out->grid = grid;
   out->unroll = unroll;
   out->flags = flags;
+  out->keys = 0;
   return SBBF_OK;
 }
 
@@ -429,8 +431,9 @@ static hipError_t workspace_alloc(void **p, size_t bytes, hipStream_t stream, in
   return hipMallocAsync(p, bytes, stream);
 }
 
-sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_t n, const sbbf_launch *cfg,
-                                 sbbf_stream s) {
+// Insert of n hashes, or of n keys hashed on load (key_hash) when keys is 1.
+static sbbf_status insert_impl(sbbf_filter *f, const uint64_t *d_hashes, size_t n, const sbbf_launch *cfg,
+                               sbbf_stream s, uint32_t keys) {
   sbbf_status st = check_batch(f, d_hashes, n, nullptr, nullptr, 1);
   if (st != SBBF_OK || n == 0) return st;
   uint32_t strategy = cfg ? cfg->strategy : SBBF_INSERT_AUTO;
@@ -442,9 +445,11 @@ sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_
   switch (strategy) {
     case SBBF_INSERT_ATOMIC32:
       if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
+      shape.keys = keys;
       return hip_error(launch_insert_atomic32(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     case SBBF_INSERT_ATOMIC64:
       if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
+      shape.keys = keys;
       return hip_error(launch_insert_atomic64(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     case SBBF_INSERT_PARTITIONED: {
       const uint32_t shift = partition_slice_shift(*info, f->num_blocks);
@@ -460,7 +465,7 @@ sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_
       if (e != hipSuccess) return hip_error(e, "hipMallocAsync(partition workspace)");
       for (uint64_t at = 0; at < n && e == hipSuccess; at += step) {
         const uint64_t m = n - at < step ? n - at : step;
-        e = launch_insert_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups, stream);
+        e = launch_insert_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups, keys, stream);
       }
       hipError_t e2 = hipFreeAsync(ws, stream);
       if (e != hipSuccess) return hip_error(e, "partitioned insert");
@@ -474,12 +479,25 @@ sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_
       if (c.block_threads == 0) c.block_threads = 1024;
       if (c.grid_blocks == 0) c.grid_blocks = 1;
       if ((st = resolve_shape(&c, n, 2, &shape)) != SBBF_OK) return st;
+      shape.keys = keys;
       return hip_error(launch_insert_lds(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     }
     default:
       return set_error(SBBF_EINVAL, "unknown insert strategy");
   }
 }
+
+sbbf_status sbbf_insert_batch_ex(sbbf_filter *f, const uint64_t *d_hashes, size_t n, const sbbf_launch *cfg,
+                                 sbbf_stream s) {
+  return insert_impl(f, d_hashes, n, cfg, s, 0u);
+}
+
+sbbf_status sbbf_insert_keys(sbbf_filter *f, const uint64_t *d_keys, size_t n, const sbbf_launch *cfg,
+                             sbbf_stream s) {
+  return insert_impl(f, d_keys, n, cfg, s, 1u);
+}
+
+uint64_t sbbf_key_hash(uint64_t key) { return key_hash(key); }
 
 uint32_t sbbf_auto_insert_strategy(const sbbf_filter *f, size_t n) {
   sbbf_status st;
@@ -497,8 +515,9 @@ sbbf_status sbbf_insert_batch(sbbf_filter *f, const uint64_t *d_hashes, size_t n
   return sbbf_insert_batch_ex(f, d_hashes, n, nullptr, s);
 }
 
-sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
-                                 uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s) {
+// Lookup of n hashes, or of n keys hashed on load (key_hash) when keys is 1.
+static sbbf_status lookup_impl(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
+                               uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s, uint32_t keys) {
   if ((d_out == nullptr) == (d_bits == nullptr) && n > 0)
     return set_error(SBBF_EINVAL, "exactly one of d_out and d_bits must be non-NULL");
   sbbf_status st = d_bits ? check_batch(f, d_hashes, n, d_bits, "d_bits", 4)
@@ -524,7 +543,7 @@ sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes,
     for (uint64_t at = 0; at < n && e == hipSuccess; at += step) {
       const uint64_t m = n - at < step ? n - at : step;
       e = launch_lookup_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups,
-                                    d_out ? d_out + at : nullptr, d_bits ? d_bits + at / 32 : nullptr, stream);
+                                    d_out ? d_out + at : nullptr, d_bits ? d_bits + at / 32 : nullptr, keys, stream);
     }
     hipError_t e2 = hipFreeAsync(ws, stream);
     if (e != hipSuccess) return hip_error(e, "partitioned lookup");
@@ -533,7 +552,18 @@ sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes,
   if (strategy != SBBF_LOOKUP_GATHER) return set_error(SBBF_EINVAL, "unknown lookup strategy");
   Shape shape;
   if ((st = resolve_shape(cfg, n, 2, &shape, 4)) != SBBF_OK) return st;
+  shape.keys = keys;
   return hip_error(launch_lookup(d_hashes, n, f->words, f->num_blocks, d_out, d_bits, shape, stream), "lookup");
+}
+
+sbbf_status sbbf_lookup_batch_ex(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,
+                                 uint32_t *d_bits, const sbbf_launch *cfg, sbbf_stream s) {
+  return lookup_impl(f, d_hashes, n, d_out, d_bits, cfg, s, 0u);
+}
+
+sbbf_status sbbf_lookup_keys(const sbbf_filter *f, const uint64_t *d_keys, size_t n, uint8_t *d_out,
+                             const sbbf_launch *cfg, sbbf_stream s) {
+  return lookup_impl(f, d_keys, n, d_out, nullptr, cfg, s, 1u);
 }
 
 sbbf_status sbbf_lookup_batch(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint8_t *d_out,

@@ -23,6 +23,7 @@ struct Shape {
   uint32_t grid;     // workgroups
   uint32_t unroll;   // 64-key chunks per wave in flight (1, 2, 4, 8)
   uint32_t flags;    // SBBF_* memory-access flags
+  uint32_t keys;     // 1: the input holds keys, hashed on load (key_hash)
 };
 
 // Cached device facts (per device, queried once).
@@ -62,11 +63,13 @@ hipError_t launch_union(uint32_t *dst, const uint32_t *src, uint64_t num_words, 
 uint32_t partition_max_slices();
 uint64_t partition_max_keys();
 uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup);
+// keys: the input holds keys, hashed on load (key_hash).
 hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
-                                     uint32_t slice_shift, void *workspace, uint32_t max_groups, hipStream_t stream);
+                                     uint32_t slice_shift, void *workspace, uint32_t max_groups, uint32_t keys,
+                                     hipStream_t stream);
 hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
-                                     uint32_t *out_bits, hipStream_t stream);
+                                     uint32_t *out_bits, uint32_t keys, hipStream_t stream);
 
 // Stream compaction of a lookup bitmap (select.hip): the workspace starts
 // with the bitmap (ceil(n / 32) words, select_bits()) the lookup writes;

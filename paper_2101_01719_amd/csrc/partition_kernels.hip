@@ -63,14 +63,14 @@ __device__ __forceinline__ void chunk_range(uint32_t g, uint32_t chunk, uint32_t
 
 __global__ void __launch_bounds__(kPartThreads)
 part_count_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t num_blocks,
-                  uint32_t slice_shift, uint32_t num_slices, uint32_t *__restrict__ hist_out) {
+                  uint32_t slice_shift, uint32_t num_slices, uint32_t keys, uint32_t *__restrict__ hist_out) {
   extern __shared__ uint32_t hist[];
   for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   uint32_t b, e;
   chunk_range(blockIdx.x, chunk, n, &b, &e);
   for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    const uint32_t s = slice_of(load_hash<0>(hashes + i), num_blocks, slice_shift);
+    const uint32_t s = slice_of(as_hash(load_hash<0>(hashes + i), keys), num_blocks, slice_shift);
     __hip_atomic_fetch_add(hist + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __syncthreads();
@@ -210,11 +210,16 @@ struct SliceCursor {
 // stays in the stage as the next tile's carry. kFull: the whole tile is
 // inside the chunk (no per-key guards).
 template <bool kWithPos, int R, uint32_t L, bool kFull>
-__device__ __forceinline__ void scatter_tile(const uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
+__device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
                                              const uint32_t *__restrict__ new_chunk_hist, uint32_t num_blocks,
-                                             uint32_t slice_shift, uint32_t num_slices, const ScatterLds &S,
-                                             SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
+                                             uint32_t slice_shift, uint32_t num_slices, uint32_t keys,
+                                             const ScatterLds &S, SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
                                              uint16_t *__restrict__ out_pos) {
+  // Keys are hashed here, where the prefetched tile is first used.
+  if (keys) {
+#pragma unroll
+    for (uint32_t t = 0; t < kScatterPer; ++t) h[t] = key_hash(h[t]);
+  }
   static_assert(L == 1u || R == 1, "carried groups need one slice per thread");
   constexpr uint32_t kCarryMax = L > 1u ? L - 1u : 1u;
   const uint32_t own = threadIdx.x * R;
@@ -315,7 +320,7 @@ __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t chunks_per_group,
                     uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices,
                     const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
-                    const uint32_t *__restrict__ hist_rows, uint64_t *__restrict__ out_keys,
+                    const uint32_t *__restrict__ hist_rows, uint32_t keys, uint64_t *__restrict__ out_keys,
                     uint16_t *__restrict__ out_pos) {
   extern __shared__ unsigned long long smem[];
   ScatterLds S;
@@ -367,7 +372,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   scatter_tile<kWithPos, R, L, FULL>(H, t0, e, t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * \
                                                                                    num_slices                  \
                                                                              : nullptr,                        \
-                                     num_blocks, slice_shift, num_slices, S, C, out_keys, out_pos)
+                                     num_blocks, slice_shift, num_slices, keys, S, C, out_keys, out_pos)
   for (; k + 2u <= nfull; k += 2u) {
     load_tile(hashes, t0 + kTile, e, hb);
     SBBF_SCATTER_TILE(true, ha);
@@ -773,7 +778,8 @@ void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uin
 
 template <bool kWithPos, int R, uint32_t L>
 hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
-                          uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L_, hipStream_t stream) {
+                          uint32_t slice_shift, uint32_t num_slices, uint32_t keys, const PartitionLayout &L_,
+                          hipStream_t stream) {
   const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L);
   // Several chunks per workgroup (lookups cut the batch finer than inserts):
   // about two workgroups per compute unit.
@@ -783,8 +789,8 @@ hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, ui
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L>), dim3(grid), dim3(kScatterThreads), lds, stream, hashes,
-                     n, chunk, per, num_blocks, slice_shift, num_slices, L_.offsets, L_.start, L_.hist, L_.keys,
-                     kWithPos ? L_.pos : nullptr);
+                     n, chunk, per, num_blocks, slice_shift, num_slices, L_.offsets, L_.start, L_.hist, keys,
+                     L_.keys, kWithPos ? L_.pos : nullptr);
   return hipGetLastError();
 }
 
@@ -793,20 +799,20 @@ hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, ui
 // kScatterGroup keys (the incomplete tail carried to the next tile).
 template <bool kWithPos>
 hipError_t launch_scatter_r(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups,
-                            uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices, const PartitionLayout &L,
-                            hipStream_t stream) {
+                            uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices, uint32_t keys,
+                            const PartitionLayout &L, hipStream_t stream) {
   if (num_slices <= kScatterThreads)
-    return launch_scatter<kWithPos, 1, kScatterGroup>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L,
-                                                      stream);
+    return launch_scatter<kWithPos, 1, kScatterGroup>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys,
+                                                      L, stream);
   if (num_slices <= 2u * kScatterThreads)
-    return launch_scatter<kWithPos, 2, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+    return launch_scatter<kWithPos, 2, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
   static_assert(4u * kScatterThreads >= kMaxSlices, "four slices per thread cover every filter");
-  return launch_scatter<kWithPos, 4, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  return launch_scatter<kWithPos, 4, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
 }
 
 hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, uint32_t slice_shift,
                      uint32_t num_slices, uint32_t chunk, uint32_t groups, const PartitionLayout &L, bool with_pos,
-                     hipStream_t stream) {
+                     uint32_t keys, hipStream_t stream) {
   hipError_t e;
   const dim3 blk(kPartThreads);
   // Dynamic LDS above the default needs the per-kernel limit raised; an error
@@ -815,7 +821,7 @@ hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, ui
                             (int)(num_slices * 4u));
   (void)hipGetLastError();
   hipLaunchKernelGGL(part_count_kernel, dim3(groups), blk, num_slices * 4u, stream, hashes, n, chunk, num_blocks,
-                     slice_shift, num_slices, L.hist);
+                     slice_shift, num_slices, keys, L.hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const dim3 scan_grid((num_slices + kScanCols - 1) / kScanCols, row_blocks(groups));
   if (scan_grid.y > 1) {  // one row block needs no carries
@@ -827,8 +833,9 @@ hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, ui
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(part_offsets_kernel, dim3(1), blk, 0, stream, L.tot, num_slices, L.offsets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (with_pos) return launch_scatter_r<true>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
-  return launch_scatter_r<false>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, L, stream);
+  if (with_pos)
+    return launch_scatter_r<true>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
+  return launch_scatter_r<false>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
 }
 
 uint32_t slices_of(uint32_t num_blocks, uint32_t slice_shift) {
@@ -847,7 +854,7 @@ uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max
 }
 
 hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
-                                     uint32_t slice_shift, void *workspace, uint32_t max_groups,
+                                     uint32_t slice_shift, void *workspace, uint32_t max_groups, uint32_t keys,
                                      hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
@@ -856,7 +863,8 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   chunking(n, max_groups, false, &chunk, &groups);
   PartitionLayout L = layout(workspace, n, num_slices, groups, false);
   L.scatter_groups = groups;
-  hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, false, stream);
+  hipError_t e =
+      partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, false, keys, stream);
   if (e != hipSuccess) return e;
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
   (void)hipFuncSetAttribute((const void *)part_slice_insert_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -869,7 +877,7 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
 
 hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
-                                     uint32_t *out_bits, hipStream_t stream) {
+                                     uint32_t *out_bits, uint32_t keys, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
@@ -877,7 +885,8 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
   chunking(n, max_groups, true, &chunk, &groups);
   PartitionLayout L = layout(workspace, n, num_slices, groups, true);
   L.scatter_groups = max_groups ? max_groups : 1u;
-  hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, true, stream);
+  hipError_t e =
+      partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, true, keys, stream);
   if (e != hipSuccess) return e;
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
   (void)hipFuncSetAttribute((const void *)part_slice_lookup_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -29,15 +29,26 @@ __device__ __forceinline__ WaveCursor wave_cursor() {
 }
 
 // Stage U chunks of 64 hashes starting at key `base`: block index and low half
-// of the hash held by each lane. Keys at or past n become hash 0 (block 0,
-// always in range); their results are discarded by the callers.
+// of the hash held by each lane (the input is hashed first when `keys` is
+// set). Keys at or past n become hash 0 (block 0, always in range); their
+// results are discarded by the callers.
 template <int U, uint32_t kFlags>
 __device__ __forceinline__ void stage(const uint64_t *__restrict__ hashes, uint64_t n, uint64_t base,
-                                      uint32_t num_blocks, uint32_t lane, uint32_t (&blk)[U], uint32_t (&lo)[U]) {
+                                      uint32_t num_blocks, uint32_t lane, uint32_t keys, uint32_t (&blk)[U],
+                                      uint32_t (&lo)[U]) {
+  uint64_t hv[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const uint64_t i = base + (uint64_t)(kWave * u) + lane;
-    const uint64_t h = i < n ? load_hash<kFlags>(hashes + i) : 0ull;
+    hv[u] = i < n ? load_hash<kFlags>(hashes + i) : 0ull;
+  }
+  if (keys) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) hv[u] = key_hash(hv[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t h = hv[u];
     lo[u] = (uint32_t)h;
     blk[u] = block_of((uint32_t)(h >> 32), num_blocks);
   }
@@ -48,7 +59,7 @@ __device__ __forceinline__ void stage(const uint64_t *__restrict__ hashes, uint6
 template <int U, bool kBits, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *__restrict__ words,
-              uint32_t num_blocks, uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
+              uint32_t num_blocks, uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits, uint32_t keys) {
   const uint32_t lane = lane_id();
   const uint32_t j = lane & 7u;       // word of the block owned by this lane
   const uint32_t group = lane & ~7u;  // first lane of this lane's 8-lane group
@@ -58,7 +69,7 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
 
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
 
     // Issue every block read of the U chunks before testing any of them.
     uint32_t word[U][8], bit[U][8];
@@ -98,7 +109,7 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
 template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
-                       uint32_t num_blocks) {
+                       uint32_t num_blocks, uint32_t keys) {
   const uint32_t lane = lane_id();
   const uint32_t j = lane & 7u;
   const uint32_t group = lane & ~7u;
@@ -108,7 +119,7 @@ insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -132,7 +143,7 @@ insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
-                       uint32_t num_blocks) {
+                       uint32_t num_blocks, uint32_t keys) {
   const uint32_t lane = lane_id();
   const uint32_t q = lane & 3u;
   const uint32_t group = lane & ~3u;
@@ -144,7 +155,7 @@ insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -172,7 +183,7 @@ insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
-                  uint32_t num_blocks) {
+                  uint32_t num_blocks, uint32_t keys) {
   extern __shared__ uint4 lds4[];
   uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
   const uint32_t n_vec4 = num_blocks * 2u;  // 32 bytes per block = 2 x uint4
@@ -189,7 +200,7 @@ insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__r
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -248,6 +259,7 @@ template <int U, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 bench_gather_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *__restrict__ buf,
                     uint32_t num_blocks, uint8_t *__restrict__ out8) {
+  constexpr uint32_t keys = 0;  // measurement kernels take hashes
   const uint32_t lane = lane_id();
   const uint32_t j = lane & 7u;
   const uint32_t group = lane & ~7u;
@@ -255,7 +267,7 @@ bench_gather_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint3
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
     uint32_t word[U][8];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -284,6 +296,7 @@ template <int U, bool kWide, uint32_t kFlags>
 __global__ void __launch_bounds__(1024)
 bench_atomic_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ buf,
                     uint32_t num_blocks) {
+  constexpr uint32_t keys = 0;  // measurement kernels take hashes
   const uint32_t lane = lane_id();
   const WaveCursor wc = wave_cursor();
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
@@ -292,7 +305,7 @@ bench_atomic_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *_
   const uint32_t group = lane & ~(kLanes - 1u);
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
     uint32_t blk[U], lo[U];
-    stage<U, kFlags>(hashes, n, base, num_blocks, lane, blk, lo);
+    stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -388,10 +401,10 @@ struct LookupLauncher {
 #define BODY(U)                                                                                              \
   if (out_bits)                                                                                              \
     hipLaunchKernelGGL((lookup_kernel<U, true, F>), g, b, 0, stream, hashes, n, words, num_blocks, nullptr,  \
-                       out_bits);                                                                            \
+                       out_bits, s.keys);                                                                    \
   else                                                                                                       \
     hipLaunchKernelGGL((lookup_kernel<U, false, F>), g, b, 0, stream, hashes, n, words, num_blocks, out8,    \
-                       nullptr);                                                                             \
+                       nullptr, s.keys);                                                                     \
   return hipGetLastError();
     SBBF_DISPATCH_U4(s.unroll, BODY)
 #undef BODY
@@ -419,14 +432,14 @@ hipError_t run_insert(int kind, const uint64_t *hashes, uint64_t n, uint32_t *wo
   const dim3 g(s.grid), b(s.threads);
   if (kind == SBBF_INSERT_ATOMIC32) {
 #define BODY(U)                                                                                       \
-  hipLaunchKernelGGL((insert_atomic32_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks);  \
+  hipLaunchKernelGGL((insert_atomic32_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks, s.keys); \
   return hipGetLastError();
     SBBF_DISPATCH_U8(s.unroll, BODY)
 #undef BODY
   }
   if (kind == SBBF_INSERT_ATOMIC64) {
 #define BODY(U)                                                                                       \
-  hipLaunchKernelGGL((insert_atomic64_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks);  \
+  hipLaunchKernelGGL((insert_atomic64_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks, s.keys); \
   return hipGetLastError();
     SBBF_DISPATCH_U8(s.unroll, BODY)
 #undef BODY
@@ -437,7 +450,7 @@ hipError_t run_insert(int kind, const uint64_t *hashes, uint64_t n, uint32_t *wo
   (void)hipFuncSetAttribute((const void *)insert_lds_kernel<U, H>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                             (int)lds_bytes);                                                                 \
   (void)hipGetLastError();                                                                                   \
-  hipLaunchKernelGGL((insert_lds_kernel<U, H>), g, b, lds_bytes, stream, hashes, n, words, num_blocks);      \
+  hipLaunchKernelGGL((insert_lds_kernel<U, H>), g, b, lds_bytes, stream, hashes, n, words, num_blocks, s.keys); \
   return hipGetLastError();
   SBBF_DISPATCH_U8(s.unroll, BODY)
 #undef BODY

@@ -68,6 +68,23 @@ __device__ __forceinline__ uint32_t lane_read(uint32_t v, uint32_t src) {
 // Wave-wide ballot of a predicate.
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Hash of a key, for the entry points that take keys instead of hashes: the
+// 64-bit finalizer of MurmurHash3 (A. Appleby, public domain), a bijection
+// on 64-bit values with full avalanche. The method hashes each key once and
+// leaves the hash function open (construction paragraph); this is the
+// library's choice of it.
+__host__ __device__ inline uint64_t key_hash(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+// v itself, or key_hash(v) when the kernel was given keys (a uniform flag).
+__device__ __forceinline__ uint64_t as_hash(uint64_t v, uint32_t keys) { return keys ? key_hash(v) : v; }
+
 // Load of one hash. By default with the non-temporal hint: the hash arrays are
 // read once and should not displace the filter from the caches.
 template <uint32_t kFlags>
