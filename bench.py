@@ -95,6 +95,10 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
     fetch, write = _counter_rows(fetch_csv, "FETCH_SIZE"), _counter_rows(write_csv, "WRITE_SIZE")
     if [r[:3] for r in fetch] != [r[:3] for r in write]:
         raise SystemExit("the two counter runs did not dispatch the same kernels")
+    others = sorted({_short_kernel(r[1]) for r in fetch if _short_kernel(r[1]).startswith(("select_", "union_"))})
+    if others:
+        raise SystemExit(f"the counter runs also dispatched {others}: collect them with --no-select so that "
+                         "every call averaged is a step's insert or lookup")
     want_kib = copy_mib * 1024.0
     copies = [i for i, r in enumerate(write) if "copy" in r[1].lower() and abs(r[3] - want_kib) < 0.05 * want_kib]
     if not copies:
