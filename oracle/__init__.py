@@ -59,6 +59,13 @@ def _load():
     lib.sbbf_oracle_index_histogram.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _U64P]
     lib.sbbf_oracle_block_histogram.argtypes = [_U64P, ctypes.c_uint64, ctypes.c_uint32, _U64P]
     lib.sbbf_oracle_key_hash.argtypes = [_U64P, ctypes.c_uint64, _U64P]
+    lib.sbbf_oracle_variant_seeds.argtypes = [ctypes.c_uint32, _U32P]
+    lib.sbbf_oracle_variant_seeds.restype = ctypes.c_int
+    lib.sbbf_oracle_variant_mask.argtypes = [ctypes.c_uint32, ctypes.c_uint32, _U32P]
+    lib.sbbf_oracle_variant_insert.argtypes = [_U32P, ctypes.c_uint32, ctypes.c_uint32, _U64P, ctypes.c_uint64]
+    lib.sbbf_oracle_variant_contains.argtypes = [_U32P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]
+    lib.sbbf_oracle_variant_contains.restype = ctypes.c_int
+    lib.sbbf_oracle_variant_lookup.argtypes = [_U32P, ctypes.c_uint32, ctypes.c_uint32, _U64P, ctypes.c_uint64, _U8P]
     _lib = lib
     return lib
 
@@ -76,11 +83,11 @@ def _hashes(h) -> np.ndarray:
     return a
 
 
-def _check_filter(words: np.ndarray, num_blocks: int):
+def _check_filter(words: np.ndarray, num_blocks: int, lanes: int = 8):
     if words.dtype != np.uint32 or not words.flags.c_contiguous:
         raise TypeError("filter words must be a contiguous uint32 array")
-    if words.size != 8 * num_blocks:
-        raise ValueError("filter must hold 8 words per block")
+    if words.size != lanes * num_blocks:
+        raise ValueError(f"filter must hold {lanes} words per block")
     if not (1 <= num_blocks <= 0xFFFFFFFF):
         raise ValueError("num_blocks must be in [1, 2**32 - 1]")
 
@@ -183,6 +190,67 @@ def key_hash(keys) -> np.ndarray:
 def build_filter(num_blocks: int, hashes) -> np.ndarray:
     """A fresh filter holding ``hashes``."""
     return insert(new_filter(num_blocks), num_blocks, hashes)
+
+
+# ---- block variants with K = 4, 8 or 16 lanes (K words per block) ----------
+
+VARIANT_LANES = (4, 8, 16)
+
+
+def _check_lanes(lanes: int):
+    if lanes not in VARIANT_LANES:
+        raise ValueError("lanes must be 4, 8 or 16")
+
+
+def variant_seeds(lanes: int) -> np.ndarray:
+    """Seeds of a K-lane block in word order."""
+    _check_lanes(lanes)
+    out = np.zeros(16, dtype=np.uint32)
+    if _load().sbbf_oracle_variant_seeds(lanes, _ptr(out, _U32P)) != 0:
+        raise ValueError("lanes must be 4, 8 or 16")
+    return out[:lanes].copy()
+
+
+def variant_mask(lanes: int, x: int) -> np.ndarray:
+    _check_lanes(lanes)
+    out = np.zeros(16, dtype=np.uint32)
+    _load().sbbf_oracle_variant_mask(lanes, ctypes.c_uint32(x), _ptr(out, _U32P))
+    return out[:lanes].copy()
+
+
+def variant_new_filter(lanes: int, num_blocks: int) -> np.ndarray:
+    _check_lanes(lanes)
+    return np.zeros(lanes * int(num_blocks), dtype=np.uint32)
+
+
+def variant_insert(words: np.ndarray, lanes: int, num_blocks: int, hashes) -> np.ndarray:
+    """OR the K-word masks of ``hashes`` into a K-lane filter in place."""
+    _check_lanes(lanes)
+    _check_filter(words, num_blocks, lanes)
+    h = _hashes(hashes)
+    _load().sbbf_oracle_variant_insert(_ptr(words, _U32P), lanes, num_blocks, _ptr(h, _U64P), h.size)
+    return words
+
+
+def variant_contains(words: np.ndarray, lanes: int, num_blocks: int, h: int) -> bool:
+    _check_lanes(lanes)
+    _check_filter(words, num_blocks, lanes)
+    return bool(_load().sbbf_oracle_variant_contains(_ptr(words, _U32P), lanes, num_blocks, ctypes.c_uint64(h)))
+
+
+def variant_lookup(words: np.ndarray, lanes: int, num_blocks: int, hashes) -> np.ndarray:
+    """uint8 0/1 per hash against a K-lane filter."""
+    _check_lanes(lanes)
+    _check_filter(words, num_blocks, lanes)
+    h = _hashes(hashes)
+    out = np.empty(h.size, dtype=np.uint8)
+    _load().sbbf_oracle_variant_lookup(_ptr(words, _U32P), lanes, num_blocks, _ptr(h, _U64P), h.size,
+                                       _ptr(out, _U8P))
+    return out
+
+
+def variant_build_filter(lanes: int, num_blocks: int, hashes) -> np.ndarray:
+    return variant_insert(variant_new_filter(lanes, num_blocks), lanes, num_blocks, hashes)
 
 
 def replay_requests(blocks, filt, op, key_off, payload, out_off=None):

@@ -39,11 +39,13 @@ def _poisson_terms(a: float):
         yield i, p
 
 
-def sbbf_fpr(a: float) -> float:
-    """The paper's Poisson-sum approximation F(a), a = mean hashes per block."""
+def sbbf_fpr(a: float, lanes: int = 8) -> float:
+    """The paper's Poisson-sum approximation F(a), a = mean hashes per block.
+    With ``lanes`` = K other than 8 (blocks of K 32-bit words, one bit per
+    word) the same argument gives the exponent K in place of 8."""
     total = 0.0
     for i, p in _poisson_terms(a):
-        total += p * (1.0 - (31.0 / 32.0) ** i) ** 8
+        total += p * (1.0 - (31.0 / 32.0) ** i) ** lanes
     return total
 
 
@@ -95,7 +97,7 @@ def load_for_fpr(target: float, lo: float = 1e-3, hi: float = 256.0) -> float:
     return 0.5 * (lo + hi)
 
 
-def blocks_for_fpr(n: int, fpr: float, max_blocks: int = 2**32 - 1) -> int:
+def blocks_for_fpr(n: int, fpr: float, max_blocks: int = 2**32 - 1, lanes: int = 8) -> int:
     """Smallest number of blocks B >= 1 with sbbf_fpr(n / B) <= fpr, by
     bisection (F grows with the load n / B). 0 when even max_blocks is not
     enough."""
@@ -103,14 +105,14 @@ def blocks_for_fpr(n: int, fpr: float, max_blocks: int = 2**32 - 1) -> int:
         raise ValueError("fpr must be in (0, 1)")
     if n == 0:
         return 1
-    if sbbf_fpr(n / max_blocks) > fpr:
+    if sbbf_fpr(n / max_blocks, lanes) > fpr:
         return 0
-    if sbbf_fpr(float(n)) <= fpr:
+    if sbbf_fpr(float(n), lanes) <= fpr:
         return 1
     lo, hi = 1, max_blocks
     while hi - lo > 1:
         mid = (lo + hi) // 2
-        if sbbf_fpr(n / mid) <= fpr:
+        if sbbf_fpr(n / mid, lanes) <= fpr:
             hi = mid
         else:
             lo = mid

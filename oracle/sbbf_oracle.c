@@ -183,3 +183,67 @@ void sbbf_oracle_key_hash(const uint64_t *keys, uint64_t n, uint64_t *out) {
     out[i] = k;
   }
 }
+
+/* ---- Block variants with four or sixteen lanes ----------------------------
+ *
+ * The paper picks eight lanes so that a block fills one 256-bit SIMD register
+ * and notes that four or sixteen lanes would work too (list of central ideas,
+ * footnote). A K-lane block is K 32-bit words, W[K b .. K b + K - 1]; block
+ * selection is unchanged and word j takes bit (s_j * lo32(h) mod 2^32) >> 27.
+ * The paper prints seeds for eight lanes only. Readings:
+ *   K = 4:  seeds 0..3 of the appendix figure (its first two constants);
+ *   K = 8:  the eight seeds of the figure (the method itself);
+ *   K = 16: the eight seeds of the figure, then eight more odd seeds: the low
+ *           32 bits of the first eight outputs of SplitMix64 seeded with 16,
+ *           each with its lowest bit set.
+ */
+static const uint32_t kExtraSeeds[8] = {
+    UINT32_C(0xba779207), UINT32_C(0xc985644b), UINT32_C(0xa4e84675), UINT32_C(0xe421c8db),
+    UINT32_C(0xbd38674f), UINT32_C(0x58ee486d), UINT32_C(0x8ddb3387), UINT32_C(0x7ea09599),
+};
+
+/* Seeds of a K-lane block in word order; returns 0, or -1 for another K. */
+int sbbf_oracle_variant_seeds(uint32_t lanes, uint32_t seeds[16]) {
+  if (lanes != 4 && lanes != 8 && lanes != 16) return -1;
+  uint32_t paper[8];
+  sbbf_oracle_seeds(paper);
+  for (uint32_t j = 0; j < lanes; ++j) seeds[j] = j < 8 ? paper[j] : kExtraSeeds[j - 8];
+  return 0;
+}
+
+/* The K-word mask for the low 32 bits of a hash: one bit in each word. */
+void sbbf_oracle_variant_mask(uint32_t lanes, uint32_t x, uint32_t mask[16]) {
+  uint32_t seeds[16];
+  sbbf_oracle_variant_seeds(lanes, seeds);
+  for (uint32_t j = 0; j < lanes; ++j) {
+    uint32_t product = (uint32_t)((uint64_t)seeds[j] * (uint64_t)x); /* mod 2^32 */
+    mask[j] = UINT32_C(1) << (product >> 27);
+  }
+}
+
+/* Insert into a K-lane filter (K * num_blocks words). */
+void sbbf_oracle_variant_insert(uint32_t *words, uint32_t lanes, uint32_t num_blocks, const uint64_t *hashes,
+                                uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t b = sbbf_oracle_block(hashes[i], num_blocks);
+    uint32_t mask[16];
+    sbbf_oracle_variant_mask(lanes, (uint32_t)(hashes[i] & UINT64_C(0xffffffff)), mask);
+    for (uint32_t j = 0; j < lanes; ++j) words[(uint64_t)lanes * b + j] |= mask[j];
+  }
+}
+
+/* One lookup in a K-lane filter: 1 when every word holds its mask bit. */
+int sbbf_oracle_variant_contains(const uint32_t *words, uint32_t lanes, uint32_t num_blocks, uint64_t hash) {
+  uint64_t b = sbbf_oracle_block(hash, num_blocks);
+  uint32_t mask[16];
+  sbbf_oracle_variant_mask(lanes, (uint32_t)(hash & UINT64_C(0xffffffff)), mask);
+  for (uint32_t j = 0; j < lanes; ++j) {
+    if ((words[(uint64_t)lanes * b + j] & mask[j]) == 0) return 0;
+  }
+  return 1;
+}
+
+void sbbf_oracle_variant_lookup(const uint32_t *words, uint32_t lanes, uint32_t num_blocks, const uint64_t *hashes,
+                                uint64_t n, uint8_t *out) {
+  for (uint64_t i = 0; i < n; ++i) out[i] = (uint8_t)sbbf_oracle_variant_contains(words, lanes, num_blocks, hashes[i]);
+}

@@ -110,3 +110,74 @@ def test_mutant_is_caught(name, tmp_path):
     assert old in text, f"mutation site for {name} not found in the oracle source"
     lib = _build(text.replace(old, new, 1), str(tmp_path / f"{name}.so"))
     assert not _pins_pass(lib)
+
+
+# --- the four- and sixteen-lane variants ---------------------------------------
+
+VARIANT_MUTANTS = {
+    "extra_seed_typo": ("UINT32_C(0x7ea09599)", "UINT32_C(0x7ea0959b)"),
+    "variant_transposed": ("words[(uint64_t)lanes * b + j] |= mask[j];",
+                           "words[(uint64_t)num_blocks * j + b] |= mask[j];"),
+    "variant_seed_shift": ("seeds[j] = j < 8 ? paper[j] : kExtraSeeds[j - 8];",
+                           "seeds[j] = j < 8 ? paper[(j + 4) % 8] : kExtraSeeds[j - 8];"),
+    "variant_lookup_skips_last": ("for (uint32_t j = 0; j < lanes; ++j) {\n    if ((words[(uint64_t)lanes * b + j] & mask[j]) == 0) return 0;",
+                                  "for (uint32_t j = 0; j + 1 < lanes; ++j) {\n    if ((words[(uint64_t)lanes * b + j] & mask[j]) == 0) return 0;"),
+}
+
+
+def _variant_pins_pass(lib):
+    """The variant battery: seeds against the readings (printed constants, then
+    SplitMix64 seeded with 16), and brute force with Python integers."""
+    from synth import splitmix64, splitmix64_stream
+
+    U64P, U32P, U8P = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint8)
+    lib.sbbf_oracle_variant_seeds.argtypes = [ctypes.c_uint32, U32P]
+    lib.sbbf_oracle_variant_insert.argtypes = [U32P, ctypes.c_uint32, ctypes.c_uint32, U64P, ctypes.c_uint64]
+    lib.sbbf_oracle_variant_lookup.argtypes = [U32P, ctypes.c_uint32, ctypes.c_uint32, U64P, ctypes.c_uint64, U8P]
+    paper = []
+    for hi, lo in read_golden("appendix_seeds.txt"):
+        paper += [int(lo, 16), int(hi, 16)]
+    extra = [(splitmix64(16, i) & M32) | 1 for i in range(8)]
+    for lanes in (4, 16):
+        want = (paper + extra)[:lanes]
+        got = np.zeros(16, dtype=np.uint32)
+        lib.sbbf_oracle_variant_seeds(lanes, got.ctypes.data_as(U32P))
+        if [int(v) for v in got[:lanes]] != want:
+            return False
+        B = 5
+        hs = splitmix64_stream(95, 40)
+        words = np.zeros(lanes * B, dtype=np.uint32)
+        lib.sbbf_oracle_variant_insert(words.ctypes.data_as(U32P), lanes, B, hs.ctypes.data_as(U64P), hs.size)
+        bits = 0
+        for h in hs.tolist():
+            b, x = ((h >> 32) * B) >> 32, h & M32
+            for j in range(lanes):
+                bits |= 1 << (lanes * 32 * b + 32 * j + (((want[j] * x) & M32) >> 27))
+        if int.from_bytes(words.astype("<u4").tobytes(), "little") != bits:
+            return False
+        probes = np.concatenate([hs, splitmix64_stream(96, 300)])
+        out = np.zeros(probes.size, dtype=np.uint8)
+        lib.sbbf_oracle_variant_lookup(words.ctypes.data_as(U32P), lanes, B, probes.ctypes.data_as(U64P), probes.size,
+                                       out.ctypes.data_as(U8P))
+        for h, r in zip(probes.tolist(), out.tolist()):
+            b, x = ((h >> 32) * B) >> 32, h & M32
+            hit = all((bits >> (lanes * 32 * b + 32 * j + (((want[j] * x) & M32) >> 27))) & 1 for j in range(lanes))
+            if bool(r) != hit:
+                return False
+    return True
+
+
+def test_unmutated_copy_passes_variant_pins(tmp_path):
+    with open(SRC) as f:
+        text = f.read()
+    assert _variant_pins_pass(_build(text, str(tmp_path / "orig_v.so")))
+
+
+@pytest.mark.parametrize("name", sorted(VARIANT_MUTANTS))
+def test_variant_mutant_is_caught(name, tmp_path):
+    with open(SRC) as f:
+        text = f.read()
+    old, new = VARIANT_MUTANTS[name]
+    assert old in text, f"mutation site for {name} not found in the oracle source"
+    lib = _build(text.replace(old, new, 1), str(tmp_path / f"{name}.so"))
+    assert not _variant_pins_pass(lib)
