@@ -259,6 +259,54 @@ def _keys(P, torch, f, w, ins_launch, look_launch, reps=5):
             "members_all_found": members_ok}
 
 
+def _variants(P, torch, w, reps=5):
+    """The same step on the block variants with four and sixteen 32-bit words
+    per block, each in a 128 MiB filter (the same bytes per key as the
+    eight-word filter): clear, insert, lookup with the library's strategies;
+    measured false-positive rate against the model with K words per block."""
+    out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
+    res = {}
+    for lanes in (4, 16):
+        B = (128 << 20) // (4 * lanes)
+        f = P.Filter(B, lanes=lanes)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+        def step(rec):
+            f.clear()
+            if rec:
+                ev[0].record()
+            f.insert(w.inserts)
+            if rec:
+                ev[1].record()
+            f.lookup(w.lookups, out=out)
+            if rec:
+                ev[2].record()
+
+        step(False)
+        torch.cuda.synchronize()
+        ins_ms = look_ms = 0.0
+        for _ in range(reps):
+            step(True)
+            torch.cuda.synchronize()
+            ins_ms += ev[0].elapsed_time(ev[1]) / reps
+            look_ms += ev[1].elapsed_time(ev[2]) / reps
+        n_ins, n_look = w.inserts.numel(), w.lookups.numel()
+        fpr = float(out[~w.is_member].float().mean().item())
+        res[str(lanes)] = {
+            "num_blocks": B, "block_bytes": 4 * lanes,
+            "insert_ms": ins_ms, "lookup_ms": look_ms,
+            "gkeys_per_s": (n_ins + n_look) / ((ins_ms + look_ms) / 1e3) / 1e9,
+            "insert_strategy": P.sbbf_auto_insert_strategy(f.handle, n_ins),
+            "lookup_strategy": P.sbbf_auto_lookup_strategy(f.handle, n_look),
+            "lookup_GBps": n_look * (8 + 4 * lanes + 1) / (look_ms / 1e3) / 1e9,
+            "insert_GBps": n_ins * (8 + 4 * lanes) / (ins_ms / 1e3) / 1e9,
+            "false_positive_rate": fpr, "model_fpr": P.sbbf_fpr_model_variant(n_ins / B, lanes),
+            "members_all_found": bool(out[w.is_member].all().item()),
+        }
+        f.close()
+    return res
+
+
 def _cpu_baseline(w):
     """The oracle, untuned, on the host: all inserts into the full-size filter,
     then the first half of the lookups. One thread."""
@@ -449,7 +497,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
-    ap.add_argument("--no-select", action="store_true", help="skip the select, union and key-hashing measurements")
+    ap.add_argument("--no-select", action="store_true", help="skip the select, union, key-hashing and block-variant measurements")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -539,6 +587,7 @@ def main(argv=None):
     select = None if a.no_select else _select(P, torch, f, w.lookups, out, look_launch)
     union = None if a.no_select else _union(P, torch, f)
     keys = None if a.no_select else _keys(P, torch, f, w, ins_launch, look_launch)
+    variants = None if a.no_select or a.workload != "plain_100m" else _variants(P, torch, w)
 
     ins_gbps = INSERT_BYTES_PER_KEY * n_ins / (insert_ms / 1e3) / 1e9
     look_gbps = LOOKUP_BYTES_PER_KEY * n_look / (lookup_ms / 1e3) / 1e9
@@ -596,6 +645,8 @@ def main(argv=None):
         result["union"] = union
     if keys is not None:
         result["keys"] = keys
+    if variants is not None:
+        result["variants"] = variants
     if not a.no_ceilings:
         c = _ceilings(P, torch, w, look_launch, ins_launch)
         c["lookup_frac_of_gather"] = result["lookup_gkeys_per_s"] / c["gather_gkeys_per_s"]

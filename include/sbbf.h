@@ -147,6 +147,13 @@ double sbbf_fpr_model(double keys_per_block);
  * The paper's useful band of rates is about 0.4 % to 19 % (introduction;
  * analysis section). */
 uint64_t sbbf_blocks_for_fpr(uint64_t n, double fpr);
+/* The same model and sizing for the block variants with `lanes` 32-bit words
+ * per block (4, 8 or 16; the paper notes that four or sixteen lanes would
+ * work as well as eight, in a footnote to its list of central ideas): the
+ * exponent 8 becomes `lanes`. On a bad lane count the model returns -1 and
+ * the sizing 0, and sbbf_last_error says why. */
+double sbbf_fpr_model_variant(double keys_per_block, uint32_t lanes);
+uint64_t sbbf_blocks_for_fpr_variant(uint64_t n, double fpr, uint32_t lanes);
 
 /* ---- single filter --------------------------------------------------------- */
 
@@ -156,6 +163,24 @@ sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out);
 /* Wrap caller-owned device memory of 32 * num_blocks bytes (32-byte
  * aligned, e.g. a torch tensor). Not cleared; never freed by the library. */
 sbbf_status sbbf_create_wrapped(void *d_words, uint32_t num_blocks, sbbf_filter **out);
+/* Block variants (footnote to the paper's list of central ideas: four or
+ * sixteen lanes would work too). A filter of num_blocks blocks of `lanes`
+ * 32-bit words (4, 8 or 16; 8 is the method itself, as sbbf_create), so
+ * 4 * lanes * num_blocks bytes, block b at byte 4 * lanes * b. Block selection
+ * is unchanged; word j of a block takes bit (s_j * lo32(h) mod 2^32) >> 27.
+ * The paper prints seeds for eight words only: four-word blocks use its seeds
+ * 0..3; sixteen-word blocks use its eight seeds for words 0..7 and, for words
+ * 8..15, 0xba779207, 0xc985644b, 0xa4e84675, 0xe421c8db, 0xbd38674f,
+ * 0x58ee486d, 0x8ddb3387, 0x7ea09599 (the low 32 bits of the first eight
+ * outputs of SplitMix64 seeded with 16, lowest bit set). Every single-filter
+ * entry point (insert, lookup, select, keys, union, serialization, copies)
+ * takes variant filters; grouped plans reject them (SBBF_EUNSUPPORTED), and
+ * the memory-access flags of sbbf_launch are ignored for them. SBBF_EINVAL
+ * for another lane count. */
+sbbf_status sbbf_create_variant(uint32_t num_blocks, uint32_t lanes, sbbf_filter **out);
+sbbf_status sbbf_create_wrapped_variant(void *d_words, uint32_t num_blocks, uint32_t lanes, sbbf_filter **out);
+/* 32-bit words per block of the filter (8 unless made as a variant; 0 for NULL). */
+uint32_t sbbf_lanes(const sbbf_filter *f);
 /* Release the handle (and its memory when owned). Does not synchronise;
  * the caller must not destroy a filter that queued work still uses. */
 sbbf_status sbbf_destroy(sbbf_filter *f);
@@ -164,7 +189,7 @@ sbbf_status sbbf_clear(sbbf_filter *f, sbbf_stream s);
 uint32_t sbbf_num_blocks(const sbbf_filter *f);
 void *sbbf_device_words(const sbbf_filter *f);
 
-/* Copy the filter's 32 * num_blocks bytes to host memory, or replace them
+/* Copy the filter's 4 * lanes * num_blocks bytes to host memory, or replace them
  * from host memory (checkpoint and restore of the byte image). Enqueued on
  * the stream; with pageable host memory the copy completes before return,
  * with pinned memory the caller synchronises before touching host_dst. */
@@ -173,23 +198,28 @@ sbbf_status sbbf_copy_words_from_host(sbbf_filter *f, const void *host_src, sbbf
 
 /* Union: dst |= src word by word, so dst then reports present every hash
  * inserted into either (a filter is the OR of its keys' masks: appendix
- * figure, insert routine). Both filters must have the same num_blocks
- * (SBBF_EINVAL otherwise); dst == src is a no-op. Enqueued on the stream. */
+ * figure, insert routine). Both filters must have the same num_blocks and
+ * lanes (SBBF_EINVAL otherwise); dst == src is a no-op. Enqueued on the stream. */
 sbbf_status sbbf_union(sbbf_filter *dst, const sbbf_filter *src, sbbf_stream s);
 
 /* Serialized form of a filter: a 32-byte header (8 bytes "SBBF256\0",
  * uint32 version 1, uint32 seed order 1 = word j uses seed j in the
- * little-endian lane order of the appendix figure's constants, uint32
- * num_blocks, uint32 word size 4, 8 reserved zero bytes; all little-endian),
- * then the 32 * num_blocks bytes of the filter image. */
+ * little-endian lane order of the appendix figure's constants (then, for
+ * sixteen-word blocks, the eight further seeds of sbbf_create_variant),
+ * uint32 num_blocks, uint32 word size 4, uint32 words per block (8; a 0 is
+ * read as 8; 4 or 16 for the variants), 4 reserved zero bytes; all
+ * little-endian), then the 4 * lanes * num_blocks bytes of the filter image.
+ * sbbf_serialized_bytes is the size for eight-word blocks, the _variant form
+ * for any (0 for a bad lane count). */
 uint64_t sbbf_serialized_bytes(uint32_t num_blocks);
+uint64_t sbbf_serialized_bytes_variant(uint32_t num_blocks, uint32_t lanes);
 /* Write the serialized form to host memory of at least
- * sbbf_serialized_bytes(num_blocks) bytes; waits for the stream (the image
- * is the filter after all work enqueued before the call). */
+ * sbbf_serialized_bytes_variant(num_blocks, lanes) bytes; waits for the
+ * stream (the image is the filter after all work enqueued before the call). */
 sbbf_status sbbf_serialize(const sbbf_filter *f, void *host_dst, size_t capacity, sbbf_stream s);
 /* A new library-owned filter from a serialized form of exactly `size` bytes.
  * SBBF_EINVAL on a bad magic, size or block count, SBBF_EUNSUPPORTED on
- * another version, word size or seed order. Synchronous. */
+ * another version, word size, seed order or words per block. Synchronous. */
 sbbf_status sbbf_deserialize(const void *host_src, size_t size, sbbf_filter **out);
 
 /* The strategy SBBF_INSERT_AUTO / SBBF_LOOKUP_AUTO picks for a batch of n

@@ -121,6 +121,20 @@ def sbbf_blocks_for_fpr(n: int, fpr: float) -> int:
     return b
 
 
+def sbbf_fpr_model_variant(keys_per_block: float, lanes: int) -> float:
+    v = float(_L().sbbf_fpr_model_variant(keys_per_block, lanes))
+    if v < 0:
+        raise SbbfError(SBBF_EINVAL, _L().sbbf_last_error().decode())
+    return v
+
+
+def sbbf_blocks_for_fpr_variant(n: int, fpr: float, lanes: int) -> int:
+    b = int(_L().sbbf_blocks_for_fpr_variant(n, fpr, lanes))
+    if b == 0:
+        raise SbbfError(SBBF_EINVAL, _L().sbbf_last_error().decode())
+    return b
+
+
 # ---- single filter ------------------------------------------------------------------
 
 def sbbf_create(num_blocks: int) -> int:
@@ -136,6 +150,28 @@ def sbbf_create_wrapped(words: torch.Tensor, num_blocks: int | None = None) -> i
     h = ctypes.c_void_p()
     _check(_L().sbbf_create_wrapped(ctypes.c_void_p(words.data_ptr()), nb, ctypes.byref(h)))
     return h.value
+
+
+def sbbf_create_variant(num_blocks: int, lanes: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_L().sbbf_create_variant(num_blocks, lanes, ctypes.byref(h)))
+    return h.value
+
+
+def sbbf_create_wrapped_variant(words: torch.Tensor, num_blocks: int, lanes: int) -> int:
+    """Wrap a contiguous CUDA tensor holding num_blocks blocks of `lanes`
+    32-bit words (the library checks the lane count and alignment)."""
+    if not words.is_cuda or not words.is_contiguous():
+        raise ValueError("filter words must be a contiguous CUDA tensor")
+    if words.element_size() * words.numel() != 4 * lanes * num_blocks:
+        raise ValueError("tensor size does not match num_blocks * lanes words")
+    h = ctypes.c_void_p()
+    _check(_L().sbbf_create_wrapped_variant(ctypes.c_void_p(words.data_ptr()), num_blocks, lanes, ctypes.byref(h)))
+    return h.value
+
+
+def sbbf_lanes(f: int) -> int:
+    return int(_L().sbbf_lanes(f))
 
 
 def sbbf_destroy(f: int) -> None:
@@ -175,9 +211,13 @@ def sbbf_serialized_bytes(num_blocks: int) -> int:
     return int(_L().sbbf_serialized_bytes(num_blocks))
 
 
+def sbbf_serialized_bytes_variant(num_blocks: int, lanes: int) -> int:
+    return int(_L().sbbf_serialized_bytes_variant(num_blocks, lanes))
+
+
 def sbbf_serialize(f: int, stream=None) -> bytes:
     """The serialized form of the filter (header + byte image) as bytes."""
-    size = sbbf_serialized_bytes(sbbf_num_blocks(f))
+    size = sbbf_serialized_bytes_variant(sbbf_num_blocks(f), sbbf_lanes(f))
     buf = ctypes.create_string_buffer(size)
     _check(_L().sbbf_serialize(f, ctypes.cast(buf, ctypes.c_void_p), size, _stream(stream)))
     return buf.raw
@@ -506,12 +546,20 @@ class Filter:
     """A filter whose words live in a torch tensor (so they can be read back
     with ``words.cpu()``), driven through the C ABI."""
 
-    def __init__(self, num_blocks: int, device="cuda"):
+    def __init__(self, num_blocks: int, device="cuda", lanes: int = 8):
+        """num_blocks blocks of `lanes` 32-bit words: 8 is the method; 4 and
+        16 are the block variants (see sbbf_create_variant)."""
         if not 1 <= num_blocks <= 0xFFFFFFFF:
             raise ValueError("num_blocks must be in [1, 2**32 - 1]")
+        if lanes not in (4, 8, 16):
+            raise ValueError("lanes must be 4, 8 or 16")
         self.num_blocks = int(num_blocks)
-        self.words = torch.zeros(8 * self.num_blocks, dtype=torch.int32, device=device)
-        self.handle = sbbf_create_wrapped(self.words, self.num_blocks)
+        self.lanes = int(lanes)
+        self.words = torch.zeros(self.lanes * self.num_blocks, dtype=torch.int32, device=device)
+        if self.lanes == 8:
+            self.handle = sbbf_create_wrapped(self.words, self.num_blocks)
+        else:
+            self.handle = sbbf_create_wrapped_variant(self.words, self.num_blocks, self.lanes)
 
     def insert(self, hashes, launch=None, stream=None):
         sbbf_insert_batch_ex(self.handle, hashes, launch, stream)

@@ -96,12 +96,18 @@ SIGNATURES = {
     "sbbf_blocks_for": (c_u64, [c_u64, ctypes.c_double]),
     "sbbf_fpr_model": (ctypes.c_double, [ctypes.c_double]),
     "sbbf_blocks_for_fpr": (c_u64, [c_u64, ctypes.c_double]),
+    "sbbf_fpr_model_variant": (ctypes.c_double, [ctypes.c_double, c_u32]),
+    "sbbf_blocks_for_fpr_variant": (c_u64, [c_u64, ctypes.c_double, c_u32]),
     "sbbf_union": (c_int, [c_vp, c_vp, c_vp]),
     "sbbf_serialized_bytes": (c_u64, [c_u32]),
+    "sbbf_serialized_bytes_variant": (c_u64, [c_u32, c_u32]),
     "sbbf_serialize": (c_int, [c_vp, c_vp, c_size, c_vp]),
     "sbbf_deserialize": (c_int, [c_vp, c_size, ctypes.POINTER(c_vp)]),
     "sbbf_create": (c_int, [c_u32, ctypes.POINTER(c_vp)]),
     "sbbf_create_wrapped": (c_int, [c_vp, c_u32, ctypes.POINTER(c_vp)]),
+    "sbbf_create_variant": (c_int, [c_u32, c_u32, ctypes.POINTER(c_vp)]),
+    "sbbf_create_wrapped_variant": (c_int, [c_vp, c_u32, c_u32, ctypes.POINTER(c_vp)]),
+    "sbbf_lanes": (c_u32, [c_vp]),
     "sbbf_destroy": (c_int, [c_vp]),
     "sbbf_clear": (c_int, [c_vp, c_vp]),
     "sbbf_num_blocks": (c_u32, [c_vp]),

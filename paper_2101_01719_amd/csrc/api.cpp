@@ -125,6 +125,7 @@ sbbf_status resolve_shape(const sbbf_launch *cfg, uint64_t n, uint32_t default_u
   out->unroll = unroll;
   out->flags = flags;
   out->keys = 0;
+  out->lanes = 8;
   return SBBF_OK;
 }
 
@@ -166,15 +167,24 @@ uint64_t sbbf_blocks_for(uint64_t n, double bits_per_key) {
   return blocks < 1.0L ? 1 : (uint64_t)blocks;
 }
 
-sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out) {
+static bool valid_lanes(uint32_t lanes) { return lanes == 4 || lanes == 8 || lanes == 16; }
+
+// Bytes of a filter: num_blocks blocks of `lanes` 32-bit words.
+static uint64_t filter_bytes(uint32_t num_blocks, uint32_t lanes) { return (uint64_t)num_blocks * 4u * lanes; }
+static uint64_t filter_bytes(const sbbf_filter *f) { return filter_bytes(f->num_blocks, f->lanes); }
+
+sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out) { return sbbf_create_variant(num_blocks, 8, out); }
+
+sbbf_status sbbf_create_variant(uint32_t num_blocks, uint32_t lanes, sbbf_filter **out) {
   if (!out) return set_error(SBBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (num_blocks == 0) return set_error(SBBF_EINVAL, "num_blocks must be >= 1");
+  if (!valid_lanes(lanes)) return set_error(SBBF_EINVAL, "lanes must be 4, 8 or 16");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
   void *p = nullptr;
-  const size_t bytes = (size_t)num_blocks * 32u;
+  const size_t bytes = (size_t)filter_bytes(num_blocks, lanes);
   e = hipMalloc(&p, bytes);
   if (e != hipSuccess) return hip_error(e, "hipMalloc(filter)");
   e = hipMemset(p, 0, bytes);
@@ -182,7 +192,7 @@ sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out) {
     (void)hipFree(p);
     return hip_error(e, "hipMemset(filter)");
   }
-  sbbf_filter *f = new (std::nothrow) sbbf_filter{static_cast<uint32_t *>(p), num_blocks, true, dev};
+  sbbf_filter *f = new (std::nothrow) sbbf_filter{static_cast<uint32_t *>(p), num_blocks, true, dev, lanes};
   if (!f) {
     (void)hipFree(p);
     return set_error(SBBF_ENOMEM, "handle allocation failed");
@@ -192,15 +202,20 @@ sbbf_status sbbf_create(uint32_t num_blocks, sbbf_filter **out) {
 }
 
 sbbf_status sbbf_create_wrapped(void *d_words, uint32_t num_blocks, sbbf_filter **out) {
+  return sbbf_create_wrapped_variant(d_words, num_blocks, 8, out);
+}
+
+sbbf_status sbbf_create_wrapped_variant(void *d_words, uint32_t num_blocks, uint32_t lanes, sbbf_filter **out) {
   if (!out) return set_error(SBBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (!d_words) return set_error(SBBF_EINVAL, "d_words is NULL");
   if (num_blocks == 0) return set_error(SBBF_EINVAL, "num_blocks must be >= 1");
+  if (!valid_lanes(lanes)) return set_error(SBBF_EINVAL, "lanes must be 4, 8 or 16");
   if (!aligned(d_words, 32)) return set_error(SBBF_EINVAL, "filter memory must be 32-byte aligned");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
-  sbbf_filter *f = new (std::nothrow) sbbf_filter{static_cast<uint32_t *>(d_words), num_blocks, false, dev};
+  sbbf_filter *f = new (std::nothrow) sbbf_filter{static_cast<uint32_t *>(d_words), num_blocks, false, dev, lanes};
   if (!f) return set_error(SBBF_ENOMEM, "handle allocation failed");
   *out = f;
   return SBBF_OK;
@@ -219,10 +234,12 @@ sbbf_status sbbf_destroy(sbbf_filter *f) {
 
 sbbf_status sbbf_clear(sbbf_filter *f, sbbf_stream s) {
   if (!f) return set_error(SBBF_EINVAL, "filter is NULL");
-  return hip_error(launch_fill(f->words, (uint64_t)f->num_blocks * 8u, 0u, (hipStream_t)s), "clear");
+  return hip_error(launch_fill(f->words, (uint64_t)f->num_blocks * f->lanes, 0u, (hipStream_t)s), "clear");
 }
 
 uint32_t sbbf_num_blocks(const sbbf_filter *f) { return f ? f->num_blocks : 0; }
+
+uint32_t sbbf_lanes(const sbbf_filter *f) { return f ? f->lanes : 0; }
 
 // ---- sizing from a target false-positive rate, union, serialization --------
 
@@ -232,7 +249,7 @@ uint32_t sbbf_num_blocks(const sbbf_filter *f) { return f ? f->num_blocks : 0; }
 // loads Poisson(a) distributed, F(a) = sum over i of Poisson_a(i) times
 // (1 - (31/32)^i)^8. Summed in double over i within 40 sqrt(a) + 50 of a,
 // outside which the Poisson weight is far below double resolution.
-static double fpr_of_load(double a) {
+static double fpr_of_load(double a, uint32_t lanes = 8) {
   if (!(a > 0.0)) return 0.0;
   const double w = 40.0 * std::sqrt(a) + 50.0;
   const double lo = std::max(1.0, std::floor(a - w)), hi = std::ceil(a + w);
@@ -241,30 +258,45 @@ static double fpr_of_load(double a) {
   for (double i = lo; i <= hi; i += 1.0) {
     const double p = std::exp(-a + i * la - std::lgamma(i + 1.0));
     const double q = -std::expm1(i * l);  // 1 - (31/32)^i
-    const double q2 = q * q, q4 = q2 * q2;
-    s += p * (q4 * q4);
+    const double q2 = q * q, q4 = q2 * q2, q8 = q4 * q4;
+    // all `lanes` bits of a non-member set: q^lanes
+    s += p * (lanes == 8 ? q8 : lanes == 4 ? q4 : q8 * q8);
   }
   return s;
 }
 
 double sbbf_fpr_model(double keys_per_block) { return fpr_of_load(keys_per_block); }
 
-uint64_t sbbf_blocks_for_fpr(uint64_t n, double fpr) {
+double sbbf_fpr_model_variant(double keys_per_block, uint32_t lanes) {
+  if (!valid_lanes(lanes)) {
+    set_error(SBBF_EINVAL, "lanes must be 4, 8 or 16");
+    return -1.0;
+  }
+  return fpr_of_load(keys_per_block, lanes);
+}
+
+uint64_t sbbf_blocks_for_fpr(uint64_t n, double fpr) { return sbbf_blocks_for_fpr_variant(n, fpr, 8); }
+
+uint64_t sbbf_blocks_for_fpr_variant(uint64_t n, double fpr, uint32_t lanes) {
+  if (!valid_lanes(lanes)) {
+    set_error(SBBF_EINVAL, "lanes must be 4, 8 or 16");
+    return 0;
+  }
   if (!(fpr > 0.0 && fpr < 1.0)) {
     set_error(SBBF_EINVAL, "fpr must be in (0, 1)");
     return 0;
   }
   if (n == 0) return 1;
   const uint64_t max_b = 0xFFFFFFFFull;
-  if (fpr_of_load((double)n / (double)max_b) > fpr) {
+  if (fpr_of_load((double)n / (double)max_b, lanes) > fpr) {
     set_error(SBBF_EINVAL, "the target rate needs more than 2^32 - 1 blocks for this many keys");
     return 0;
   }
-  if (fpr_of_load((double)n) <= fpr) return 1;
+  if (fpr_of_load((double)n, lanes) <= fpr) return 1;
   uint64_t lo = 1, hi = max_b;  // F(n / lo) > fpr >= F(n / hi); F grows with the load
   while (hi - lo > 1) {
     const uint64_t mid = lo + (hi - lo) / 2;
-    if (fpr_of_load((double)n / (double)mid) <= fpr)
+    if (fpr_of_load((double)n / (double)mid, lanes) <= fpr)
       hi = mid;
     else
       lo = mid;
@@ -275,8 +307,10 @@ uint64_t sbbf_blocks_for_fpr(uint64_t n, double fpr) {
 sbbf_status sbbf_union(sbbf_filter *dst, const sbbf_filter *src, sbbf_stream s) {
   if (!dst || !src) return set_error(SBBF_EINVAL, "filter is NULL");
   if (dst->num_blocks != src->num_blocks) return set_error(SBBF_EINVAL, "filters differ in num_blocks");
+  if (dst->lanes != src->lanes) return set_error(SBBF_EINVAL, "filters differ in lanes per block");
   if (dst->words == src->words) return SBBF_OK;
-  return hip_error(launch_union(dst->words, src->words, (uint64_t)dst->num_blocks * 8u, (hipStream_t)s), "union");
+  return hip_error(launch_union(dst->words, src->words, (uint64_t)dst->num_blocks * dst->lanes, (hipStream_t)s),
+                   "union");
 }
 
 namespace {
@@ -285,9 +319,11 @@ struct SerialHeader {
   char magic[8];        // "SBBF256" and a zero byte
   uint32_t version;     // 1
   uint32_t seed_order;  // 1: word j uses seed j of the little-endian lane order of the appendix figure's constants
+                        //    (sixteen-word blocks: then the eight SplitMix64-derived seeds)
   uint32_t num_blocks;
   uint32_t word_bytes;  // 4
-  uint64_t reserved;    // 0
+  uint32_t lanes;       // words per block: 8 (0 is read as 8), 4 or 16
+  uint32_t reserved;    // 0
 };
 static_assert(sizeof(SerialHeader) == 32, "header is 32 bytes");
 const char kMagic[8] = {'S', 'B', 'B', 'F', '2', '5', '6', '\0'};
@@ -295,18 +331,23 @@ const char kMagic[8] = {'S', 'B', 'B', 'F', '2', '5', '6', '\0'};
 
 uint64_t sbbf_serialized_bytes(uint32_t num_blocks) { return 32u + (uint64_t)num_blocks * 32u; }
 
+uint64_t sbbf_serialized_bytes_variant(uint32_t num_blocks, uint32_t lanes) {
+  return valid_lanes(lanes) ? 32u + filter_bytes(num_blocks, lanes) : 0u;
+}
+
 sbbf_status sbbf_serialize(const sbbf_filter *f, void *host_dst, size_t capacity, sbbf_stream s) {
   if (!f || !host_dst) return set_error(SBBF_EINVAL, "filter or host_dst is NULL");
-  if (capacity < sbbf_serialized_bytes(f->num_blocks)) return set_error(SBBF_EINVAL, "host_dst is too small");
+  if (capacity < 32u + filter_bytes(f)) return set_error(SBBF_EINVAL, "host_dst is too small");
   SerialHeader h;
   memcpy(h.magic, kMagic, 8);
   h.version = 1;
   h.seed_order = 1;
   h.num_blocks = f->num_blocks;
   h.word_bytes = 4;
+  h.lanes = f->lanes;
   h.reserved = 0;
   memcpy(host_dst, &h, sizeof(h));
-  hipError_t e = hipMemcpyAsync(static_cast<char *>(host_dst) + sizeof(h), f->words, (size_t)f->num_blocks * 32u,
+  hipError_t e = hipMemcpyAsync(static_cast<char *>(host_dst) + sizeof(h), f->words, (size_t)filter_bytes(f),
                                 hipMemcpyDeviceToHost, (hipStream_t)s);
   if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(serialize)");
   return hip_error(hipStreamSynchronize((hipStream_t)s), "hipStreamSynchronize(serialize)");
@@ -321,11 +362,14 @@ sbbf_status sbbf_deserialize(const void *host_src, size_t size, sbbf_filter **ou
   if (h.version != 1 || h.word_bytes != 4) return set_error(SBBF_EUNSUPPORTED, "unsupported format version");
   if (h.seed_order != 1) return set_error(SBBF_EUNSUPPORTED, "filter written with another seed order");
   if (h.num_blocks == 0) return set_error(SBBF_EINVAL, "num_blocks is 0");
-  if (size != sbbf_serialized_bytes(h.num_blocks)) return set_error(SBBF_EINVAL, "size does not match num_blocks");
+  const uint32_t lanes = h.lanes == 0 ? 8u : h.lanes;
+  if (!valid_lanes(lanes) || h.reserved != 0) return set_error(SBBF_EUNSUPPORTED, "unsupported block layout");
+  if (size != 32u + filter_bytes(h.num_blocks, lanes))
+    return set_error(SBBF_EINVAL, "size does not match num_blocks and lanes");
   sbbf_filter *f = nullptr;
-  sbbf_status st = sbbf_create(h.num_blocks, &f);
+  sbbf_status st = sbbf_create_variant(h.num_blocks, lanes, &f);
   if (st != SBBF_OK) return st;
-  hipError_t e = hipMemcpy(f->words, static_cast<const char *>(host_src) + sizeof(h), (size_t)h.num_blocks * 32u,
+  hipError_t e = hipMemcpy(f->words, static_cast<const char *>(host_src) + sizeof(h), (size_t)filter_bytes(f),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     sbbf_destroy(f);
@@ -337,14 +381,14 @@ sbbf_status sbbf_deserialize(const void *host_src, size_t size, sbbf_filter **ou
 
 sbbf_status sbbf_copy_words_to_host(const sbbf_filter *f, void *host_dst, sbbf_stream s) {
   if (!f || !host_dst) return set_error(SBBF_EINVAL, "filter or host_dst is NULL");
-  return hip_error(hipMemcpyAsync(host_dst, f->words, (size_t)f->num_blocks * 32u, hipMemcpyDeviceToHost,
+  return hip_error(hipMemcpyAsync(host_dst, f->words, (size_t)filter_bytes(f), hipMemcpyDeviceToHost,
                                   (hipStream_t)s),
                    "hipMemcpyAsync(filter to host)");
 }
 
 sbbf_status sbbf_copy_words_from_host(sbbf_filter *f, const void *host_src, sbbf_stream s) {
   if (!f || !host_src) return set_error(SBBF_EINVAL, "filter or host_src is NULL");
-  return hip_error(hipMemcpyAsync(f->words, host_src, (size_t)f->num_blocks * 32u, hipMemcpyHostToDevice,
+  return hip_error(hipMemcpyAsync(f->words, host_src, (size_t)filter_bytes(f), hipMemcpyHostToDevice,
                                   (hipStream_t)s),
                    "hipMemcpyAsync(filter from host)");
 }
@@ -366,12 +410,15 @@ static sbbf_status check_batch(const sbbf_filter *f, const void *d_hashes, size_
 }
 
 // Slice size of the partitioned kernels: about four slices per compute unit
-// so the slice phase fills the device, at least 64 blocks (2 KiB) and at most
-// the largest power of two of blocks (up to 4096, 128 KiB) whose words fit one
-// workgroup's LDS.
-static uint32_t partition_slice_shift(const sbbf_device_info &info, uint32_t num_blocks) {
-  uint32_t max_shift = 12;
-  while (max_shift > 6 && ((uint64_t)32u << max_shift) > info.lds_per_block) --max_shift;
+// so the slice phase fills the device, at least 64 blocks and at most the
+// largest power of two of blocks (up to 128 KiB) whose words fit one
+// workgroup's LDS (4096 blocks of eight words; 8192 of four, 2048 of sixteen).
+static uint32_t partition_slice_shift(const sbbf_device_info &info, uint32_t num_blocks, uint32_t lanes) {
+  const uint64_t block_bytes = 4u * (uint64_t)lanes;
+  uint32_t max_shift = 6;
+  while (max_shift < 13 && (block_bytes << (max_shift + 1)) <= (128u << 10) &&
+         (block_bytes << (max_shift + 1)) <= info.lds_per_block)
+    ++max_shift;
   const uint64_t target = (uint64_t)num_blocks / (4u * (uint64_t)info.compute_units);
   uint32_t shift = 6;
   while (shift < max_shift && ((uint64_t)1u << (shift + 1)) <= target) ++shift;
@@ -382,8 +429,9 @@ static uint32_t partition_slices(uint32_t num_blocks, uint32_t shift) {
   return (uint32_t)(((uint64_t)num_blocks + (1u << shift) - 1u) >> shift);
 }
 
-static bool partition_fits(const sbbf_device_info &info, uint32_t num_blocks) {
-  return partition_slices(num_blocks, partition_slice_shift(info, num_blocks)) <= partition_max_slices();
+static bool partition_fits(const sbbf_device_info &info, const sbbf_filter *f) {
+  return partition_slices(f->num_blocks, partition_slice_shift(info, f->num_blocks, f->lanes)) <=
+         partition_max_slices();
 }
 
 // Library choice of insert strategy (SBBF_INSERT_AUTO): the partitioned insert
@@ -392,7 +440,7 @@ static bool partition_fits(const sbbf_device_info &info, uint32_t num_blocks) {
 // caps at about 27 G keys/s whatever the filter size) and the filter splits
 // into few enough slices; otherwise global 32-bit atomics.
 static uint32_t auto_insert_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
-  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && partition_fits(info, f->num_blocks))
+  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && partition_fits(info, f))
     return SBBF_INSERT_PARTITIONED;
   return SBBF_INSERT_ATOMIC32;
 }
@@ -402,8 +450,7 @@ static uint32_t auto_insert_strategy(const sbbf_filter *f, size_t n, const sbbf_
 // miss-handling rate beyond it, so the partitioned lookup (streaming traffic
 // only) is used for filters above 16 MiB with at least four keys per block.
 static uint32_t auto_lookup_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
-  if ((uint64_t)f->num_blocks * 32u > (16ull << 20) && (uint64_t)n >= 4u * (uint64_t)f->num_blocks &&
-      partition_fits(info, f->num_blocks))
+  if (filter_bytes(f) > (16ull << 20) && (uint64_t)n >= 4u * (uint64_t)f->num_blocks && partition_fits(info, f))
     return SBBF_LOOKUP_PARTITIONED;
   return SBBF_LOOKUP_GATHER;
 }
@@ -446,13 +493,15 @@ static sbbf_status insert_impl(sbbf_filter *f, const uint64_t *d_hashes, size_t 
     case SBBF_INSERT_ATOMIC32:
       if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
       shape.keys = keys;
+      shape.lanes = f->lanes;
       return hip_error(launch_insert_atomic32(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     case SBBF_INSERT_ATOMIC64:
       if ((st = resolve_shape(cfg, n, 2, &shape)) != SBBF_OK) return st;
       shape.keys = keys;
+      shape.lanes = f->lanes;
       return hip_error(launch_insert_atomic64(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     case SBBF_INSERT_PARTITIONED: {
-      const uint32_t shift = partition_slice_shift(*info, f->num_blocks);
+      const uint32_t shift = partition_slice_shift(*info, f->num_blocks, f->lanes);
       const uint32_t slices = partition_slices(f->num_blocks, shift);
       if (slices > partition_max_slices())
         return set_error(SBBF_EUNSUPPORTED, "filter has more than " + std::to_string(partition_max_slices()) +
@@ -465,14 +514,15 @@ static sbbf_status insert_impl(sbbf_filter *f, const uint64_t *d_hashes, size_t 
       if (e != hipSuccess) return hip_error(e, "hipMallocAsync(partition workspace)");
       for (uint64_t at = 0; at < n && e == hipSuccess; at += step) {
         const uint64_t m = n - at < step ? n - at : step;
-        e = launch_insert_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups, keys, stream);
+        e = launch_insert_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups, keys, stream,
+                                      f->lanes);
       }
       hipError_t e2 = hipFreeAsync(ws, stream);
       if (e != hipSuccess) return hip_error(e, "partitioned insert");
       return hip_error(e2, "hipFreeAsync(partition workspace)");
     }
     case SBBF_INSERT_LDS: {
-      if ((uint64_t)f->num_blocks * 32u > info->lds_per_block)
+      if (filter_bytes(f) > info->lds_per_block)
         return set_error(SBBF_EUNSUPPORTED, "filter does not fit one workgroup's LDS (" +
                                                 std::to_string(info->lds_per_block) + " bytes)");
       sbbf_launch c = cfg ? *cfg : sbbf_launch{0, 0, 0, 0, 0};
@@ -480,6 +530,7 @@ static sbbf_status insert_impl(sbbf_filter *f, const uint64_t *d_hashes, size_t 
       if (c.grid_blocks == 0) c.grid_blocks = 1;
       if ((st = resolve_shape(&c, n, 2, &shape)) != SBBF_OK) return st;
       shape.keys = keys;
+      shape.lanes = f->lanes;
       return hip_error(launch_insert_lds(d_hashes, n, f->words, f->num_blocks, shape, stream), "insert");
     }
     default:
@@ -529,7 +580,7 @@ static sbbf_status lookup_impl(const sbbf_filter *f, const uint64_t *d_hashes, s
   uint32_t strategy = cfg ? cfg->strategy : SBBF_LOOKUP_AUTO;
   if (strategy == SBBF_LOOKUP_AUTO) strategy = auto_lookup_strategy(f, n, *info);
   if (strategy == SBBF_LOOKUP_PARTITIONED) {
-    const uint32_t shift = partition_slice_shift(*info, f->num_blocks);
+    const uint32_t shift = partition_slice_shift(*info, f->num_blocks, f->lanes);
     const uint32_t slices = partition_slices(f->num_blocks, shift);
     if (slices > partition_max_slices())
       return set_error(SBBF_EUNSUPPORTED, "filter has more than " + std::to_string(partition_max_slices()) +
@@ -543,7 +594,8 @@ static sbbf_status lookup_impl(const sbbf_filter *f, const uint64_t *d_hashes, s
     for (uint64_t at = 0; at < n && e == hipSuccess; at += step) {
       const uint64_t m = n - at < step ? n - at : step;
       e = launch_lookup_partitioned(d_hashes + at, m, f->words, f->num_blocks, shift, ws, groups,
-                                    d_out ? d_out + at : nullptr, d_bits ? d_bits + at / 32 : nullptr, keys, stream);
+                                    d_out ? d_out + at : nullptr, d_bits ? d_bits + at / 32 : nullptr, keys, stream,
+                                    f->lanes);
     }
     hipError_t e2 = hipFreeAsync(ws, stream);
     if (e != hipSuccess) return hip_error(e, "partitioned lookup");
@@ -553,6 +605,7 @@ static sbbf_status lookup_impl(const sbbf_filter *f, const uint64_t *d_hashes, s
   Shape shape;
   if ((st = resolve_shape(cfg, n, 2, &shape, 4)) != SBBF_OK) return st;
   shape.keys = keys;
+  shape.lanes = f->lanes;
   return hip_error(launch_lookup(d_hashes, n, f->words, f->num_blocks, d_out, d_bits, shape, stream), "lookup");
 }
 

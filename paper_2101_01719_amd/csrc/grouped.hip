@@ -954,8 +954,12 @@ sbbf_status sbbf_grouped_create(sbbf_filter *const *filters, uint32_t num_filter
   if (!out) return set_error(SBBF_EINVAL, "out is NULL");
   *out = nullptr;
   if (num_filters == 0 || !filters) return set_error(SBBF_EINVAL, "a group needs at least one filter");
-  for (uint32_t f = 0; f < num_filters; ++f)
+  for (uint32_t f = 0; f < num_filters; ++f) {
     if (!filters[f]) return set_error(SBBF_EINVAL, "filter " + std::to_string(f) + " is NULL");
+    if (filters[f]->lanes != 8)
+      return set_error(SBBF_EUNSUPPORTED, "filter " + std::to_string(f) + " is a block variant; groups take "
+                                          "eight-word blocks only");
+  }
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");

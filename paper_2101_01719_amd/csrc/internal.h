@@ -9,10 +9,11 @@
 #include "sbbf.h"
 
 struct sbbf_filter {
-  uint32_t *words;      // 8 * num_blocks uint32, 32-byte aligned device memory
+  uint32_t *words;      // lanes * num_blocks uint32, 32-byte aligned device memory
   uint32_t num_blocks;  // 1 .. 2^32 - 1
   bool owned;           // memory allocated by sbbf_create
   int device;           // device current when the handle was made
+  uint32_t lanes;       // 32-bit words per block: 8 (the method), or 4 or 16 (block variants)
 };
 
 namespace sbbf {
@@ -24,6 +25,7 @@ struct Shape {
   uint32_t unroll;   // 64-key chunks per wave in flight (1, 2, 4, 8)
   uint32_t flags;    // SBBF_* memory-access flags
   uint32_t keys;     // 1: the input holds keys, hashed on load (key_hash)
+  uint32_t lanes;    // 32-bit words per block (8, or 4 or 16 for the block variants)
 };
 
 // Cached device facts (per device, queried once).
@@ -64,12 +66,14 @@ uint32_t partition_max_slices();
 uint64_t partition_max_keys();
 uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup);
 // keys: the input holds keys, hashed on load (key_hash).
+// lanes: 32-bit words per block (8, or 4 or 16); slices hold 2^slice_shift
+// blocks of 4 * lanes bytes.
 hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint32_t keys,
-                                     hipStream_t stream);
+                                     hipStream_t stream, uint32_t lanes = 8);
 hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
-                                     uint32_t *out_bits, uint32_t keys, hipStream_t stream);
+                                     uint32_t *out_bits, uint32_t keys, hipStream_t stream, uint32_t lanes = 8);
 
 // Stream compaction of a lookup bitmap (select.hip): the workspace starts
 // with the bitmap (ceil(n / 32) words, select_bits()) the lookup writes;

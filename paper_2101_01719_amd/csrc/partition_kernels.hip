@@ -399,11 +399,12 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   }
 }
 
-// Copy of a slice (nb blocks from block b0) into LDS: eight 16-byte loads
-// per thread issued back to back, then the LDS stores.
+// Copy of a slice (nb blocks of K words from block b0) into LDS: eight
+// 16-byte loads per thread issued back to back, then the LDS stores.
+template <uint32_t K>
 __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *words, uint32_t b0, uint32_t nb) {
-  const uint4 *src4 = reinterpret_cast<const uint4 *>(words + (uint64_t)b0 * 8u);
-  const uint32_t count = nb * 2u;
+  const uint4 *src4 = reinterpret_cast<const uint4 *>(words + (uint64_t)b0 * K);
+  const uint32_t count = nb * (K / 4u);
   for (uint32_t base = 0; base < count; base += 8u * kPartThreads) {
     uint4 v[8];
 #pragma unroll
@@ -459,7 +460,9 @@ __device__ __forceinline__ void load_step(const uint64_t *__restrict__ keys, uin
   }
 }
 
-// OR the masks of one step's keys into the slice in LDS.
+// OR the masks of one step's keys into the slice in LDS: K/2 64-bit ORs per
+// key (word pairs 2w, 2w+1 of a K-word block).
+template <uint32_t K>
 __device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, uint32_t ns, uint32_t num_blocks,
                                             uint32_t b0, uint32_t nb, unsigned long long *lds2) {
   const uint32_t lane = lane_id();
@@ -472,48 +475,44 @@ __device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, u
       const uint32_t x = (uint32_t)h;
       const uint32_t bl = min(block_of((uint32_t)(h >> 32), num_blocks) - b0, nb - 1u);
       const uint32_t one = at + k < ns ? 1u : 0u;
-      unsigned long long *blk = lds2 + (uint64_t)bl * 4u;
-      __hip_atomic_fetch_or(blk + 0, (unsigned long long)(one << bit_of(kSeed0, x)) |
-                                         ((unsigned long long)(one << bit_of(kSeed1, x)) << 32),
-                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_or(blk + 1, (unsigned long long)(one << bit_of(kSeed2, x)) |
-                                         ((unsigned long long)(one << bit_of(kSeed3, x)) << 32),
-                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_or(blk + 2, (unsigned long long)(one << bit_of(kSeed4, x)) |
-                                         ((unsigned long long)(one << bit_of(kSeed5, x)) << 32),
-                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_or(blk + 3, (unsigned long long)(one << bit_of(kSeed6, x)) |
-                                         ((unsigned long long)(one << bit_of(kSeed7, x)) << 32),
-                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      unsigned long long *blk = lds2 + (uint64_t)bl * (K / 2u);
+#pragma unroll
+      for (uint32_t w = 0; w < K / 2u; ++w)
+        __hip_atomic_fetch_or(blk + w, (unsigned long long)(one << bit_of(seed_k(2u * w), x)) |
+                                           ((unsigned long long)(one << bit_of(seed_k(2u * w + 1u), x)) << 32),
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
 }
 
-// Test one step's keys against the slice in LDS and write one result word
-// (four result bytes) per group.
+// Test one step's keys against the slice in LDS (K/4 16-byte reads per key)
+// and write one result word (four result bytes) per group.
+template <uint32_t K>
 __device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, uint32_t ns, uint32_t num_blocks,
                                             uint32_t b0, uint32_t nb, const uint4 *lds4, uint32_t begin,
                                             uint32_t spare, uint32_t *__restrict__ res4) {
+  constexpr uint32_t V = K / 4u;  // 16-byte pieces per block
   const uint32_t lane = lane_id();
 #pragma unroll
   for (uint32_t u = 0; u < kSliceSteps; ++u) {
     const uint32_t at = base + 256u * u + 4u * lane;
-    uint4 w[4][2];
+    uint4 w[4][V];
 #pragma unroll
     for (uint32_t k = 0; k < 4u; ++k) {
       const uint32_t bl = min(block_of((uint32_t)(s.h[u][k] >> 32), num_blocks) - b0, nb - 1u);
-      w[k][0] = lds4[2u * bl];
-      w[k][1] = lds4[2u * bl + 1u];
+#pragma unroll
+      for (uint32_t q = 0; q < V; ++q) w[k][q] = lds4[V * bl + q];
     }
     uint32_t r = 0;
 #pragma unroll
     for (uint32_t k = 0; k < 4u; ++k) {
       const uint32_t x = (uint32_t)s.h[u][k];
-      const uint32_t t = (w[k][0].x >> bit_of(kSeed0, x)) & (w[k][0].y >> bit_of(kSeed1, x)) &
-                         (w[k][0].z >> bit_of(kSeed2, x)) & (w[k][0].w >> bit_of(kSeed3, x)) &
-                         (w[k][1].x >> bit_of(kSeed4, x)) & (w[k][1].y >> bit_of(kSeed5, x)) &
-                         (w[k][1].z >> bit_of(kSeed6, x)) & (w[k][1].w >> bit_of(kSeed7, x)) & 1u;
-      r |= t << (8u * k);
+      uint32_t t = 1u;
+#pragma unroll
+      for (uint32_t q = 0; q < V; ++q)
+        t &= (w[k][q].x >> bit_of(seed_k(4u * q), x)) & (w[k][q].y >> bit_of(seed_k(4u * q + 1u), x)) &
+             (w[k][q].z >> bit_of(seed_k(4u * q + 2u), x)) & (w[k][q].w >> bit_of(seed_k(4u * q + 3u), x));
+      r |= (t & 1u) << (8u * k);
     }
     res4[at < ns ? (begin + at) / 4u : spare] = r;
   }
@@ -544,6 +543,8 @@ __device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, u
     }                                                                       \
   } while (0)
 
+// K: 32-bit words per block (8 for the method, 4 or 16 for the variants).
+template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
                          const uint32_t *__restrict__ tot, uint32_t *__restrict__ words, uint32_t num_blocks,
@@ -555,20 +556,21 @@ part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   if (ns == 0) return;  // whole workgroup: the slice is unchanged
   const uint32_t b0 = slice << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
-  load_slice_to_lds(lds4, words, b0, nb);
+  load_slice_to_lds<K>(lds4, words, b0, nb);
   __syncthreads();
 
   const uint64_t *keys = part + offsets[slice];
   const uint32_t last = ((ns + 3u) & ~3u) - 4u;
   constexpr uint32_t waves = kPartThreads / kWave;
-#define SBBF_INSERT_STEP(S, BASE) insert_step(S, BASE, ns, num_blocks, b0, nb, lds2)
+#define SBBF_INSERT_STEP(S, BASE) insert_step<K>(S, BASE, ns, num_blocks, b0, nb, lds2)
   SBBF_SLICE_LOOP(SBBF_INSERT_STEP);
 #undef SBBF_INSERT_STEP
   __syncthreads();
-  uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * 8u);
-  for (uint32_t i = threadIdx.x; i < nb * 2u; i += kPartThreads) dst4[i] = lds4[i];
+  uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * K);
+  for (uint32_t i = threadIdx.x; i < nb * (K / 4u); i += kPartThreads) dst4[i] = lds4[i];
 }
 
+template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
                          const uint32_t *__restrict__ tot, const uint32_t *__restrict__ words, uint32_t num_blocks,
@@ -579,7 +581,7 @@ part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   if (ns == 0) return;  // whole workgroup
   const uint32_t b0 = slice << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
-  load_slice_to_lds(lds4, words, b0, nb);
+  load_slice_to_lds<K>(lds4, words, b0, nb);
   __syncthreads();
 
   const uint32_t begin = offsets[slice];
@@ -590,7 +592,7 @@ part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   const uint32_t spare = offsets[gridDim.x] / 4u;
   const uint32_t last = ((ns + 3u) & ~3u) - 4u;
   constexpr uint32_t waves = kPartThreads / kWave;
-#define SBBF_LOOKUP_STEP(S, BASE) lookup_step(S, BASE, ns, num_blocks, b0, nb, lds4, begin, spare, res4)
+#define SBBF_LOOKUP_STEP(S, BASE) lookup_step<K>(S, BASE, ns, num_blocks, b0, nb, lds4, begin, spare, res4)
   SBBF_SLICE_LOOP(SBBF_LOOKUP_STEP);
 #undef SBBF_LOOKUP_STEP
 }
@@ -853,10 +855,37 @@ uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max
   return layout(nullptr, n, num_slices, groups, lookup).bytes;
 }
 
+// Slice insert for K-word blocks: the slice (2^slice_shift blocks of 4K
+// bytes) in dynamic LDS.
+template <uint32_t K>
+hipError_t launch_slice_insert(const PartitionLayout &L, uint32_t num_slices, uint32_t *words, uint32_t num_blocks,
+                               uint32_t slice_shift, hipStream_t stream) {
+  const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K;
+  (void)hipFuncSetAttribute((const void *)part_slice_insert_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(part_slice_insert_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
+                     L.offsets, L.tot, words, num_blocks, slice_shift);
+  return hipGetLastError();
+}
+
+template <uint32_t K>
+hipError_t launch_slice_lookup(const PartitionLayout &L, uint32_t num_slices, const uint32_t *words,
+                               uint32_t num_blocks, uint32_t slice_shift, hipStream_t stream) {
+  const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K;
+  (void)hipFuncSetAttribute((const void *)part_slice_lookup_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(part_slice_lookup_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
+                     L.offsets, L.tot, words, num_blocks, slice_shift, L.res);
+  return hipGetLastError();
+}
+
 hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint32_t keys,
-                                     hipStream_t stream) {
+                                     hipStream_t stream, uint32_t lanes) {
   if (n == 0) return hipSuccess;
+  if (lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
   uint32_t chunk, groups;
@@ -866,19 +895,16 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   hipError_t e =
       partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, false, keys, stream);
   if (e != hipSuccess) return e;
-  const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
-  (void)hipFuncSetAttribute((const void *)part_slice_insert_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes);
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(part_slice_insert_kernel, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
-                     L.offsets, L.tot, words, num_blocks, slice_shift);
-  return hipGetLastError();
+  if (lanes == 4) return launch_slice_insert<4>(L, num_slices, words, num_blocks, slice_shift, stream);
+  if (lanes == 16) return launch_slice_insert<16>(L, num_slices, words, num_blocks, slice_shift, stream);
+  return launch_slice_insert<8>(L, num_slices, words, num_blocks, slice_shift, stream);
 }
 
 hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
                                      uint32_t slice_shift, void *workspace, uint32_t max_groups, uint8_t *out8,
-                                     uint32_t *out_bits, uint32_t keys, hipStream_t stream) {
+                                     uint32_t *out_bits, uint32_t keys, hipStream_t stream, uint32_t lanes) {
   if (n == 0) return hipSuccess;
+  if (lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
   uint32_t chunk, groups;
@@ -888,13 +914,13 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
   hipError_t e =
       partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, true, keys, stream);
   if (e != hipSuccess) return e;
-  const size_t lds_bytes = ((size_t)1 << slice_shift) * 32u;
-  (void)hipFuncSetAttribute((const void *)part_slice_lookup_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_bytes);
-  (void)hipGetLastError();
-  hipLaunchKernelGGL(part_slice_lookup_kernel, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
-                     L.offsets, L.tot, words, num_blocks, slice_shift, L.res);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (lanes == 4)
+    e = launch_slice_lookup<4>(L, num_slices, words, num_blocks, slice_shift, stream);
+  else if (lanes == 16)
+    e = launch_slice_lookup<16>(L, num_slices, words, num_blocks, slice_shift, stream);
+  else
+    e = launch_slice_lookup<8>(L, num_slices, words, num_blocks, slice_shift, stream);
+  if (e != hipSuccess) return e;
   const size_t u_lds = (size_t)num_slices * 8u + 64u + chunk;
   (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)u_lds);

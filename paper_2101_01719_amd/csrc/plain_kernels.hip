@@ -7,7 +7,8 @@
 // grid-stride loop over 64-key chunks; each wave keeps `U` chunks in flight so
 // that 8U independent 32-byte block accesses are outstanding per wave.
 // `kFlags` selects cache policies only (SBBF_* flags); results never depend
-// on it.
+// on it. `K` is the number of 32-bit words per block: 8 for the method, 4 or
+// 16 for the block variants (groups of K lanes per key, K passes per chunk).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -56,14 +57,24 @@ __device__ __forceinline__ void stage(const uint64_t *__restrict__ hashes, uint6
 
 // ---- lookup -----------------------------------------------------------------
 
-template <int U, bool kBits, uint32_t kFlags>
+// Seed of word j for K-word blocks (j < K).
+template <uint32_t K>
+__device__ __forceinline__ uint32_t lane_seed(uint32_t j) {
+  if constexpr (K <= 8) {
+    return seed_of_word(j);
+  } else {
+    return seed_k(j);
+  }
+}
+
+template <int U, bool kBits, uint32_t kFlags, uint32_t K = 8>
 __global__ void __launch_bounds__(1024)
 lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *__restrict__ words,
               uint32_t num_blocks, uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits, uint32_t keys) {
   const uint32_t lane = lane_id();
-  const uint32_t j = lane & 7u;       // word of the block owned by this lane
-  const uint32_t group = lane & ~7u;  // first lane of this lane's 8-lane group
-  const uint32_t seed = seed_of_word(j);
+  const uint32_t j = lane & (K - 1u);       // word of the block owned by this lane
+  const uint32_t group = lane & ~(K - 1u);  // first lane of this lane's K-lane group
+  const uint32_t seed = lane_seed<K>(j);
   const WaveCursor wc = wave_cursor();
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
 
@@ -72,15 +83,15 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
     stage<U, kFlags>(hashes, n, base, num_blocks, lane, keys, blk, lo);
 
     // Issue every block read of the U chunks before testing any of them.
-    uint32_t word[U][8], bit[U][8];
+    uint32_t word[U][K], bit[U][K];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
+      for (uint32_t p = 0; p < K; ++p) {
         const uint32_t b = lane_read(blk[u], group + p);
         const uint32_t x = lane_read(lo[u], group + p);
         bit[u][p] = bit_of(seed, x);
-        word[u][p] = load_word<kFlags>(words + (uint64_t)b * 8u + j);
+        word[u][p] = load_word<kFlags>(words + (uint64_t)b * K + j);
       }
     }
 
@@ -88,7 +99,7 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
     for (int u = 0; u < U; ++u) {
       uint64_t r = 0;
 #pragma unroll
-      for (int p = 0; p < 8; ++p) r |= fold_pass(ballot((word[u][p] >> bit[u][p]) & 1u), p);
+      for (uint32_t p = 0; p < K; ++p) r |= fold_pass_k<K>(ballot((word[u][p] >> bit[u][p]) & 1u), p);
       const uint64_t i0 = base + (uint64_t)(kWave * u);
       if (i0 >= n) break;
       if constexpr (!kBits) {
@@ -106,14 +117,14 @@ lookup_kernel(const uint64_t *__restrict__ hashes, uint64_t n, const uint32_t *_
 
 // ---- insert: 32-bit global atomics, one key per 8 lanes ---------------------
 
-template <int U, uint32_t kFlags>
+template <int U, uint32_t kFlags, uint32_t K = 8>
 __global__ void __launch_bounds__(1024)
 insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
                        uint32_t num_blocks, uint32_t keys) {
   const uint32_t lane = lane_id();
-  const uint32_t j = lane & 7u;
-  const uint32_t group = lane & ~7u;
-  const uint32_t seed = seed_of_word(j);
+  const uint32_t j = lane & (K - 1u);
+  const uint32_t group = lane & ~(K - 1u);
+  const uint32_t seed = lane_seed<K>(j);
   const WaveCursor wc = wave_cursor();
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
 
@@ -123,12 +134,12 @@ insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
+      for (uint32_t p = 0; p < K; ++p) {
         const uint32_t b = lane_read(blk[u], group + p);
         const uint32_t x = lane_read(lo[u], group + p);
         const uint64_t key = base + (uint64_t)(kWave * u) + group + p;
         if (key < n) {
-          __hip_atomic_fetch_or(words + (uint64_t)b * 8u + j, 1u << bit_of(seed, x), __ATOMIC_RELAXED,
+          __hip_atomic_fetch_or(words + (uint64_t)b * K + j, 1u << bit_of(seed, x), __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);
         }
       }
@@ -136,19 +147,21 @@ insert_atomic32_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
   }
 }
 
-// ---- insert: 64-bit global atomics, one key per 4 lanes ---------------------
-// Lane l handles words 2q and 2q+1 (q = l % 4) of the key of lane 4g + p in
-// pass p (g = l / 4), so a pass covers 16 keys and four passes a chunk.
+// ---- insert: 64-bit global atomics, one key per K/2 lanes -------------------
+// With Q = K/2, lane l handles words 2q and 2q+1 (q = l % Q) of the key of
+// lane Q g + p in pass p (g = l / Q), so a pass covers 64/Q keys and Q passes
+// a chunk (for K = 8: 16 keys per pass, four passes).
 
-template <int U, uint32_t kFlags>
+template <int U, uint32_t kFlags, uint32_t K = 8>
 __global__ void __launch_bounds__(1024)
 insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
                        uint32_t num_blocks, uint32_t keys) {
+  constexpr uint32_t Q = K / 2u;
   const uint32_t lane = lane_id();
-  const uint32_t q = lane & 3u;
-  const uint32_t group = lane & ~3u;
-  const uint32_t seed_lo = seed_of_word(2u * q);
-  const uint32_t seed_hi = seed_of_word(2u * q + 1u);
+  const uint32_t q = lane & (Q - 1u);
+  const uint32_t group = lane & ~(Q - 1u);
+  const uint32_t seed_lo = lane_seed<K>(2u * q);
+  const uint32_t seed_hi = lane_seed<K>(2u * q + 1u);
   unsigned long long *pairs = reinterpret_cast<unsigned long long *>(words);
   const WaveCursor wc = wave_cursor();
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
@@ -159,14 +172,14 @@ insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
+      for (uint32_t p = 0; p < Q; ++p) {
         const uint32_t b = lane_read(blk[u], group + p);
         const uint32_t x = lane_read(lo[u], group + p);
         const uint64_t key = base + (uint64_t)(kWave * u) + group + p;
         if (key < n) {
           const unsigned long long m = (unsigned long long)(1u << bit_of(seed_lo, x)) |
                                        ((unsigned long long)(1u << bit_of(seed_hi, x)) << 32);
-          __hip_atomic_fetch_or(pairs + (uint64_t)b * 4u + q, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_or(pairs + (uint64_t)b * Q + q, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
@@ -174,28 +187,28 @@ insert_atomic64_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t
 }
 
 // ---- insert: LDS-private copies -----------------------------------------------
-// The whole filter (8 * num_blocks words) lives in this workgroup's LDS. With
+// The whole filter (K * num_blocks words) lives in this workgroup's LDS. With
 // one workgroup it starts from the filter's current contents and is stored
 // back with plain stores (the workgroup is the only writer). With several,
 // each starts from zero, ORs its share of the keys, and ORs its non-zero
 // 64-bit word pairs into the filter with global atomics.
 
-template <int U, uint32_t kFlags>
+template <int U, uint32_t kFlags, uint32_t K = 8>
 __global__ void __launch_bounds__(1024)
 insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__restrict__ words,
                   uint32_t num_blocks, uint32_t keys) {
   extern __shared__ uint4 lds4[];
   uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
-  const uint32_t n_vec4 = num_blocks * 2u;  // 32 bytes per block = 2 x uint4
+  const uint32_t n_vec4 = num_blocks * (K / 4u);  // 4K bytes per block = K/4 x uint4
   const bool owner = gridDim.x == 1;
   const uint4 *src4 = reinterpret_cast<const uint4 *>(words);
   for (uint32_t i = threadIdx.x; i < n_vec4; i += blockDim.x) lds4[i] = owner ? src4[i] : make_uint4(0, 0, 0, 0);
   __syncthreads();
 
   const uint32_t lane = lane_id();
-  const uint32_t j = lane & 7u;
-  const uint32_t group = lane & ~7u;
-  const uint32_t seed = seed_of_word(j);
+  const uint32_t j = lane & (K - 1u);
+  const uint32_t group = lane & ~(K - 1u);
+  const uint32_t seed = lane_seed<K>(j);
   const WaveCursor wc = wave_cursor();
   constexpr uint64_t kChunk = (uint64_t)kWave * U;
   for (uint64_t base = wc.first * kChunk; base < n; base += wc.stride * kChunk) {
@@ -204,12 +217,12 @@ insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__r
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int p = 0; p < 8; ++p) {
+      for (uint32_t p = 0; p < K; ++p) {
         const uint32_t b = lane_read(blk[u], group + p);
         const uint32_t x = lane_read(lo[u], group + p);
         const uint64_t key = base + (uint64_t)(kWave * u) + group + p;
         if (key < n) {
-          __hip_atomic_fetch_or(lds + b * 8u + j, 1u << bit_of(seed, x), __ATOMIC_RELAXED,
+          __hip_atomic_fetch_or(lds + b * K + j, 1u << bit_of(seed, x), __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
@@ -223,7 +236,7 @@ insert_lds_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint32_t *__r
   } else {
     const unsigned long long *lds2 = reinterpret_cast<const unsigned long long *>(lds4);
     unsigned long long *pairs = reinterpret_cast<unsigned long long *>(words);
-    for (uint32_t i = threadIdx.x; i < num_blocks * 4u; i += blockDim.x) {
+    for (uint32_t i = threadIdx.x; i < num_blocks * (K / 2u); i += blockDim.x) {
       const unsigned long long v = lds2[i];
       if (v) __hip_atomic_fetch_or(pairs + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -360,6 +373,13 @@ bench_stream_kernel(const uint64_t *__restrict__ hashes, uint64_t n, uint8_t *__
     default: return hipErrorInvalidValue; \
   }
 
+#define SBBF_DISPATCH_U2(u, BODY)         \
+  switch (u) {                            \
+    case 1: { BODY(1) }                   \
+    case 2: { BODY(2) }                   \
+    default: return hipErrorInvalidValue; \
+  }
+
 #define SBBF_DISPATCH_U8(u, BODY)         \
   switch (u) {                            \
     case 1: { BODY(1) }                   \
@@ -411,6 +431,29 @@ struct LookupLauncher {
   }
 };
 
+// Lookups in the four- and sixteen-word block variants, with the default
+// cache policies. Sixteen-word blocks keep at most two chunks in flight per
+// wave (32 block words per lane).
+template <uint32_t K>
+hipError_t run_lookup_variant(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
+                              uint8_t *out8, uint32_t *out_bits, const Shape &s, hipStream_t stream) {
+  const dim3 g(s.grid), b(s.threads);
+#define BODY(U)                                                                                              \
+  if (out_bits)                                                                                              \
+    hipLaunchKernelGGL((lookup_kernel<U, true, 0, K>), g, b, 0, stream, hashes, n, words, num_blocks, nullptr, \
+                       out_bits, s.keys);                                                                    \
+  else                                                                                                       \
+    hipLaunchKernelGGL((lookup_kernel<U, false, 0, K>), g, b, 0, stream, hashes, n, words, num_blocks, out8,   \
+                       nullptr, s.keys);                                                                     \
+  return hipGetLastError();
+  if constexpr (K == 16) {
+    SBBF_DISPATCH_U2(s.unroll > 2 ? 2u : s.unroll, BODY)
+  } else {
+    SBBF_DISPATCH_U4(s.unroll, BODY)
+  }
+#undef BODY
+}
+
 template <uint32_t F>
 struct GatherLauncher {
   static hipError_t run(const uint32_t *buf, uint32_t num_blocks, const uint64_t *hashes, uint64_t n, uint8_t *out,
@@ -425,32 +468,33 @@ struct GatherLauncher {
 };
 
 // Inserts only use the hash-load flag, so each insert kernel exists in two
-// cache variants (H = 0 or SBBF_HASH_LOAD_CACHED).
-template <uint32_t H>
+// cache variants (H = 0 or SBBF_HASH_LOAD_CACHED); the block variants (K = 4
+// or 16 words) use the default.
+template <uint32_t H, uint32_t K = 8>
 hipError_t run_insert(int kind, const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                       const Shape &s, hipStream_t stream) {
   const dim3 g(s.grid), b(s.threads);
   if (kind == SBBF_INSERT_ATOMIC32) {
 #define BODY(U)                                                                                       \
-  hipLaunchKernelGGL((insert_atomic32_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks, s.keys); \
+  hipLaunchKernelGGL((insert_atomic32_kernel<U, H, K>), g, b, 0, stream, hashes, n, words, num_blocks, s.keys); \
   return hipGetLastError();
     SBBF_DISPATCH_U8(s.unroll, BODY)
 #undef BODY
   }
   if (kind == SBBF_INSERT_ATOMIC64) {
 #define BODY(U)                                                                                       \
-  hipLaunchKernelGGL((insert_atomic64_kernel<U, H>), g, b, 0, stream, hashes, n, words, num_blocks, s.keys); \
+  hipLaunchKernelGGL((insert_atomic64_kernel<U, H, K>), g, b, 0, stream, hashes, n, words, num_blocks, s.keys); \
   return hipGetLastError();
     SBBF_DISPATCH_U8(s.unroll, BODY)
 #undef BODY
   }
-  const size_t lds_bytes = (size_t)num_blocks * 32u;
+  const size_t lds_bytes = (size_t)num_blocks * 4u * K;
 #define BODY(U)                                                                                              \
   /* Raise the dynamic LDS limit; an error here shows up at launch. */                                       \
-  (void)hipFuncSetAttribute((const void *)insert_lds_kernel<U, H>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+  (void)hipFuncSetAttribute((const void *)insert_lds_kernel<U, H, K>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                             (int)lds_bytes);                                                                 \
   (void)hipGetLastError();                                                                                   \
-  hipLaunchKernelGGL((insert_lds_kernel<U, H>), g, b, lds_bytes, stream, hashes, n, words, num_blocks, s.keys); \
+  hipLaunchKernelGGL((insert_lds_kernel<U, H, K>), g, b, lds_bytes, stream, hashes, n, words, num_blocks, s.keys); \
   return hipGetLastError();
   SBBF_DISPATCH_U8(s.unroll, BODY)
 #undef BODY
@@ -459,6 +503,9 @@ hipError_t run_insert(int kind, const uint64_t *hashes, uint64_t n, uint32_t *wo
 hipError_t insert_any(int kind, const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
                       const Shape &s, hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  if (s.lanes == 4) return run_insert<0, 4>(kind, hashes, n, words, num_blocks, s, stream);
+  if (s.lanes == 16) return run_insert<0, 16>(kind, hashes, n, words, num_blocks, s, stream);
+  if (s.lanes != 8) return hipErrorInvalidValue;
   if (s.flags & SBBF_HASH_LOAD_CACHED)
     return run_insert<SBBF_HASH_LOAD_CACHED>(kind, hashes, n, words, num_blocks, s, stream);
   return run_insert<0>(kind, hashes, n, words, num_blocks, s, stream);
@@ -469,6 +516,9 @@ hipError_t insert_any(int kind, const uint64_t *hashes, uint64_t n, uint32_t *wo
 hipError_t launch_lookup(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
                          uint8_t *out8, uint32_t *out_bits, const Shape &s, hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  if (s.lanes == 4) return run_lookup_variant<4>(hashes, n, words, num_blocks, out8, out_bits, s, stream);
+  if (s.lanes == 16) return run_lookup_variant<16>(hashes, n, words, num_blocks, out8, out_bits, s, stream);
+  if (s.lanes != 8) return hipErrorInvalidValue;
   return dispatch_flags<LookupLauncher>(s.flags, hashes, n, words, num_blocks, out8, out_bits, s, stream);
 }
 

@@ -47,6 +47,34 @@ __device__ __forceinline__ uint32_t seed_of_word(uint32_t j) {
   return (j & 4) ? cd : ab;
 }
 
+// Block variants with K = 4 or 16 words (the paper notes that four or sixteen
+// lanes would work as well as eight, and prints seeds for eight only). Four
+// lanes use seeds 0..3 above. Sixteen lanes use the eight above for words
+// 0..7 and these for words 8..15: the low 32 bits of the first eight outputs
+// of SplitMix64 seeded with 16, each with its lowest bit set (odd, as
+// multiply-shift hashing needs).
+constexpr uint32_t kSeed8 = 0xba779207u;
+constexpr uint32_t kSeed9 = 0xc985644bu;
+constexpr uint32_t kSeed10 = 0xa4e84675u;
+constexpr uint32_t kSeed11 = 0xe421c8dbu;
+constexpr uint32_t kSeed12 = 0xbd38674fu;
+constexpr uint32_t kSeed13 = 0x58ee486du;
+constexpr uint32_t kSeed14 = 0x8ddb3387u;
+constexpr uint32_t kSeed15 = 0x7ea09599u;
+
+// Seed of word j (0..15) of a block of any variant (the first K are used).
+// A select chain for run-time j, folded to a constant for a constant j.
+__host__ __device__ constexpr uint32_t seed_k(uint32_t j) {
+  const uint32_t lo[8] = {kSeed0, kSeed1, kSeed2, kSeed3, kSeed4, kSeed5, kSeed6, kSeed7};
+  const uint32_t hi[8] = {kSeed8, kSeed9, kSeed10, kSeed11, kSeed12, kSeed13, kSeed14, kSeed15};
+  uint32_t a = 0, b = 0;
+  for (uint32_t i = 0; i < 8; ++i) {
+    a = (j & 7u) == i ? lo[i] : a;
+    b = (j & 7u) == i ? hi[i] : b;
+  }
+  return j < 8u ? a : b;
+}
+
 // Block of a hash: high 32 bits of hi32(h) * num_blocks (a 32x32 multiply-high).
 __device__ __forceinline__ uint32_t block_of(uint32_t hash_hi, uint32_t num_blocks) {
   return __umulhi(hash_hi, num_blocks);
@@ -129,6 +157,19 @@ __device__ __forceinline__ uint64_t fold_pass(uint64_t m, int p) {
   t &= t >> 2;
   t &= t >> 1;
   return (t & 0x0101010101010101ull) << p;
+}
+
+// fold_pass for K-lane groups: in pass p, group g of K lanes holds the K
+// word tests of the key of lane K g + p; the result bit of that key is the
+// AND of the group's K bits, placed at bit K g + p.
+template <uint32_t K>
+__device__ __forceinline__ uint64_t fold_pass_k(uint64_t m, uint32_t p) {
+  static_assert(K == 4 || K == 8 || K == 16, "four, eight or sixteen lanes");
+  uint64_t t = m;
+#pragma unroll
+  for (uint32_t s = K / 2; s >= 1; s /= 2) t &= t >> s;
+  constexpr uint64_t kFirst = K == 4 ? 0x1111111111111111ull : K == 8 ? 0x0101010101010101ull : 0x0001000100010001ull;
+  return (t & kFirst) << p;
 }
 
 // Workgroup barrier that orders LDS accesses only: outstanding global loads

@@ -70,8 +70,8 @@ def test_serialize_round_trip(P, B):
     f.insert(dev(keys))
     blob = f.serialize()
     assert len(blob) == P.sbbf_serialized_bytes(B) == 32 + 32 * B
-    magic, version, order, nb, wb, reserved = struct.unpack("<8sIIIIQ", blob[:32])
-    assert (magic, version, order, nb, wb, reserved) == (b"SBBF256\0", 1, 1, B, 4, 0)
+    magic, version, order, nb, wb, lanes, reserved = struct.unpack("<8sIIIIII", blob[:32])
+    assert (magic, version, order, nb, wb, lanes, reserved) == (b"SBBF256\0", 1, 1, B, 4, 8, 0)
     ref = oracle.build_filter(B, keys)
     assert np.array_equal(np.frombuffer(blob[32:], dtype="<u4"), ref)
     h = P.sbbf_deserialize(blob)
@@ -95,7 +95,14 @@ def test_deserialize_rejects_bad_input(P):
            bytes(blob[:12]) + struct.pack("<I", 2) + bytes(blob[16:]),  # seed order
            bytes(blob[:16]) + struct.pack("<I", 0) + bytes(blob[20:]),  # zero blocks
            bytes(blob[:16]) + struct.pack("<I", 4) + bytes(blob[20:]),  # size mismatch
+           bytes(blob[:24]) + struct.pack("<I", 5) + bytes(blob[28:]),  # words per block
+           bytes(blob[:24]) + struct.pack("<I", 4) + bytes(blob[28:]),  # lanes 4: size mismatch
+           bytes(blob[:28]) + struct.pack("<I", 1) + bytes(blob[32:]),  # reserved bits
            bytes(blob) + b"\0"]                               # trailing byte
     for b in bad:
         with pytest.raises(P.SbbfError):
             P.sbbf_deserialize(b)
+    # a header written with a zero words-per-block field reads as eight
+    h = P.sbbf_deserialize(bytes(blob[:24]) + struct.pack("<I", 0) + bytes(blob[28:]))
+    assert P.sbbf_lanes(h) == 8
+    P.sbbf_destroy(h)

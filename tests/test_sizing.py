@@ -66,3 +66,32 @@ def test_blocks_for_fpr_errors(P):
             P.sbbf_blocks_for_fpr(1000, bad)
     with pytest.raises(P.SbbfError):
         P.sbbf_blocks_for_fpr(2**62, 1e-6)  # needs more than 2^32 - 1 blocks
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16])
+@pytest.mark.parametrize("a", [0.01, 1.0, 12.2, 24.38, 48.8, 100.0])
+def test_variant_model_matches_oracle(P, lanes, a):
+    got, ref = P.sbbf_fpr_model_variant(a, lanes), fpr.sbbf_fpr(a, lanes)
+    assert got == pytest.approx(ref, rel=1e-12, abs=1e-300)
+    if lanes == 8:
+        assert got == P.sbbf_fpr_model(a)
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+@pytest.mark.parametrize("n,target", [(1000, 0.01), (1_000_000, 0.0274), (100_000_000, 0.0091), (50_000, 0.001)])
+def test_variant_blocks_for_fpr_matches_oracle(P, lanes, n, target):
+    B = P.sbbf_blocks_for_fpr_variant(n, target, lanes)
+    assert fpr.sbbf_fpr(n / B, lanes) <= target * (1 + 1e-12)
+    assert B == 1 or fpr.sbbf_fpr(n / (B - 1), lanes) > target * (1 - 1e-12)
+    assert abs(B - fpr.blocks_for_fpr(n, target, lanes=lanes)) <= 1
+
+
+def test_variant_sizing_errors(P):
+    for bad in (0, 3, 5, 32):
+        with pytest.raises(P.SbbfError):
+            P.sbbf_fpr_model_variant(10.0, bad)
+        with pytest.raises(P.SbbfError):
+            P.sbbf_blocks_for_fpr_variant(1000, 0.01, bad)
+    assert P.sbbf_serialized_bytes_variant(10, 4) == 32 + 160
+    assert P.sbbf_serialized_bytes_variant(10, 16) == 32 + 640
+    assert P.sbbf_serialized_bytes_variant(10, 3) == 0
