@@ -352,7 +352,8 @@ def _host_cpu() -> str:
 def _ceilings(P, torch, w, look_launch, ins_launch, reps=5):
     """Measured ceilings with the same access pattern and launch shape:
     random 32-byte gather (lookup without the mask), random 8 x 32-bit atomic
-    OR (insert without the mask), and streaming (8 B in, 1 B out)."""
+    OR (insert without the mask), streaming (8 B in, 1 B out), and a plain
+    device copy."""
     buf = torch.full((8 * w.num_blocks,), 1, dtype=torch.int32, device="cuda")
     out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
     res = {}
@@ -379,7 +380,12 @@ def _ceilings(P, torch, w, look_launch, ins_launch, reps=5):
     t = timed(lambda: P.sbbf_bench_stream(w.lookups, out, launch=look_launch))
     res["stream_gkeys_per_s"] = w.lookups.numel() / t / 1e9
     res["stream_GBps"] = 9 * w.lookups.numel() / t / 1e9
-    del buf, out
+    # A plain device copy of the lookup hashes (equal read and write
+    # traffic): the practical bandwidth of a read-and-write streaming pass.
+    dst = torch.empty_like(w.lookups)
+    t = timed(lambda: dst.copy_(w.lookups))
+    res["copy_GBps"] = 2 * 8 * w.lookups.numel() / t / 1e9
+    del buf, out, dst
     return res
 
 
