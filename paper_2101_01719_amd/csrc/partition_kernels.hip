@@ -184,13 +184,19 @@ struct ScatterLds {
 };
 
 // Hashes of tile t0 for this thread: index t0 + t * kScatterThreads + thread,
-// clamped to the chunk's last key so loads never branch.
+// clamped to the chunk's last key so loads never branch. Lookups load them
+// through the caches and inserts with the non-temporal hint: measured on
+// MI355X at 1e8 inserts and 2e8 lookups into 128 MiB, that order is 6 %
+// faster for the lookup scatter (and its slice kernel) and 5 % faster for
+// the insert scatter than the other.
+template <bool kCached>
 __device__ __forceinline__ void load_tile(const uint64_t *__restrict__ hashes, uint32_t t0, uint32_t e,
                                           uint64_t (&h)[kScatterPer]) {
+  constexpr uint32_t kLoad = kCached ? (uint32_t)SBBF_HASH_LOAD_CACHED : 0u;
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
-    h[t] = load_hash<0>(hashes + (i < e ? i : e - 1u));
+    h[t] = load_hash<kLoad>(hashes + (i < e ? i : e - 1u));
   }
 }
 
@@ -294,7 +300,9 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     if (kFull || i < e) {
       const uint32_t k = S.sbase[s[t]] + rank[t];
       S.stage[k] = h[t];
-      if constexpr (kWithPos) out_pos[i] = (uint16_t)(k + S.pdelta[s[t]]);
+      // Positions are read back only by the unpermute kernel, after the
+      // slice phase: stored non-temporally (3 % faster lookups on MI355X).
+      if constexpr (kWithPos) __builtin_nontemporal_store((uint16_t)(k + S.pdelta[s[t]]), out_pos + i);
     }
   }
   lds_barrier();
@@ -366,7 +374,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   // issued before this tile's stores and need no register copies.
   const uint32_t nfull = (e - b) / kTile;
   uint64_t ha[kScatterPer], hb[kScatterPer];
-  load_tile(hashes, b, e, ha);
+  load_tile<kWithPos>(hashes, b, e, ha);
   uint32_t t0 = b, k = 0;
 #define SBBF_SCATTER_TILE(FULL, H)                                                                            \
   scatter_tile<kWithPos, R, L, FULL>(H, t0, e, t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * \
@@ -374,15 +382,15 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
                                                                              : nullptr,                        \
                                      num_blocks, slice_shift, num_slices, keys, S, C, out_keys, out_pos)
   for (; k + 2u <= nfull; k += 2u) {
-    load_tile(hashes, t0 + kTile, e, hb);
+    load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
     SBBF_SCATTER_TILE(true, ha);
     t0 += kTile;
-    load_tile(hashes, t0 + kTile, e, ha);
+    load_tile<kWithPos>(hashes, t0 + kTile, e, ha);
     SBBF_SCATTER_TILE(true, hb);
     t0 += kTile;
   }
   if (k < nfull) {
-    load_tile(hashes, t0 + kTile, e, hb);
+    load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
     SBBF_SCATTER_TILE(true, ha);
     t0 += kTile;
     if (t0 < e) SBBF_SCATTER_TILE(false, hb);
@@ -441,18 +449,21 @@ __device__ __forceinline__ uint32_t wave_index() {
 
 // Hashes of one loop step for this lane: kSliceSteps groups of four keys
 // (steps of 256 keys), each group index clamped to the slice's last group.
+// The lookup kernel loads them through the caches, the insert kernel with the
+// non-temporal hint (each the faster of the two for that kernel on MI355X).
 struct SliceStep {
   uint64_t h[kSliceSteps][4];
 };
 
+template <bool kCached>
 __device__ __forceinline__ void load_step(const uint64_t *__restrict__ keys, uint32_t base, uint32_t last,
                                           SliceStep &s) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (uint32_t u = 0; u < kSliceSteps; ++u) {
     const u64x2 *p = reinterpret_cast<const u64x2 *>(keys + min(base + 256u * u + 4u * lane, last));
-    const u64x2 a = __builtin_nontemporal_load(p);
-    const u64x2 b = __builtin_nontemporal_load(p + 1);
+    const u64x2 a = kCached ? p[0] : __builtin_nontemporal_load(p);
+    const u64x2 b = kCached ? p[1] : __builtin_nontemporal_load(p + 1);
     s.h[u][0] = a.x;
     s.h[u][1] = a.y;
     s.h[u][2] = b.x;
@@ -530,13 +541,13 @@ __device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, u
     uint32_t base = wave_index() * 256u * kSliceSteps;                      \
     const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u; \
     SliceStep sa, sb;                                                       \
-    load_step(keys, base, last, sa);                                        \
+    load_step<kCachedKeys>(keys, base, last, sa);                           \
     for (uint32_t it = 0; it < steps; it += 2u) {                           \
-      load_step(keys, base + stride, last, sb);                             \
+      load_step<kCachedKeys>(keys, base + stride, last, sb);                \
       __builtin_amdgcn_sched_barrier(0);                                    \
       STEP(sa, base);                                                       \
       base += stride;                                                       \
-      load_step(keys, base + stride, last, sa);                             \
+      load_step<kCachedKeys>(keys, base + stride, last, sa);                \
       __builtin_amdgcn_sched_barrier(0);                                    \
       STEP(sb, base);                                                       \
       base += stride;                                                       \
@@ -562,6 +573,7 @@ part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   const uint64_t *keys = part + offsets[slice];
   const uint32_t last = ((ns + 3u) & ~3u) - 4u;
   constexpr uint32_t waves = kPartThreads / kWave;
+  constexpr bool kCachedKeys = false;
 #define SBBF_INSERT_STEP(S, BASE) insert_step<K>(S, BASE, ns, num_blocks, b0, nb, lds2)
   SBBF_SLICE_LOOP(SBBF_INSERT_STEP);
 #undef SBBF_INSERT_STEP
@@ -592,6 +604,7 @@ part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   const uint32_t spare = offsets[gridDim.x] / 4u;
   const uint32_t last = ((ns + 3u) & ~3u) - 4u;
   constexpr uint32_t waves = kPartThreads / kWave;
+  constexpr bool kCachedKeys = true;
 #define SBBF_LOOKUP_STEP(S, BASE) lookup_step<K>(S, BASE, ns, num_blocks, b0, nb, lds4, begin, spare, res4)
   SBBF_SLICE_LOOP(SBBF_LOOKUP_STEP);
 #undef SBBF_LOOKUP_STEP
