@@ -31,6 +31,16 @@ namespace {
 constexpr uint32_t kServeThreads = 256;
 constexpr uint32_t kServeUnroll = 2;
 constexpr uint32_t kArenaAlign = 256;
+// Inserts into filters of at most this many blocks (32 KiB) are ORed into a
+// zeroed LDS copy first and merged with one device atomic per non-zero 64-bit
+// word pair: a tile's keys land on few blocks of such a filter, and per-key
+// device atomics on the same words serialize.
+constexpr uint32_t kServeLdsBlocks = 1024;
+// Lookup tiles are laid out so that workgroup i runs on XCD i % 8 (workgroups
+// are dealt to the eight XCDs in turn) and every tile of a filter on the same
+// XCD, so a filter's blocks are cached in one L2 instead of eight.
+constexpr uint32_t kServeXcds = 8;
+constexpr uint64_t kServeSlack = 65536;
 
 struct STile {
   const uint64_t *keys;
@@ -40,14 +50,50 @@ struct STile {
   uint32_t count;
 };
 
-// One workgroup per tile; 8-lane layout, 32-bit global atomics.
+// One workgroup per tile; 8-lane layout. Small filters: 32-bit LDS atomics
+// into a zeroed copy, then one 64-bit device atomic per non-zero word pair;
+// larger filters: 32-bit device atomics.
 __global__ void __launch_bounds__(kServeThreads) serve_insert_kernel(const STile *__restrict__ tiles) {
+  __shared__ unsigned long long lds2[kServeLdsBlocks * 4u];
   const STile t = tiles[blockIdx.x];
   const uint32_t lane = lane_id();
   const uint32_t j = lane & 7u;
   const uint32_t group = lane & ~7u;
   const uint32_t seed = seed_of_word(j);
   constexpr uint32_t kChunk = 64u * kServeUnroll;
+  const bool small = t.num_blocks <= kServeLdsBlocks;  // uniform over the workgroup
+  if (small) {
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds2);
+    for (uint32_t i = threadIdx.x; i < t.num_blocks * 4u; i += blockDim.x) lds2[i] = 0ull;
+    __syncthreads();
+    for (uint32_t base = (threadIdx.x / kWave) * kChunk; base < t.count; base += (blockDim.x / kWave) * kChunk) {
+      uint32_t blk[kServeUnroll], lo[kServeUnroll];
+#pragma unroll
+      for (uint32_t u = 0; u < kServeUnroll; ++u) {
+        const uint32_t i = base + 64u * u + lane;
+        const uint64_t h = load_hash<0>(t.keys + (i < t.count ? i : t.count - 1u));
+        lo[u] = (uint32_t)h;
+        blk[u] = block_of((uint32_t)(h >> 32), t.num_blocks);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kServeUnroll; ++u) {
+#pragma unroll
+        for (uint32_t p = 0; p < 8; ++p) {
+          const uint32_t b = lane_read(blk[u], group + p);
+          const uint32_t x = lane_read(lo[u], group + p);
+          __hip_atomic_fetch_or(lds + b * 8u + j, 1u << bit_of(seed, x), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      }
+    }
+    __syncthreads();
+    unsigned long long *pairs = reinterpret_cast<unsigned long long *>(t.words);
+    for (uint32_t i = threadIdx.x; i < t.num_blocks * 4u; i += blockDim.x) {
+      const unsigned long long v = lds2[i];
+      if (v) __hip_atomic_fetch_or(pairs + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
   for (uint32_t base = (threadIdx.x / kWave) * kChunk; base < t.count; base += (blockDim.x / kWave) * kChunk) {
     uint32_t blk[kServeUnroll], lo[kServeUnroll];
 #pragma unroll
@@ -243,8 +289,10 @@ namespace sbbf {
 namespace {
 
 sbbf_status server_make_slots(sbbf_server *s) {
-  const uint32_t tiles = (uint32_t)((s->cfg.max_step_keys + s->cfg.tile_keys - 1) / s->cfg.tile_keys) +
-                         s->cfg.max_step_requests + 1;
+  // Real tiles of a full step, twice over for the padding of the per-XCD
+  // lookup queues (a slot grows later if a step needs more).
+  const uint32_t tiles = 2u * ((uint32_t)((s->cfg.max_step_keys + s->cfg.tile_keys - 1) / s->cfg.tile_keys) +
+                               s->cfg.max_step_requests + 1) + 8u * 64u;
   s->slots.resize(s->cfg.max_inflight_steps);
   for (auto &sl : s->slots) {
     hipError_t e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
@@ -287,7 +335,9 @@ sbbf_status server_harvest(sbbf_server *s, bool block) {
 sbbf_status server_launch_step(sbbf_server *s, Slot &sl, uint64_t *taken) {
   *taken = 0;
   const uint32_t T = s->cfg.tile_keys;
-  std::vector<STile> ins, look;
+  std::vector<STile> ins;
+  std::vector<STile> lq[kServeXcds];  // lookup tiles per XCD queue
+  uint64_t lq_keys[kServeXcds] = {};
   uint64_t keys = 0;
   uint32_t nreq = 0;
   const size_t nready = s->ready.size();
@@ -295,18 +345,29 @@ sbbf_status server_launch_step(sbbf_server *s, Slot &sl, uint64_t *taken) {
     const uint32_t fid = s->ready.front();
     s->ready.pop_front();
     ServeFilter &f = s->filters[fid];
-    // Longest FIFO prefix of the form inserts* lookups*, within the step budget.
+    // This filter's lookup tiles go to one XCD queue (the least loaded when
+    // its first lookup is taken); a request moves the filter to the least
+    // loaded queue when its own is more than kServeSlack keys ahead, so one
+    // large filter still spreads over every XCD.
+    uint32_t q = kServeXcds;
     bool seen_lookup = false;
     while (!f.fifo.empty() && nreq < s->cfg.max_step_requests) {
       Request &r = s->reqs[f.fifo.front()];
       if (r.op == 0 && seen_lookup) break;
       if (keys > 0 && keys + r.n > s->cfg.max_step_keys) break;
       seen_lookup |= r.op == 1;
+      if (r.op) {
+        uint32_t least = 0;
+        for (uint32_t x = 1; x < kServeXcds; ++x)
+          if (lq_keys[x] < lq_keys[least]) least = x;
+        if (q == kServeXcds || lq_keys[q] > lq_keys[least] + kServeSlack) q = least;
+      }
       for (uint64_t at = 0; at < r.n; at += T) {
         const uint32_t c = (uint32_t)std::min<uint64_t>(T, r.n - at);
         STile t{r.keys + at, r.op ? r.out + at : nullptr, f.words, f.num_blocks, c};
-        (r.op ? look : ins).push_back(t);
+        (r.op ? lq[q] : ins).push_back(t);
       }
+      if (r.op) lq_keys[q] += r.n;
       keys += r.n;
       sl.reqs.push_back(f.fifo.front());
       f.fifo.pop_front();
@@ -321,6 +382,15 @@ sbbf_status server_launch_step(sbbf_server *s, Slot &sl, uint64_t *taken) {
     if (nreq >= s->cfg.max_step_requests || keys >= s->cfg.max_step_keys) break;
   }
   if (nreq == 0) return SBBF_OK;
+  // Interleave the queues: tile i comes from queue i % 8; shorter queues are
+  // padded with empty tiles (count 0: the workgroup does nothing).
+  size_t qmax = 0;
+  for (uint32_t k = 0; k < kServeXcds; ++k) qmax = std::max(qmax, lq[k].size());
+  std::vector<STile> look;
+  look.reserve(qmax * kServeXcds);
+  for (size_t i = 0; i < qmax; ++i)
+    for (uint32_t k = 0; k < kServeXcds; ++k)
+      look.push_back(i < lq[k].size() ? lq[k][i] : STile{nullptr, nullptr, nullptr, 1u, 0u});
   const size_t nt = ins.size() + look.size();
   if (nt > sl.cap) {  // one request larger than the step budget: grow this slot's buffers (the slot is idle)
     (void)hipHostFree(sl.host);

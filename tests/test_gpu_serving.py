@@ -168,3 +168,34 @@ def test_serving_workload_scale(P):
     assert st["requests_done"] == L.num_requests
     check(P, s, L, d_out, ref)
     P.sbbf_server_destroy(s)
+
+
+def test_one_large_filter_spreads(P):
+    """Steps whose lookups all hit one large filter (and a few small ones):
+    the lookup tiles of that filter move between the per-XCD queues as they
+    fill; inserts into the small filters take the LDS-merge path. Results
+    equal the oracle's in-order replay."""
+    from synth import splitmix64_stream
+    from synth.serving import ServingLog
+
+    blocks = np.array([41_016, 40, 1024, 1025], dtype=np.int64)
+    ops, filt, sizes = [], [], []
+    for f, n in ((0, 65_536), (0, 65_536), (1, 3_000), (2, 5_000), (3, 5_000)):
+        ops.append(0); filt.append(f); sizes.append(n)
+    for k in range(40):
+        ops.append(1); filt.append(0 if k % 8 else 1 + (k // 8) % 3); sizes.append(65_536 if k % 8 else 777)
+    ops, filt, sizes = (np.array(ops, dtype=np.uint32), np.array(filt, dtype=np.uint32),
+                        np.array(sizes, dtype=np.int64))
+    key_off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    payload = splitmix64_stream(4242, int(key_off[-1]))
+    ins = payload[: key_off[2]]
+    payload[key_off[5]: key_off[5] + 1000] = ins[:1000]  # some members among the lookups
+    out_off = np.concatenate([[0], np.cumsum(np.where(ops == 1, sizes, 0))]).astype(np.int64)
+    L = ServingLog(blocks=blocks, capacity=blocks * 24, arrival_ns=np.arange(ops.size, dtype=np.uint64),
+                   filter=filt, op=ops, n=sizes, key_off=key_off, out_off=out_off, payload=payload)
+    ref = oracle.replay_requests(L.blocks, L.filter, L.op, L.key_off, L.payload, L.out_off)
+    s = make_server(P, L, max_step_keys=4 << 20)
+    d_payload, d_out = staged(L)
+    P.sbbf_server_replay(s, P.serving_requests(L, d_payload, d_out), realtime=False)
+    check(P, s, L, d_out, ref)
+    P.sbbf_server_destroy(s)
