@@ -437,22 +437,42 @@ static bool partition_fits(const sbbf_device_info &info, const sbbf_filter *f) {
 // Library choice of insert strategy (SBBF_INSERT_AUTO): the partitioned insert
 // when the batch has at least two keys per block (so the one-time read and
 // write of the whole filter costs less than per-key atomics, which the device
-// caps at about 27 G keys/s whatever the filter size) and the filter splits
-// into few enough slices; otherwise global 32-bit atomics.
+// caps at about 27 G keys/s whatever the filter size), at least 4M keys (below
+// that its fixed costs lose to the atomics: measured on MI355X for filters of
+// 1 to 64 MiB) and the filter splits into few enough slices; otherwise global
+// 32-bit atomics.
 static uint32_t auto_insert_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
-  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && partition_fits(info, f))
+  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && (uint64_t)n >= (4ull << 20) && partition_fits(info, f))
     return SBBF_INSERT_PARTITIONED;
   return SBBF_INSERT_ATOMIC32;
 }
 
-// Library choice of lookup strategy (SBBF_LOOKUP_AUTO): random 32-byte reads
-// run at L2 speed while the filter fits the per-XCD L2 and fall to the
-// miss-handling rate beyond it, so the partitioned lookup (streaming traffic
-// only) is used for filters above 16 MiB with at least four keys per block.
+// Rate of the gather lookup (G keys/s) on MI355X by filter size, measured
+// with about 24 keys per block: L2-resident up to 4 MiB, then falling as
+// more of the random 32-byte reads miss (the 256 MB last-level cache, then
+// HBM).
+static double gather_rate_gkeys(uint64_t bytes) {
+  const uint64_t MiB = 1ull << 20;
+  if (bytes <= 4 * MiB) return 140.0;
+  if (bytes <= 8 * MiB) return 98.0;
+  if (bytes <= 16 * MiB) return 70.0;
+  if (bytes <= 32 * MiB) return 57.0;
+  if (bytes <= 64 * MiB) return 52.0;
+  if (bytes <= 256 * MiB) return 50.0;
+  return 43.0;
+}
+
+// Library choice of lookup strategy (SBBF_LOOKUP_AUTO) from a cost model
+// fitted to MI355X measurements (filters of 1 to 128 MiB, 1M to 200M keys):
+// the partitioned lookup takes about 50 us plus one read of the filter at
+// 5 TB/s plus 9 us per million keys; the gather takes n / rate(filter size).
+// The cheaper one is used (when the filter splits into few enough slices).
 static uint32_t auto_lookup_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
-  if (filter_bytes(f) > (16ull << 20) && (uint64_t)n >= 4u * (uint64_t)f->num_blocks && partition_fits(info, f))
-    return SBBF_LOOKUP_PARTITIONED;
-  return SBBF_LOOKUP_GATHER;
+  if (!partition_fits(info, f)) return SBBF_LOOKUP_GATHER;
+  const double bytes = (double)filter_bytes(f);
+  const double part_us = 50.0 + bytes / 5e6 + 9.0 * (double)n / 1e6;
+  const double gather_us = (double)n / (gather_rate_gkeys(filter_bytes(f)) * 1e3);
+  return part_us < gather_us ? SBBF_LOOKUP_PARTITIONED : SBBF_LOOKUP_GATHER;
 }
 
 // Stream-ordered workspace: allocated from the device's default memory pool

@@ -95,8 +95,9 @@ def test_variant_128mib_filter(P, lanes):
     ref = oracle.variant_build_filter(lanes, B, h)
     want = oracle.variant_lookup(ref, lanes, B, probes)
     f = P.Filter(B, lanes=lanes)
-    assert P.sbbf_auto_insert_strategy(f.handle, 2 * B) == 4
-    assert P.sbbf_auto_lookup_strategy(f.handle, 4 * B) == 2
+    # batches of the 100M-key workload's size pick the partitioned paths
+    assert P.sbbf_auto_insert_strategy(f.handle, 100_000_000) == 4
+    assert P.sbbf_auto_lookup_strategy(f.handle, 200_000_000) == 2
     dh, dp = dev(h), dev(probes)
     f.insert(dh, launch=INSERTS["partitioned"])
     assert np.array_equal(host_words(f), ref)
