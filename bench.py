@@ -307,6 +307,63 @@ def _variants(P, torch, w, reps=5):
     return res
 
 
+def _strategy_sweep(out_md: str) -> int:
+    """Rates of both lookup and both insert strategies over filter sizes and
+    batch sizes (about 24 keys per block inserted first, as in the 100M-key
+    workload), with the strategy the library picks for each point."""
+    _ensure_built()
+    import torch
+
+    import paper_2101_01719_amd as P
+    from synth import splitmix64_stream
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    torch.cuda.set_device(0)
+    h = splitmix64_stream(1, 64_000_000, backend="torch", device="cuda")
+    o = torch.empty(h.numel(), dtype=torch.uint8, device="cuda")
+    look_names, ins_names = {1: "gather", 2: "partitioned"}, {1: "atomic32", 4: "partitioned"}
+    rows = []
+    for mib in (1, 2, 4, 8, 16, 32, 64):
+        B = (mib << 20) // 32
+        f = P.Filter(B)
+        f.insert(h[: B * 24])
+        torch.cuda.synchronize()
+        for n in (1 << 20, 4 << 20, 16 << 20, 64_000_000):
+            x, y = h[:n], o[:n]
+            lg = n / timed(lambda: f.lookup(x, out=y, launch=dict(strategy=1))) / 1e6
+            lp = n / timed(lambda: f.lookup(x, out=y, launch=dict(strategy=2))) / 1e6
+            ia = n / timed(lambda: f.insert(x, launch=dict(strategy=1))) / 1e6
+            ip = n / timed(lambda: f.insert(x, launch=dict(strategy=4))) / 1e6
+            al, ai = P.sbbf_auto_lookup_strategy(f.handle, n), P.sbbf_auto_insert_strategy(f.handle, n)
+            rows.append((mib, n, lg, lp, look_names[al], ia, ip, ins_names[ai]))
+            print(json.dumps({"mib": mib, "n": n, "lookup_gather": lg, "lookup_partitioned": lp, "auto_lookup": al,
+                              "insert_atomic32": ia, "insert_partitioned": ip, "auto_insert": ai}), flush=True)
+        f.close()
+    with open(out_md, "w") as fh:
+        fh.write("# Strategy sweep: gather vs partitioned lookup, atomic vs partitioned insert\n\n")
+        fh.write("Command (from the repository root, on one MI355X):\n\n```\npython bench.py --strategy-sweep "
+                 + out_md + "\n```\n\n")
+        fh.write("G keys/s per strategy (HIP events around each call, mean of 5 after one warm-up), one filter of the "
+                 "given size holding about 24 keys per block, SplitMix64 hashes (seed 1); `auto` is what the library "
+                 "picks for that filter and batch (SBBF_*_AUTO). The faster strategy of each pair is in bold.\n\n")
+        fh.write("| filter | keys | lookup gather | lookup partitioned | auto | insert atomic32 | insert partitioned "
+                 "| auto |\n|---:|---:|---:|---:|---|---:|---:|---|\n")
+        for mib, n, lg, lp, al, ia, ip, ai in rows:
+            b = lambda v, w: f"**{v:.1f}**" if v >= w else f"{v:.1f}"
+            fh.write(f"| {mib} MiB | {n:,} | {b(lg, lp)} | {b(lp, lg)} | {al} | {b(ia, ip)} | {b(ip, ia)} | {ai} |\n")
+    return 0
+
+
 def _cpu_baseline(w):
     """The oracle, untuned, on the host: all inserts into the full-size filter,
     then the first half of the lookups. One thread."""
@@ -517,11 +574,16 @@ def main(argv=None):
                     help="write a markdown kernel-time summary of a rocprofv3 kernel_stats.csv, then exit")
     ap.add_argument("--summary-title", default="Kernel time summary")
     ap.add_argument("--summary-command", default="")
+    ap.add_argument("--strategy-sweep", metavar="OUT_MD",
+                    help="time the gather and partitioned lookups and the atomic and partitioned inserts over filter "
+                         "sizes of 1 to 64 MiB and batches of 1M to 64M keys, write a markdown table, then exit")
     a = ap.parse_args(argv)
 
     if a.traffic_from:
         return _traffic_from_counters(a.traffic_from[0], a.traffic_from[1], a.workload,
                                       a.calibrate_copy_mib or 1024, a.traffic_commands)
+    if a.strategy_sweep:
+        return _strategy_sweep(a.strategy_sweep)
     if a.kernel_summary:
         return _kernel_summary(a.kernel_summary[0], a.kernel_summary[1], a.summary_title, a.summary_command)
 
