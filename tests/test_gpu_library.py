@@ -106,3 +106,24 @@ def test_deserialize_rejects_bad_input(P):
     h = P.sbbf_deserialize(bytes(blob[:24]) + struct.pack("<I", 0) + bytes(blob[28:]))
     assert P.sbbf_lanes(h) == 8
     P.sbbf_destroy(h)
+
+
+@pytest.mark.parametrize("mib,n,look,ins", [
+    (1, 64_000_000, 1, 4),        # L2-resident filter: gather even for huge batches
+    (4, 16_777_216, 1, 4),
+    (16, 4_194_304, 1, 4),        # partitioned lookup loses below about 10M keys at 16 MiB
+    (16, 16_777_216, 2, 4),
+    (32, 1_048_576, 1, 1),        # partitioned insert loses below 4M keys
+    (128, 200_000_000, 2, 4),     # the 100M-key workload's filter and batches
+    (128, 100_000_000, 2, 4),
+])
+def test_auto_strategy_follows_the_measured_crossovers(P, mib, n, look, ins):
+    """The automatic choice (no device work) against the crossovers measured
+    by `bench.py --strategy-sweep`: lookup 1 = gather, 2 = partitioned;
+    insert 1 = 32-bit atomics, 4 = partitioned."""
+    B = (mib << 20) // 32
+    words = torch.empty(8 * B, dtype=torch.int32, device="cuda")
+    h = P.sbbf_create_wrapped(words, B)
+    assert P.sbbf_auto_lookup_strategy(h, n) == look
+    assert P.sbbf_auto_insert_strategy(h, n) == ins
+    P.sbbf_destroy(h)
