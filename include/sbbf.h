@@ -66,10 +66,12 @@ typedef enum sbbf_status {
 /* Insert strategies. All produce identical filter bytes. */
 typedef enum sbbf_insert_strategy {
   SBBF_INSERT_AUTO = 0,     /* library choice by filter size and key count */
-  SBBF_INSERT_ATOMIC32 = 1, /* one key per 8 lanes, one 32-bit global atomic OR per lane */
-  SBBF_INSERT_ATOMIC64 = 2, /* one key per 4 lanes, one 64-bit global atomic OR per lane */
+  SBBF_INSERT_ATOMIC32 = 1, /* one key per K lanes (K = words per block, 8 unless a
+                               variant), one 32-bit global atomic OR per lane */
+  SBBF_INSERT_ATOMIC64 = 2, /* one key per K/2 lanes, one 64-bit global atomic OR per lane */
   SBBF_INSERT_LDS = 3,      /* private copies of the whole filter in LDS, OR-merged;
-                               only when 32 * num_blocks fits one workgroup's LDS */
+                               only when the filter's 4 * K * num_blocks bytes fit one
+                               workgroup's LDS */
   SBBF_INSERT_PARTITIONED = 4 /* keys split by filter slice (a slice fits one workgroup's
                                LDS), then one workgroup ORs each slice in LDS and stores
                                it back; no global atomics on the filter. Uses a
@@ -81,7 +83,7 @@ typedef enum sbbf_insert_strategy {
  * give identical results. */
 typedef enum sbbf_lookup_strategy {
   SBBF_LOOKUP_AUTO = 0,        /* library choice by filter size and key count */
-  SBBF_LOOKUP_GATHER = 1,      /* one 32-byte block read per key, 8 lanes per key */
+  SBBF_LOOKUP_GATHER = 1,      /* one block read per key, K lanes per key */
   SBBF_LOOKUP_PARTITIONED = 2  /* keys split by filter slice, each slice tested from one
                                   workgroup's LDS, results returned to input order; uses a
                                   stream-ordered device workspace of about 13 bytes per key
@@ -223,7 +225,11 @@ sbbf_status sbbf_serialize(const sbbf_filter *f, void *host_dst, size_t capacity
 sbbf_status sbbf_deserialize(const void *host_src, size_t size, sbbf_filter **out);
 
 /* The strategy SBBF_INSERT_AUTO / SBBF_LOOKUP_AUTO picks for a batch of n
- * hashes on this filter and the current device (0 on a bad argument). */
+ * hashes on this filter and the current device (0 on a bad argument).
+ * Inserts: partitioned when n is at least two keys per block and at least
+ * 4M keys (and the filter splits into at most 4,096 slices), else 32-bit
+ * atomics. Lookups: the cheaper of the gather and the partitioned lookup by
+ * a cost model fitted to MI355X measurements (filter size and n). */
 uint32_t sbbf_auto_insert_strategy(const sbbf_filter *f, size_t n);
 uint32_t sbbf_auto_lookup_strategy(const sbbf_filter *f, size_t n);
 
