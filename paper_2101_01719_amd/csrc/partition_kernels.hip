@@ -782,12 +782,31 @@ PartitionLayout layout(void *workspace, uint64_t n, uint32_t num_slices, uint32_
 // Chunking of n keys over about max_groups partitioning workgroups: chunk is
 // a multiple of the scatter tile, at most kLookupChunk keys for lookups (so
 // there may be more groups than max_groups), and every group gets a
-// non-empty chunk.
+// non-empty chunk. When lookups need more chunks than max_groups (the
+// workgroups the count and unpermute kernels keep resident, two per compute
+// unit), the tiles per chunk (5 to the most that fit) minimise rounds x
+// (chunk length + a tile of fixed work per chunk): e.g. 2e8 keys take 8-tile
+// chunks (3,488, seven full rounds of 512) rather than 9-tile ones (3,101, a
+// seventh round almost empty).
 void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uint32_t *groups) {
   const uint64_t tiles = (n + kTile - 1) / kTile;
   const uint64_t g0 = tiles < max_groups ? (tiles ? tiles : 1) : max_groups;
   uint64_t tiles_per = (tiles + g0 - 1) / g0;
-  if (lookup && tiles_per * kTile > kLookupChunk) tiles_per = kLookupChunk / kTile;
+  if (lookup && tiles_per * kTile > kLookupChunk) {
+    const uint64_t slots = max_groups ? max_groups : 1u;
+    uint64_t best = kLookupChunk / kTile, best_cost = UINT64_MAX;
+    for (uint64_t tp = kLookupChunk / kTile; tp >= 5u; --tp) {
+      const uint64_t g = (tiles + tp - 1u) / tp;
+      // rounds x (chunk length + one tile for each chunk's fixed work: its
+      // count row, the unpermute's scan over the slices)
+      const uint64_t cost = (g + slots - 1u) / slots * (tp + 1u);
+      if (cost < best_cost) {
+        best_cost = cost;
+        best = tp;
+      }
+    }
+    tiles_per = best;
+  }
   *chunk = (uint32_t)(tiles_per * kTile);
   *groups = (uint32_t)((n + *chunk - 1) / *chunk);
   if (*groups == 0) *groups = 1;
