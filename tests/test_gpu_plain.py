@@ -316,3 +316,21 @@ def test_plain_100m_full(P, strategy):
     ref_look = oracle.lookup(ref, w.num_blocks, look)
     for name, g in got.items():
         assert np.array_equal(g, ref_look), name
+
+
+@pytest.mark.parametrize("B", [4096 * 2048 + 5, 4096 * 4096])
+def test_partitioned_many_slices(P, B):
+    """Filters above 128 MiB: 2,049 slices of 4,096 blocks (two slices per
+    scatter thread, a five-block last slice) and the limit of 4,096 slices
+    (512 MiB, four per thread). Whole filter and every lookup against the
+    oracle, for the partitioned insert and lookup."""
+    h = splitmix64_stream(560 + B % 7, 6_000_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    probes = np.concatenate([h[::5], splitmix64_stream(561, 5_000_001)])
+    want = oracle.lookup(ref, B, probes)
+    got = f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy()
+    assert np.array_equal(got, want)
+    f.close()
