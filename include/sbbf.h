@@ -76,7 +76,11 @@ typedef enum sbbf_insert_strategy {
                                LDS), then one workgroup ORs each slice in LDS and stores
                                it back; no global atomics on the filter. Uses a
                                stream-ordered device workspace of about 8 bytes per key
-                               (batches above 2^31 keys are processed 2^31 at a time) */
+                               (batches above 2^31 keys are processed 2^31 at a time).
+                               Filters of more than 4,096 slices (above 512 MiB) are
+                               partitioned in two levels (by group of 1,024 slices, then
+                               by slice), about twice the workspace, and the call waits
+                               for the stream once to size the second level */
 } sbbf_insert_strategy;
 
 /* Lookup strategies (the `strategy` field of sbbf_launch for lookups). All
@@ -87,7 +91,8 @@ typedef enum sbbf_lookup_strategy {
   SBBF_LOOKUP_PARTITIONED = 2  /* keys split by filter slice, each slice tested from one
                                   workgroup's LDS, results returned to input order; uses a
                                   stream-ordered device workspace of about 13 bytes per key
-                                  (batches above 2^31 keys are processed 2^31 at a time) */
+                                  (batches above 2^31 keys are processed 2^31 at a time);
+                                  above 4,096 slices two levels, as for inserts */
 } sbbf_lookup_strategy;
 
 /* Memory-access flags of sbbf_launch (cache policy only; results are

@@ -470,7 +470,15 @@ static double gather_rate_gkeys(uint64_t bytes) {
 static uint32_t auto_lookup_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
   if (!partition_fits(info, f)) return SBBF_LOOKUP_GATHER;
   const double bytes = (double)filter_bytes(f);
-  const double part_us = 50.0 + bytes / 5e6 + 9.0 * (double)n / 1e6;
+  double part_us = 50.0 + bytes / 5e6 + 9.0 * (double)n / 1e6;
+  // Filters of more slices than one level takes: a level-1 count and scatter
+  // (about 6.2 us per million keys), one wait for the stream and the fixed
+  // cost of a one-level call per group of slices.
+  const uint32_t slices = partition_slices(f->num_blocks, partition_slice_shift(info, f->num_blocks, f->lanes));
+  if (slices > partition_level_slices()) {
+    const double groups = (double)((slices + partition_group_slices() - 1u) / partition_group_slices());
+    part_us += 40.0 + 50.0 * groups + 6.2 * (double)n / 1e6;
+  }
   const double gather_us = (double)n / (gather_rate_gkeys(filter_bytes(f)) * 1e3);
   return part_us < gather_us ? SBBF_LOOKUP_PARTITIONED : SBBF_LOOKUP_GATHER;
 }

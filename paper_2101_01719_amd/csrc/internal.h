@@ -63,6 +63,11 @@ hipError_t launch_union(uint32_t *dst, const uint32_t *src, uint64_t num_words, 
 // `max_groups` chunks (one partitioning workgroup each); `workspace` holds
 // partition_workspace_bytes(n, slices, max_groups, lookup) bytes.
 uint32_t partition_max_slices();
+// Slices one level of the partition handles; filters with more take two
+// levels (keys grouped by runs of this many slices first; the host waits for
+// the stream once per call to size the second level).
+uint32_t partition_level_slices();
+uint32_t partition_group_slices();  // slices per level-2 group
 uint64_t partition_max_keys();
 uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup);
 // keys: the input holds keys, hashed on load (key_hash).

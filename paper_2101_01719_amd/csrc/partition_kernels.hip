@@ -32,6 +32,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 #include "sbbf_device.h"
 
@@ -55,6 +58,15 @@ __device__ __forceinline__ uint32_t slice_of(uint64_t h, uint32_t num_blocks, ui
   return block_of((uint32_t)(h >> 32), num_blocks) >> slice_shift;
 }
 
+// Slice of a hash relative to the first slice of the partition (slice_base:
+// 0 for one level; a group's first slice in the second level of a two-level
+// partition, whose keys all lie in that group), clamped into [0, num_slices)
+// so that no key can index past the per-slice arrays.
+__device__ __forceinline__ uint32_t local_slice(uint64_t h, uint32_t num_blocks, uint32_t slice_shift,
+                                                uint32_t slice_base, uint32_t num_slices) {
+  return min(slice_of(h, num_blocks, slice_shift) - slice_base, num_slices - 1u);
+}
+
 __device__ __forceinline__ void chunk_range(uint32_t g, uint32_t chunk, uint32_t n, uint32_t *b, uint32_t *e) {
   const uint64_t lo = (uint64_t)g * chunk;
   *b = (uint32_t)min<uint64_t>(lo, n);
@@ -63,14 +75,16 @@ __device__ __forceinline__ void chunk_range(uint32_t g, uint32_t chunk, uint32_t
 
 __global__ void __launch_bounds__(kPartThreads)
 part_count_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t num_blocks,
-                  uint32_t slice_shift, uint32_t num_slices, uint32_t keys, uint32_t *__restrict__ hist_out) {
+                  uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, uint32_t keys,
+                  uint32_t *__restrict__ hist_out) {
   extern __shared__ uint32_t hist[];
   for (uint32_t i = threadIdx.x; i < num_slices; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   uint32_t b, e;
   chunk_range(blockIdx.x, chunk, n, &b, &e);
   for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    const uint32_t s = slice_of(as_hash(load_hash<0>(hashes + i), keys), num_blocks, slice_shift);
+    const uint32_t s =
+        local_slice(as_hash(load_hash<0>(hashes + i), keys), num_blocks, slice_shift, slice_base, num_slices);
     __hip_atomic_fetch_add(hist + s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __syncthreads();
@@ -218,7 +232,8 @@ struct SliceCursor {
 template <bool kWithPos, int R, uint32_t L, bool kFull>
 __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
                                              const uint32_t *__restrict__ new_chunk_hist, uint32_t num_blocks,
-                                             uint32_t slice_shift, uint32_t num_slices, uint32_t keys,
+                                             uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
+                                             uint32_t keys,
                                              const ScatterLds &S, SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
                                              uint16_t *__restrict__ out_pos) {
   // Keys are hashed here, where the prefetched tile is first used.
@@ -248,7 +263,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
-    s[t] = slice_of(h[t], num_blocks, slice_shift);
+    s[t] = local_slice(h[t], num_blocks, slice_shift, slice_base, num_slices);
     rank[t] = __hip_atomic_fetch_add(S.hist + s[t], (kFull || i < e) ? 1u : 0u, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
   }
@@ -311,7 +326,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     const uint32_t k = t * kScatterThreads + threadIdx.x;
     if ((L == 1u && kFull) || k < total) {
       const uint64_t key = S.stage[k];
-      const uint2 in = S.info[slice_of(key, num_blocks, slice_shift)];
+      const uint2 in = S.info[local_slice(key, num_blocks, slice_shift, slice_base, num_slices)];
       if (L == 1u || k < in.y) out_keys[k + in.x] = key;
     }
   }
@@ -326,7 +341,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
 template <bool kWithPos, int R, uint32_t L>
 __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t chunks_per_group,
-                    uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices,
+                    uint32_t num_blocks, uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
                     const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
                     const uint32_t *__restrict__ hist_rows, uint32_t keys, uint64_t *__restrict__ out_keys,
                     uint16_t *__restrict__ out_pos) {
@@ -380,7 +395,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   scatter_tile<kWithPos, R, L, FULL>(H, t0, e, t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * \
                                                                                    num_slices                  \
                                                                              : nullptr,                        \
-                                     num_blocks, slice_shift, num_slices, keys, S, C, out_keys, out_pos)
+                                     num_blocks, slice_shift, slice_base, num_slices, keys, S, C, out_keys, out_pos)
   for (; k + 2u <= nfull; k += 2u) {
     load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
     SBBF_SCATTER_TILE(true, ha);
@@ -561,13 +576,13 @@ template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
                          const uint32_t *__restrict__ tot, uint32_t *__restrict__ words, uint32_t num_blocks,
-                         uint32_t slice_shift) {
+                         uint32_t slice_shift, uint32_t slice_base) {
   extern __shared__ uint4 lds4[];
   unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
   const uint32_t slice = blockIdx.x;
   const uint32_t ns = tot[slice];
   if (ns == 0) return;  // whole workgroup: the slice is unchanged
-  const uint32_t b0 = slice << slice_shift;
+  const uint32_t b0 = (slice_base + slice) << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
   load_slice_to_lds<K>(lds4, words, b0, nb);
   __syncthreads();
@@ -588,12 +603,12 @@ template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
                          const uint32_t *__restrict__ tot, const uint32_t *__restrict__ words, uint32_t num_blocks,
-                         uint32_t slice_shift, uint8_t *__restrict__ res) {
+                         uint32_t slice_shift, uint32_t slice_base, uint8_t *__restrict__ res) {
   extern __shared__ uint4 lds4[];
   const uint32_t slice = blockIdx.x;
   const uint32_t ns = tot[slice];
   if (ns == 0) return;  // whole workgroup
-  const uint32_t b0 = slice << slice_shift;
+  const uint32_t b0 = (slice_base + slice) << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
   load_slice_to_lds<K>(lds4, words, b0, nb);
   __syncthreads();
@@ -814,8 +829,8 @@ void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uin
 
 template <bool kWithPos, int R, uint32_t L>
 hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
-                          uint32_t slice_shift, uint32_t num_slices, uint32_t keys, const PartitionLayout &L_,
-                          hipStream_t stream) {
+                          uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, uint32_t keys,
+                          const PartitionLayout &L_, hipStream_t stream) {
   const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L);
   // Several chunks per workgroup (lookups cut the batch finer than inserts):
   // about two workgroups per compute unit.
@@ -825,8 +840,8 @@ hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, ui
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
   hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L>), dim3(grid), dim3(kScatterThreads), lds, stream, hashes,
-                     n, chunk, per, num_blocks, slice_shift, num_slices, L_.offsets, L_.start, L_.hist, keys,
-                     L_.keys, kWithPos ? L_.pos : nullptr);
+                     n, chunk, per, num_blocks, slice_shift, slice_base, num_slices, L_.offsets, L_.start, L_.hist,
+                     keys, L_.keys, kWithPos ? L_.pos : nullptr);
   return hipGetLastError();
 }
 
@@ -835,20 +850,24 @@ hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, ui
 // kScatterGroup keys (the incomplete tail carried to the next tile).
 template <bool kWithPos>
 hipError_t launch_scatter_r(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups,
-                            uint32_t num_blocks, uint32_t slice_shift, uint32_t num_slices, uint32_t keys,
-                            const PartitionLayout &L, hipStream_t stream) {
+                            uint32_t num_blocks, uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
+                            uint32_t keys, const PartitionLayout &L, hipStream_t stream) {
   if (num_slices <= kScatterThreads)
-    return launch_scatter<kWithPos, 1, kScatterGroup>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys,
-                                                      L, stream);
+    return launch_scatter<kWithPos, 1, kScatterGroup>(hashes, n, chunk, groups, num_blocks, slice_shift, slice_base,
+                                                      num_slices, keys, L, stream);
   if (num_slices <= 2u * kScatterThreads)
-    return launch_scatter<kWithPos, 2, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
+    return launch_scatter<kWithPos, 2, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, slice_base, num_slices,
+                                          keys, L, stream);
   static_assert(4u * kScatterThreads >= kMaxSlices, "four slices per thread cover every filter");
-  return launch_scatter<kWithPos, 4, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
+  return launch_scatter<kWithPos, 4, 1>(hashes, n, chunk, groups, num_blocks, slice_shift, slice_base, num_slices,
+                                        keys, L, stream);
 }
 
+// Count, scan and scatter of n keys that all lie in the num_slices slices
+// from slice_base (of 2^slice_shift blocks each).
 hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, uint32_t slice_shift,
-                     uint32_t num_slices, uint32_t chunk, uint32_t groups, const PartitionLayout &L, bool with_pos,
-                     uint32_t keys, hipStream_t stream) {
+                     uint32_t slice_base, uint32_t num_slices, uint32_t chunk, uint32_t groups,
+                     const PartitionLayout &L, bool with_pos, uint32_t keys, hipStream_t stream) {
   hipError_t e;
   const dim3 blk(kPartThreads);
   // Dynamic LDS above the default needs the per-kernel limit raised; an error
@@ -857,7 +876,7 @@ hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, ui
                             (int)(num_slices * 4u));
   (void)hipGetLastError();
   hipLaunchKernelGGL(part_count_kernel, dim3(groups), blk, num_slices * 4u, stream, hashes, n, chunk, num_blocks,
-                     slice_shift, num_slices, keys, L.hist);
+                     slice_shift, slice_base, num_slices, keys, L.hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const dim3 scan_grid((num_slices + kScanCols - 1) / kScanCols, row_blocks(groups));
   if (scan_grid.y > 1) {  // one row block needs no carries
@@ -870,49 +889,152 @@ hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, ui
   hipLaunchKernelGGL(part_offsets_kernel, dim3(1), blk, 0, stream, L.tot, num_slices, L.offsets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (with_pos)
-    return launch_scatter_r<true>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
-  return launch_scatter_r<false>(hashes, n, chunk, groups, num_blocks, slice_shift, num_slices, keys, L, stream);
+    return launch_scatter_r<true>(hashes, n, chunk, groups, num_blocks, slice_shift, slice_base, num_slices, keys, L,
+                                  stream);
+  return launch_scatter_r<false>(hashes, n, chunk, groups, num_blocks, slice_shift, slice_base, num_slices, keys, L,
+                                 stream);
 }
 
 uint32_t slices_of(uint32_t num_blocks, uint32_t slice_shift) {
   return (uint32_t)(((uint64_t)num_blocks + (1u << slice_shift) - 1u) >> slice_shift);
 }
 
-}  // namespace
-
-uint32_t partition_max_slices() { return kMaxSlices; }
-uint64_t partition_max_keys() { return 1ull << 31; }
-
-uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup) {
-  uint32_t chunk, groups;
-  chunking(n, max_groups, lookup, &chunk, &groups);
-  return layout(nullptr, n, num_slices, groups, lookup).bytes;
-}
-
 // Slice insert for K-word blocks: the slice (2^slice_shift blocks of 4K
 // bytes) in dynamic LDS.
 template <uint32_t K>
 hipError_t launch_slice_insert(const PartitionLayout &L, uint32_t num_slices, uint32_t *words, uint32_t num_blocks,
-                               uint32_t slice_shift, hipStream_t stream) {
+                               uint32_t slice_shift, uint32_t slice_base, hipStream_t stream) {
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K;
   (void)hipFuncSetAttribute((const void *)part_slice_insert_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes);
   (void)hipGetLastError();
   hipLaunchKernelGGL(part_slice_insert_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
-                     L.offsets, L.tot, words, num_blocks, slice_shift);
+                     L.offsets, L.tot, words, num_blocks, slice_shift, slice_base);
   return hipGetLastError();
 }
 
 template <uint32_t K>
 hipError_t launch_slice_lookup(const PartitionLayout &L, uint32_t num_slices, const uint32_t *words,
-                               uint32_t num_blocks, uint32_t slice_shift, hipStream_t stream) {
+                               uint32_t num_blocks, uint32_t slice_shift, uint32_t slice_base, hipStream_t stream) {
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K;
   (void)hipFuncSetAttribute((const void *)part_slice_lookup_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes);
   (void)hipGetLastError();
   hipLaunchKernelGGL(part_slice_lookup_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, L.keys,
-                     L.offsets, L.tot, words, num_blocks, slice_shift, L.res);
+                     L.offsets, L.tot, words, num_blocks, slice_shift, slice_base, L.res);
   return hipGetLastError();
+}
+
+// Results of a partition (in partitioned order, L.res) back to input order.
+hipError_t unpermute(const PartitionLayout &L, uint32_t num_slices, uint32_t n, uint32_t chunk, uint32_t groups,
+                     uint8_t *out8, uint32_t *out_bits, hipStream_t stream) {
+  const size_t u_lds = (size_t)num_slices * 8u + 64u + chunk;
+  (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)u_lds);
+  (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)u_lds);
+  (void)hipGetLastError();
+  if (out_bits)
+    hipLaunchKernelGGL(part_unpermute_kernel<true>, dim3(groups), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
+                       L.offsets, L.start, L.hist, num_slices, n, chunk, nullptr, out_bits);
+  else
+    hipLaunchKernelGGL(part_unpermute_kernel<false>, dim3(groups), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
+                       L.offsets, L.start, L.hist, num_slices, n, chunk, out8, nullptr);
+  return hipGetLastError();
+}
+
+// One level: the n keys all lie in the num_slices slices from slice_base.
+hipError_t insert_level(const uint64_t *hashes, uint32_t n, uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
+                        uint32_t slice_base, uint32_t num_slices, void *workspace, uint32_t max_groups, uint32_t keys,
+                        hipStream_t stream, uint32_t lanes) {
+  uint32_t chunk, groups;
+  chunking(n, max_groups, false, &chunk, &groups);
+  PartitionLayout L = layout(workspace, n, num_slices, groups, false);
+  L.scatter_groups = groups;
+  hipError_t e =
+      partition(hashes, n, num_blocks, slice_shift, slice_base, num_slices, chunk, groups, L, false, keys, stream);
+  if (e != hipSuccess) return e;
+  if (lanes == 4) return launch_slice_insert<4>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
+  if (lanes == 16) return launch_slice_insert<16>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
+  return launch_slice_insert<8>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
+}
+
+hipError_t lookup_level(const uint64_t *hashes, uint32_t n, const uint32_t *words, uint32_t num_blocks,
+                        uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, void *workspace,
+                        uint32_t max_groups, uint8_t *out8, uint32_t *out_bits, uint32_t keys, hipStream_t stream,
+                        uint32_t lanes) {
+  uint32_t chunk, groups;
+  chunking(n, max_groups, true, &chunk, &groups);
+  PartitionLayout L = layout(workspace, n, num_slices, groups, true);
+  L.scatter_groups = max_groups ? max_groups : 1u;
+  hipError_t e =
+      partition(hashes, n, num_blocks, slice_shift, slice_base, num_slices, chunk, groups, L, true, keys, stream);
+  if (e != hipSuccess) return e;
+  if (lanes == 4)
+    e = launch_slice_lookup<4>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
+  else if (lanes == 16)
+    e = launch_slice_lookup<16>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
+  else
+    e = launch_slice_lookup<8>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
+  if (e != hipSuccess) return e;
+  return unpermute(L, num_slices, n, chunk, groups, out8, out_bits, stream);
+}
+
+// Two levels, for filters of more than kOneLevelSlices slices: level 1
+// partitions the keys by group of kGroupSlices consecutive slices (one slice
+// per scatter thread, so level 2 writes whole 64-byte groups; at most 2,048
+// groups: a filter has at most 2^21 slices), then each group's keys,
+// contiguous in the level-1 output, take the one-level path with that
+// group's first slice as slice_base. Launching level 2 needs each group's key
+// count, so the host waits for level 1 once.
+constexpr uint32_t kGroupShift = 10;
+constexpr uint32_t kGroupSlices = 1u << kGroupShift;
+constexpr uint32_t kOneLevelSlices = kMaxSlices;
+static_assert(kGroupSlices == kScatterThreads, "a level-2 group has one slice per scatter thread");
+static_assert((2u << 20) / kGroupSlices <= kMaxSlices, "level 1 takes every filter's groups");
+
+struct TwoLevel {
+  uint32_t groups;           // level-1 "slices": groups of kMaxSlices slices
+  uint32_t chunk, chunks;    // level-1 chunking
+  PartitionLayout L1;
+  void *level2;              // workspace of the level-2 calls
+};
+
+TwoLevel two_level_plan(void *workspace, uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup) {
+  TwoLevel t;
+  t.groups = (num_slices + kGroupSlices - 1u) >> kGroupShift;
+  chunking(n, max_groups, lookup, &t.chunk, &t.chunks);
+  t.L1 = layout(workspace, n, t.groups, t.chunks, lookup);
+  t.L1.scatter_groups = lookup ? (max_groups ? max_groups : 1u) : t.chunks;
+  t.level2 = static_cast<char *>(workspace) + t.L1.bytes;
+  return t;
+}
+
+// Level-1 slice offsets and totals, read back to the host (waits for the stream).
+hipError_t group_counts(const TwoLevel &t, std::vector<uint32_t> *offsets, std::vector<uint32_t> *tot,
+                        hipStream_t stream) {
+  offsets->resize(t.groups + 1u);
+  tot->resize(t.groups);
+  hipError_t e = hipMemcpyAsync(offsets->data(), t.L1.offsets, (t.groups + 1u) * 4u, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(tot->data(), t.L1.tot, t.groups * 4u, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  return e;
+}
+
+}  // namespace
+
+uint32_t partition_max_slices() { return 2u << 20; }
+uint32_t partition_level_slices() { return kOneLevelSlices; }
+uint32_t partition_group_slices() { return kGroupSlices; }
+uint64_t partition_max_keys() { return 1ull << 31; }
+
+uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup) {
+  uint32_t chunk, groups;
+  chunking(n, max_groups, lookup, &chunk, &groups);
+  if (num_slices <= kOneLevelSlices) return layout(nullptr, n, num_slices, groups, lookup).bytes;
+  // level 1, then level 2 for at most all n keys in one group
+  const uint32_t g = (num_slices + kGroupSlices - 1u) >> kGroupShift;
+  return layout(nullptr, n, g, groups, lookup).bytes + partition_workspace_bytes(n, kGroupSlices, max_groups, lookup);
 }
 
 hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_t *words, uint32_t num_blocks,
@@ -922,16 +1044,22 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   if (lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
-  uint32_t chunk, groups;
-  chunking(n, max_groups, false, &chunk, &groups);
-  PartitionLayout L = layout(workspace, n, num_slices, groups, false);
-  L.scatter_groups = groups;
-  hipError_t e =
-      partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, false, keys, stream);
-  if (e != hipSuccess) return e;
-  if (lanes == 4) return launch_slice_insert<4>(L, num_slices, words, num_blocks, slice_shift, stream);
-  if (lanes == 16) return launch_slice_insert<16>(L, num_slices, words, num_blocks, slice_shift, stream);
-  return launch_slice_insert<8>(L, num_slices, words, num_blocks, slice_shift, stream);
+  if (num_slices <= kOneLevelSlices)
+    return insert_level(hashes, (uint32_t)n, words, num_blocks, slice_shift, 0u, num_slices, workspace, max_groups,
+                        keys, stream, lanes);
+  TwoLevel t = two_level_plan(workspace, n, num_slices, max_groups, false);
+  hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift + kGroupShift, 0u, t.groups, t.chunk,
+                           t.chunks, t.L1, false, keys, stream);
+  std::vector<uint32_t> off, tot;
+  if (e == hipSuccess) e = group_counts(t, &off, &tot, stream);
+  for (uint32_t g = 0; g < t.groups && e == hipSuccess; ++g) {
+    if (tot[g] == 0) continue;
+    const uint32_t base = g << kGroupShift;
+    // level-1 output holds hashes (keys were hashed there)
+    e = insert_level(t.L1.keys + off[g], tot[g], words, num_blocks, slice_shift, base,
+                     std::min(kGroupSlices, num_slices - base), t.level2, max_groups, 0u, stream, lanes);
+  }
+  return e;
 }
 
 hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const uint32_t *words, uint32_t num_blocks,
@@ -941,33 +1069,25 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
   if (lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
-  uint32_t chunk, groups;
-  chunking(n, max_groups, true, &chunk, &groups);
-  PartitionLayout L = layout(workspace, n, num_slices, groups, true);
-  L.scatter_groups = max_groups ? max_groups : 1u;
-  hipError_t e =
-      partition(hashes, (uint32_t)n, num_blocks, slice_shift, num_slices, chunk, groups, L, true, keys, stream);
+  if (num_slices <= kOneLevelSlices)
+    return lookup_level(hashes, (uint32_t)n, words, num_blocks, slice_shift, 0u, num_slices, workspace, max_groups,
+                        out8, out_bits, keys, stream, lanes);
+  TwoLevel t = two_level_plan(workspace, n, num_slices, max_groups, true);
+  hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift + kGroupShift, 0u, t.groups, t.chunk,
+                           t.chunks, t.L1, true, keys, stream);
+  std::vector<uint32_t> off, tot;
+  if (e == hipSuccess) e = group_counts(t, &off, &tot, stream);
+  // Each group's results go, one byte per key, to its run of the level-1
+  // results (level-1 partitioned order), which level 1 then unpermutes.
+  for (uint32_t g = 0; g < t.groups && e == hipSuccess; ++g) {
+    if (tot[g] == 0) continue;
+    const uint32_t base = g << kGroupShift;
+    e = lookup_level(t.L1.keys + off[g], tot[g], words, num_blocks, slice_shift, base,
+                     std::min(kGroupSlices, num_slices - base), t.level2, max_groups, t.L1.res + off[g], nullptr, 0u,
+                     stream, lanes);
+  }
   if (e != hipSuccess) return e;
-  if (lanes == 4)
-    e = launch_slice_lookup<4>(L, num_slices, words, num_blocks, slice_shift, stream);
-  else if (lanes == 16)
-    e = launch_slice_lookup<16>(L, num_slices, words, num_blocks, slice_shift, stream);
-  else
-    e = launch_slice_lookup<8>(L, num_slices, words, num_blocks, slice_shift, stream);
-  if (e != hipSuccess) return e;
-  const size_t u_lds = (size_t)num_slices * 8u + 64u + chunk;
-  (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)u_lds);
-  (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)u_lds);
-  (void)hipGetLastError();
-  if (out_bits)
-    hipLaunchKernelGGL(part_unpermute_kernel<true>, dim3(groups), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
-                       L.offsets, L.start, L.hist, num_slices, (uint32_t)n, chunk, nullptr, out_bits);
-  else
-    hipLaunchKernelGGL(part_unpermute_kernel<false>, dim3(groups), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
-                       L.offsets, L.start, L.hist, num_slices, (uint32_t)n, chunk, out8, nullptr);
-  return hipGetLastError();
+  return unpermute(t.L1, t.groups, (uint32_t)n, t.chunk, t.chunks, out8, out_bits, stream);
 }
 
 }  // namespace sbbf

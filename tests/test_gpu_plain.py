@@ -247,17 +247,53 @@ def test_partitioned_slice_edges(P, B):
     assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
 
 
-def test_partitioned_refuses_too_many_slices(P):
-    f = P.Filter(4096 * 4096 + 1)  # one slice over the limit of 4096 slices of 4096 blocks
-    h = dev(splitmix64_stream(1, 1000))
-    with pytest.raises(P.SbbfError) as e:
-        f.insert(h, launch=dict(strategy=4))
-    assert e.value.status == P.SBBF_EUNSUPPORTED
-    with pytest.raises(P.SbbfError) as e:
-        f.lookup(h, launch=dict(strategy=2))
-    assert e.value.status == P.SBBF_EUNSUPPORTED
-    f.insert(h)  # the library's choices still work
-    assert bool(f.lookup(h).all())
+def test_partitioned_two_levels_minimal(P):
+    """One block over 4,096 slices of 4,096 blocks: the two-level partition
+    with a second group of one slice holding one block."""
+    B = 4096 * 4096 + 1
+    h = splitmix64_stream(570, 3_000_000)
+    h[:5] = np.array([(1 << 64) - 1, 0xFFFFFFFF00000000, 0xFFFFFFFF12345678, 0, 1 << 63], dtype=np.uint64)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    probes = np.concatenate([h[::3], splitmix64_stream(571, 2_000_003)])
+    want = oracle.lookup(ref, B, probes)
+    assert np.array_equal(f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy(), want)
+    bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
+    f.close()
+
+
+def test_partitioned_two_levels_large(P):
+    """A 1.5 GiB filter (12,289 slices: four groups, a short last one): the
+    two-level insert and lookup, from hashes and from keys, against the
+    oracle; the library picks the partitioned paths for batches this size."""
+    B = 3 * (1 << 24) + 12_345
+    free, _ = torch.cuda.mem_get_info()
+    if free < 8 * 32 * B:
+        pytest.skip("not enough device memory")
+    h = splitmix64_stream(572, 20_000_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h[:1_000_000]), launch=dict(strategy=1))  # start from a non-empty filter
+    f.insert(dev(h[1_000_000:]), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    probes = np.concatenate([h[::9], splitmix64_stream(573, 18_000_000)])
+    probes = probes[np.random.default_rng(5).permutation(probes.size)]
+    want = oracle.lookup(ref, B, probes)
+    assert np.array_equal(f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy(), want)
+    assert np.array_equal(f.lookup(dev(probes), launch=LOOKUPS["gather"]).cpu().numpy(), want)
+    keys = np.arange(5_000_000, dtype=np.uint64) * np.uint64(3)
+    g = P.Filter(B)
+    g.insert_keys(dev(keys), launch=dict(strategy=4))
+    kref = oracle.build_filter(B, oracle.key_hash(keys))
+    assert np.array_equal(words_of(g), kref)
+    kp = np.arange(0, 6_000_000, dtype=np.uint64)
+    got = g.lookup_keys(dev(kp), launch=LOOKUPS["partitioned"]).cpu().numpy()
+    assert np.array_equal(got, oracle.lookup(kref, B, oracle.key_hash(kp)))
+    f.close()
+    g.close()
 
 
 def test_all_ones_filter_reports_every_probe(P):
