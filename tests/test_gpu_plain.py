@@ -370,3 +370,21 @@ def test_partitioned_many_slices(P, B):
     got = f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy()
     assert np.array_equal(got, want)
     f.close()
+
+
+def test_partitioned_two_slices_per_thread(P):
+    """1,537 slices (a 192 MiB filter with a seven-block last slice): two
+    slices per scatter thread with carried four-key groups."""
+    B = 4096 * 1536 + 7
+    h = splitmix64_stream(575, 9_000_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h[:2_000_000]), launch=dict(strategy=4))
+    f.insert(dev(h[2_000_000:]), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    probes = np.concatenate([h[::4], splitmix64_stream(576, 7_000_001)])
+    want = oracle.lookup(ref, B, probes)
+    assert np.array_equal(f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy(), want)
+    bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
+    f.close()
