@@ -739,15 +739,31 @@ part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint8_t *__restric
       }
     }
   } else {
-    // Phase 2 (bits): one position per lane. i0 is wave-uniform (chunks start
-    // at multiples of 64), so every lane of a wave runs the same iterations
-    // and the ballot sees the whole wave.
-    for (uint32_t i0 = b + (threadIdx.x & ~63u); i0 < e; i0 += blockDim.x) {
-      const uint32_t i = i0 + lane;
-      const uint8_t r = i < e ? vals[pos[i]] : (uint8_t)0;
-      const uint64_t m = ballot(r != 0);
-      if (lane == 0) out_bits[i0 / 32u] = (uint32_t)m;
-      if (lane == 1 && n - i0 > 32u) out_bits[i0 / 32u + 1u] = (uint32_t)(m >> 32);
+    // Phase 2 (bits): a wave takes 256 positions per step, four consecutive
+    // ones per lane (one 8-byte load of positions), as a nibble; lanes 8w ..
+    // 8w+7 OR their nibbles into the word of positions i0 + 32w .. +31, which
+    // lane 8w stores. i0 is a multiple of 256 (chunks start at multiples of
+    // the 7,168-key tile), so words are whole; positions at or past e give 0
+    // bits, and a word is stored only when it starts before e.
+    constexpr uint32_t kWaveSpan = 256u;
+    const uint32_t wave = threadIdx.x >> 6;
+    for (uint32_t i0 = b + wave * kWaveSpan; i0 < e; i0 += (kPartThreads / 64u) * kWaveSpan) {
+      const uint32_t i = i0 + 4u * lane;
+      uint32_t nib = 0;
+      if (i + 4u <= e) {
+        const uint2 p2 = *reinterpret_cast<const uint2 *>(pos + i);
+        nib = (uint32_t)(vals[p2.x & 0xffffu] != 0) | ((uint32_t)(vals[p2.x >> 16] != 0) << 1) |
+              ((uint32_t)(vals[p2.y & 0xffffu] != 0) << 2) | ((uint32_t)(vals[p2.y >> 16] != 0) << 3);
+      } else {
+        for (uint32_t k = 0; k < 4u; ++k)
+          if (i + k < e) nib |= (uint32_t)(vals[pos[i + k]] != 0) << k;
+      }
+      uint32_t w = nib << (4u * (lane & 7u));
+      w |= (uint32_t)__shfl_xor((int)w, 1);
+      w |= (uint32_t)__shfl_xor((int)w, 2);
+      w |= (uint32_t)__shfl_xor((int)w, 4);
+      const uint32_t start = i0 + 32u * (lane >> 3);
+      if ((lane & 7u) == 0 && start < e) out_bits[start / 32u] = w;
     }
   }
 }
