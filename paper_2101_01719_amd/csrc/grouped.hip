@@ -131,27 +131,14 @@ struct GPlanDev {
 // ---- insert -----------------------------------------------------------------
 
 // OR the mask of one key into the slice [b0, b0 + nb) of a filter of B blocks
-// held in LDS (four 64-bit words per block): four 64-bit LDS ORs. A key
-// outside the slice, or an invalid lane, ORs a zero mask into block 0.
+// held in LDS (four 64-bit words per block; pairs in a per-block rotated
+// order). A key outside the slice, or an invalid lane, ORs a zero mask into
+// block 0.
 __device__ __forceinline__ void or_key(unsigned long long *lds2, uint64_t h, bool valid, uint32_t B, uint32_t b0,
                                        uint32_t nb) {
   const uint32_t rel = block_of((uint32_t)(h >> 32), B) - b0;
   const bool in = valid && rel < nb;
-  const uint32_t one = in ? 1u : 0u;
-  const uint32_t x = (uint32_t)h;
-  unsigned long long *blk = lds2 + (uint64_t)(in ? rel : 0u) * 4u;
-  __hip_atomic_fetch_or(blk + 0, (unsigned long long)(one << bit_of(kSeed0, x)) |
-                                     ((unsigned long long)(one << bit_of(kSeed1, x)) << 32),
-                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_or(blk + 1, (unsigned long long)(one << bit_of(kSeed2, x)) |
-                                     ((unsigned long long)(one << bit_of(kSeed3, x)) << 32),
-                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_or(blk + 2, (unsigned long long)(one << bit_of(kSeed4, x)) |
-                                     ((unsigned long long)(one << bit_of(kSeed5, x)) << 32),
-                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_fetch_or(blk + 3, (unsigned long long)(one << bit_of(kSeed6, x)) |
-                                     ((unsigned long long)(one << bit_of(kSeed7, x)) << 32),
-                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  lds_or_key<8>(lds2, in ? rel : 0u, (uint32_t)h, in ? 1u : 0u);
 }
 
 // Partition of one chunk of a partitioned filter's insert keys by slice: rank

@@ -86,6 +86,35 @@ __device__ __forceinline__ uint32_t bit_of(uint32_t seed, uint32_t hash_lo) {
   return (seed * hash_lo) >> 27;
 }
 
+// OR the mask of one key (low hash half x) into block bl of a filter of K-word
+// blocks held in LDS as K/2 64-bit word pairs (one = 0 ORs nothing). The i-th
+// OR goes to pair p = (i + r) mod K/2, r taken from block-index bits above the
+// eight 32-byte blocks of one 256-byte LDS bank row: with one key per lane and
+// the pairs in a fixed order, the i-th ORs of a wave's keys all fall on one of
+// eight bank offsets; rotated, they spread over the whole row. OR is
+// order-free, so the filter is the same either way.
+template <uint32_t K>
+__device__ __forceinline__ void lds_or_key(unsigned long long *lds2, uint32_t bl, uint32_t x, uint32_t one) {
+  constexpr uint32_t kPairs = K / 2u;
+  unsigned long long *blk = lds2 + (uint64_t)bl * kPairs;
+  const uint32_t r = ((bl >> 3) ^ (bl >> 5)) & (kPairs - 1u);
+#pragma unroll
+  for (uint32_t i = 0; i < kPairs; ++i) {
+    const uint32_t p = (i + r) & (kPairs - 1u);
+    // seeds of words 2p and 2p + 1, picked by compare-and-select
+    uint32_t sa = seed_k(0), sb = seed_k(1);
+#pragma unroll
+    for (uint32_t j = 1; j < kPairs; ++j) {
+      sa = p == j ? seed_k(2u * j) : sa;
+      sb = p == j ? seed_k(2u * j + 1u) : sb;
+    }
+    __hip_atomic_fetch_or(blk + p,
+                          (unsigned long long)(one << bit_of(sa, x)) |
+                              ((unsigned long long)(one << bit_of(sb, x)) << 32),
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // Value of `v` in lane `src` (0..63) of this wave.
