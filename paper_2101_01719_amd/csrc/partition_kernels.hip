@@ -33,6 +33,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "internal.h"
@@ -224,25 +225,46 @@ struct SliceCursor {
   uint32_t cursor[R], pbase[R], carry[R], carry_at[R];
 };
 
+// Fixed-capacity buckets of the count-free insert partition. Scatter
+// workgroup g writes its keys of slice s to bucket g * num_slices + s, which
+// holds up to cap keys (a multiple of 8) from position (g * num_slices + s) *
+// cap; count[g * num_slices + s] is the bucket's key count rounded up to a
+// multiple of four (padded with copies of its last key: a key inserted twice
+// sets the same bits). Keys that find their bucket full go to ovf (ovf_n of
+// them, at most ovf_cap), which a global-atomic pass inserts afterwards.
+struct Buckets {
+  uint32_t cap;
+  uint32_t *count;
+  uint64_t *ovf;
+  uint32_t *ovf_n;
+  uint32_t ovf_cap;
+};
+
+// End (exclusive) of scatter workgroup g's bucket of slice s.
+__device__ __forceinline__ uint32_t bucket_end(uint32_t g, uint32_t s, uint32_t num_slices, uint32_t cap) {
+  return (g * num_slices + s + 1u) * cap;
+}
+
 // One tile of the scatter: rank every key within its slice (LDS atomics),
 // scan the slice counts (plus carried keys), stage the keys sorted by slice
 // behind each slice's carried keys, and write every complete, aligned group
 // of L keys with consecutive lanes; the incomplete tail of each slice's run
 // stays in the stage as the next tile's carry. kFull: the whole tile is
 // inside the chunk (no per-key guards).
-template <bool kWithPos, int R, uint32_t L, bool kFull>
+template <bool kWithPos, int R, uint32_t L, bool kBucket, bool kFull>
 __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
                                              const uint32_t *__restrict__ new_chunk_hist, uint32_t num_blocks,
                                              uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
                                              uint32_t keys,
                                              const ScatterLds &S, SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
-                                             uint16_t *__restrict__ out_pos) {
+                                             uint16_t *__restrict__ out_pos, const Buckets &Bk) {
   // Keys are hashed here, where the prefetched tile is first used.
   if (keys) {
 #pragma unroll
     for (uint32_t t = 0; t < kScatterPer; ++t) h[t] = key_hash(h[t]);
   }
   static_assert(L == 1u || R <= 2, "carried groups need at most two slices per thread");
+  static_assert(!kBucket || (L >= 4u && !kWithPos), "buckets are for inserts with carried groups");
   constexpr uint32_t kCarryMax = L > 1u ? L - 1u : 1u;
   const uint32_t own = threadIdx.x * R;
   if constexpr (kWithPos) {
@@ -296,14 +318,22 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     }
     const uint32_t first = C.cursor[r] - C.carry[r];  // global position of staged position `run`
     const uint32_t end = C.cursor[r] + c[r];
-    const uint32_t aligned = end & ~(L - 1u);
+    uint32_t aligned = end & ~(L - 1u);
+    // Buckets: once the run passes the bucket's end, the bucket is written up
+    // to its end and the rest of the run goes to the overflow list, uncarried.
+    bool spill = false;
+    if constexpr (kBucket) {
+      const uint32_t cap_end = bucket_end(blockIdx.x, sl, num_slices, Bk.cap);
+      spill = end > cap_end;
+      if (spill) aligned = cap_end;
+    }
     const uint32_t wlen = aligned > first ? aligned - first : 0u;  // keys written by this tile
     if (sl < num_slices) {
       S.info[sl] = make_uint2(first - run, run + wlen);
       S.sbase[sl] = run + C.carry[r];
       if constexpr (kWithPos) S.pdelta[sl] = C.pbase[r] - (run + C.carry[r]);
     }
-    C.carry[r] = m[r] - wlen;
+    C.carry[r] = spill ? 0u : m[r] - wlen;
     C.carry_at[r] = run + wlen;
     C.cursor[r] = end;
     C.pbase[r] += c[r];
@@ -327,8 +357,17 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     const uint32_t k = t * kScatterThreads + threadIdx.x;
     if ((L == 1u && kFull) || k < total) {
       const uint64_t key = S.stage[k];
-      const uint2 in = S.info[local_slice(key, num_blocks, slice_shift, slice_base, num_slices)];
-      if (L == 1u || k < in.y) out_keys[k + in.x] = key;
+      const uint32_t sl = local_slice(key, num_blocks, slice_shift, slice_base, num_slices);
+      const uint2 in = S.info[sl];
+      if (L == 1u || k < in.y) {
+        out_keys[k + in.x] = key;
+      } else if constexpr (kBucket) {
+        // past the bucket's end: to the overflow list (carried keys are not)
+        if (k + in.x >= bucket_end(blockIdx.x, sl, num_slices, Bk.cap)) {
+          const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (o < Bk.ovf_cap) Bk.ovf[o] = key;
+        }
+      }
     }
   }
   // The next tile's first barrier orders these reads of stage and info
@@ -339,13 +378,13 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
 // of the chunk, the 16-bit position of its result inside the chunk's own
 // results (the chunk's runs of all slices laid end to end in slice order),
 // which is what the unpermute kernel reads back from LDS.
-template <bool kWithPos, int R, uint32_t L>
+template <bool kWithPos, int R, uint32_t L, bool kBucket>
 __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t chunks_per_group,
                     uint32_t num_blocks, uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
                     const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
                     const uint32_t *__restrict__ hist_rows, uint32_t keys, uint64_t *__restrict__ out_keys,
-                    uint16_t *__restrict__ out_pos) {
+                    uint16_t *__restrict__ out_pos, Buckets Bk) {
   extern __shared__ unsigned long long smem[];
   ScatterLds S;
   S.stage = reinterpret_cast<uint64_t *>(smem);
@@ -359,21 +398,31 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   const uint32_t u0 = blockIdx.x * chunks_per_group;
   uint32_t b, e;
   chunk_range(blockIdx.x, chunk * chunks_per_group, n, &b, &e);
-  if (b >= e) return;  // whole workgroup
-
   const uint32_t own = threadIdx.x * R;
-  const uint32_t *my_start = start + (uint64_t)u0 * num_slices;
-  const uint32_t *my_hist = hist_rows + (uint64_t)u0 * num_slices;
+  if (b >= e) {  // whole workgroup
+    if constexpr (kBucket) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (own + r < num_slices) Bk.count[blockIdx.x * num_slices + own + r] = 0u;
+    }
+    return;
+  }
+
+  const uint32_t *my_start = kBucket ? nullptr : start + (uint64_t)u0 * num_slices;
+  const uint32_t *my_hist = kWithPos ? hist_rows + (uint64_t)u0 * num_slices : nullptr;
   SliceCursor<R> C;
   uint32_t c[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t sl = own + r;
-    C.cursor[r] = sl < num_slices ? offsets[sl] + my_start[sl] : 0u;
+    if constexpr (kBucket)
+      C.cursor[r] = bucket_end(blockIdx.x, sl, num_slices, Bk.cap) - Bk.cap;
+    else
+      C.cursor[r] = sl < num_slices ? offsets[sl] + my_start[sl] : 0u;
     C.carry[r] = 0u;
     C.carry_at[r] = 0u;
     C.pbase[r] = 0u;
-    c[r] = sl < num_slices ? my_hist[sl] : 0u;
+    c[r] = kWithPos && sl < num_slices ? my_hist[sl] : 0u;
     if (sl < num_slices) S.hist[sl] = 0u;
   }
   if constexpr (kWithPos) {
@@ -393,10 +442,9 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   load_tile<kWithPos>(hashes, b, e, ha);
   uint32_t t0 = b, k = 0;
 #define SBBF_SCATTER_TILE(FULL, H)                                                                            \
-  scatter_tile<kWithPos, R, L, FULL>(H, t0, e, t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * \
-                                                                                   num_slices                  \
-                                                                             : nullptr,                        \
-                                     num_blocks, slice_shift, slice_base, num_slices, keys, S, C, out_keys, out_pos)
+  scatter_tile<kWithPos, R, L, kBucket, FULL>(                                                                \
+      H, t0, e, kWithPos && t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * num_slices : nullptr, \
+      num_blocks, slice_shift, slice_base, num_slices, keys, S, C, out_keys, out_pos, Bk)
   for (; k + 2u <= nfull; k += 2u) {
     load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
     SBBF_SCATTER_TILE(true, ha);
@@ -420,6 +468,23 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
 #pragma unroll
     for (int r = 0; r < R; ++r)
       for (uint32_t j = 0; j < C.carry[r]; ++j) out_keys[C.cursor[r] - C.carry[r] + j] = S.stage[C.carry_at[r] + j];
+  }
+  // Buckets: pad each to a multiple of four keys with copies of its last
+  // (carried) key and record its count. A bucket with no carry ends at a
+  // multiple of L (or is full), already a multiple of four.
+  if constexpr (kBucket) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t sl = own + r;
+      if (sl >= num_slices) continue;
+      const uint32_t cap_end = bucket_end(blockIdx.x, sl, num_slices, Bk.cap);
+      uint32_t end = min(C.cursor[r], cap_end);
+      if (C.carry[r] > 0u) {
+        const uint64_t last = S.stage[C.carry_at[r] + C.carry[r] - 1u];
+        for (; end & 3u; ++end) out_keys[end] = last;
+      }
+      Bk.count[blockIdx.x * num_slices + sl] = end - (cap_end - Bk.cap);
+    }
   }
 }
 
@@ -594,6 +659,103 @@ part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   __syncthreads();
   uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * K);
   for (uint32_t i = threadIdx.x; i < nb * (K / 4u); i += kPartThreads) dst4[i] = lds4[i];
+}
+
+// Records of one loop step of a bucketed slice: as load_step, over the
+// slice's buckets laid end to end (prefix[g]: keys of the slice's buckets of
+// workgroups before g; counts are multiples of four, so a group of four keys
+// lies in one bucket). Each group's bucket is found by binary search over the
+// prefix in LDS.
+constexpr uint32_t kMaxBucketGroups = 1024;  // scatter workgroups of a bucketed insert
+
+__device__ __forceinline__ void load_step_buckets(const uint64_t *__restrict__ part, const uint32_t *prefix,
+                                                  uint32_t groups, uint32_t slice, uint32_t num_slices, uint32_t cap,
+                                                  uint32_t base, uint32_t last, SliceStep &s) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t u = 0; u < kSliceSteps; ++u) {
+    const uint32_t v = min(base + 256u * u + 4u * lane, last);
+    // largest g < groups with prefix[g] <= v (prefix[0] = 0)
+    uint32_t g = 0;
+#pragma unroll
+    for (uint32_t step = kMaxBucketGroups / 2u; step > 0u; step >>= 1) {
+      const uint32_t t = g + step;
+      if (t < groups && prefix[t] <= v) g = t;
+    }
+    const u64x2 *p =
+        reinterpret_cast<const u64x2 *>(part + (uint64_t)(g * num_slices + slice) * cap + (v - prefix[g]));
+    const u64x2 a = __builtin_nontemporal_load(p);
+    const u64x2 b = __builtin_nontemporal_load(p + 1);
+    s.h[u][0] = a.x;
+    s.h[u][1] = a.y;
+    s.h[u][2] = b.x;
+    s.h[u][3] = b.y;
+  }
+}
+
+// Slice insert over the fixed-capacity buckets of a count-free partition
+// (one bucket per scatter workgroup): the slice in LDS, the buckets' key
+// counts scanned into a prefix after it, then the slice loop over the
+// buckets as one sequence.
+template <uint32_t K>
+__global__ void __launch_bounds__(kPartThreads)
+part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ counts, uint32_t groups,
+                          uint32_t cap, uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift,
+                          uint32_t num_slices) {
+  extern __shared__ uint4 lds4[];
+  unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
+  const uint32_t slice = blockIdx.x;
+  const uint32_t b0 = slice << slice_shift;
+  const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
+  uint32_t *prefix = reinterpret_cast<uint32_t *>(lds4 + ((size_t)nb * K) / 4u);  // [groups + 1]
+  uint32_t *wsum = prefix + kMaxBucketGroups + 1u;                               // [16]
+  uint32_t ns;
+  {
+    const uint32_t c[1] = {threadIdx.x < groups ? counts[threadIdx.x * num_slices + slice] : 0u};
+    const uint32_t run = block_scan_owned<1>(c, wsum, &ns);
+    if (threadIdx.x < groups) prefix[threadIdx.x] = run;
+  }
+  if (ns == 0) return;  // whole workgroup: the slice is unchanged
+  load_slice_to_lds<K>(lds4, words, b0, nb);
+  __syncthreads();
+
+  const uint32_t last = ns - 4u;  // counts are multiples of four
+  constexpr uint32_t waves = kPartThreads / kWave;
+  constexpr uint32_t stride = waves * 256u * kSliceSteps;
+  uint32_t base = wave_index() * 256u * kSliceSteps;
+  const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
+  SliceStep sa, sb;
+  load_step_buckets(part, prefix, groups, slice, num_slices, cap, base, last, sa);
+  for (uint32_t it = 0; it < steps; it += 2u) {
+    load_step_buckets(part, prefix, groups, slice, num_slices, cap, base + stride, last, sb);
+    __builtin_amdgcn_sched_barrier(0);
+    insert_step<K>(sa, base, ns, num_blocks, b0, nb, lds2);
+    base += stride;
+    load_step_buckets(part, prefix, groups, slice, num_slices, cap, base + stride, last, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    insert_step<K>(sb, base, ns, num_blocks, b0, nb, lds2);
+    base += stride;
+  }
+  __syncthreads();
+  uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * K);
+  for (uint32_t i = threadIdx.x; i < nb * (K / 4u); i += kPartThreads) dst4[i] = lds4[i];
+}
+
+// Keys that found their bucket full, inserted with global atomics after the
+// slice inserts (ovf_n of them; usually none).
+template <uint32_t K>
+__global__ void __launch_bounds__(256)
+part_overflow_insert_kernel(const uint64_t *__restrict__ ovf, const uint32_t *__restrict__ ovf_n, uint32_t ovf_cap,
+                            uint32_t *__restrict__ words, uint32_t num_blocks) {
+  const uint32_t n = min(*ovf_n, ovf_cap);
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    const uint64_t h = ovf[i];
+    const uint32_t x = (uint32_t)h;
+    uint32_t *blk = words + (uint64_t)block_of((uint32_t)(h >> 32), num_blocks) * K;
+#pragma unroll
+    for (uint32_t w = 0; w < K; ++w)
+      __hip_atomic_fetch_or(blk + w, 1u << bit_of(seed_k(w), x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 template <uint32_t K>
@@ -840,21 +1002,21 @@ void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uin
   if (*groups == 0) *groups = 1;
 }
 
-template <bool kWithPos, int R, uint32_t L>
+template <bool kWithPos, int R, uint32_t L, bool kBucket = false>
 hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
                           uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, uint32_t keys,
-                          const PartitionLayout &L_, hipStream_t stream) {
+                          const PartitionLayout &L_, hipStream_t stream, const Buckets &Bk = Buckets{}) {
   const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L, R);
   // Several chunks per workgroup (lookups cut the batch finer than inserts):
   // about two workgroups per compute unit.
   const uint32_t per = kWithPos ? (groups + L_.scatter_groups - 1u) / L_.scatter_groups : 1u;
   const uint32_t grid = (groups + per - 1u) / per;
-  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R, L>,
+  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R, L, kBucket>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
-  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L>), dim3(grid), dim3(kScatterThreads), lds, stream, hashes,
-                     n, chunk, per, num_blocks, slice_shift, slice_base, num_slices, L_.offsets, L_.start, L_.hist,
-                     keys, L_.keys, kWithPos ? L_.pos : nullptr);
+  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L, kBucket>), dim3(grid), dim3(kScatterThreads), lds, stream,
+                     hashes, n, chunk, per, num_blocks, slice_shift, slice_base, num_slices, L_.offsets, L_.start,
+                     L_.hist, keys, L_.keys, kWithPos ? L_.pos : nullptr, Bk);
   return hipGetLastError();
 }
 
@@ -958,6 +1120,94 @@ hipError_t unpermute(const PartitionLayout &L, uint32_t num_slices, uint32_t n, 
   return hipGetLastError();
 }
 
+// Count-free insert partition (fixed-capacity buckets, struct Buckets): for
+// one-level inserts into at most 2 * kScatterThreads slices (runs carried in
+// groups of four or eight keys), with at most kMaxBucketGroups scatter
+// workgroups and every bucket position below 2^32. It skips the count and
+// scan kernels (one read of the batch) at the price of bucket room (the
+// expected keys per bucket plus eight standard deviations and 32 keys) and an
+// overflow list as long as the batch.
+struct BucketPlan {
+  uint32_t chunk, groups, cap;
+  uint64_t count_off, ovfn_off, ovf_off, keys_off, bytes;
+};
+
+bool bucket_plan(uint64_t n, uint32_t num_slices, uint32_t max_groups, BucketPlan *bp) {
+  if (n == 0 || num_slices > 2u * kScatterThreads) return false;
+  chunking(n, max_groups, false, &bp->chunk, &bp->groups);
+  if (bp->groups > kMaxBucketGroups) return false;
+  // Keys of one chunk per slice: a slice holds at most 1 / (slices - 1) of
+  // the blocks (all but the last are whole).
+  const double mean = (double)bp->chunk / (double)(num_slices > 1u ? num_slices - 1u : 1u);
+  const uint64_t cap = ((uint64_t)(mean + 8.0 * std::sqrt(mean) + 32.0) + 7u) & ~(uint64_t)7u;
+  const uint64_t positions = (uint64_t)bp->groups * num_slices * cap;
+  if (positions >= (1ull << 32)) return false;
+  bp->cap = (uint32_t)cap;
+  auto up = [](uint64_t v) { return (v + 255u) & ~(uint64_t)255u; };
+  uint64_t off = 0;
+  bp->count_off = off;
+  off += up((uint64_t)bp->groups * num_slices * 4u);
+  bp->ovfn_off = off;
+  off += 256u;
+  bp->ovf_off = off;
+  off += up(n * 8u);
+  bp->keys_off = off;
+  off += up(positions * 8u);
+  bp->bytes = off;
+  return true;
+}
+
+template <uint32_t K>
+hipError_t launch_bucket_insert(const uint64_t *part, const uint32_t *counts, const BucketPlan &bp,
+                                uint32_t num_slices, uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
+                                hipStream_t stream) {
+  const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K + (kMaxBucketGroups + 1u + 16u) * 4u;
+  (void)hipFuncSetAttribute((const void *)part_bucket_insert_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(part_bucket_insert_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, part,
+                     counts, bp.groups, bp.cap, words, num_blocks, slice_shift, num_slices);
+  return hipGetLastError();
+}
+
+template <uint32_t K>
+hipError_t launch_overflow_insert(const Buckets &Bk, uint32_t *words, uint32_t num_blocks, hipStream_t stream) {
+  hipLaunchKernelGGL(part_overflow_insert_kernel<K>, dim3(256), dim3(256), 0, stream, Bk.ovf, Bk.ovf_n, Bk.ovf_cap,
+                     words, num_blocks);
+  return hipGetLastError();
+}
+
+hipError_t insert_buckets(const uint64_t *hashes, uint32_t n, uint32_t *words, uint32_t num_blocks,
+                          uint32_t slice_shift, uint32_t num_slices, void *workspace, const BucketPlan &bp,
+                          uint32_t keys, hipStream_t stream, uint32_t lanes) {
+  char *base = static_cast<char *>(workspace);
+  const Buckets Bk{bp.cap, reinterpret_cast<uint32_t *>(base + bp.count_off),
+                   reinterpret_cast<uint64_t *>(base + bp.ovf_off), reinterpret_cast<uint32_t *>(base + bp.ovfn_off),
+                   n};
+  hipError_t e = launch_fill(Bk.ovf_n, 1u, 0u, stream);  // a fill kernel, not a memset (graph capture)
+  if (e != hipSuccess) return e;
+  PartitionLayout L{};
+  L.keys = reinterpret_cast<uint64_t *>(base + bp.keys_off);
+  L.scatter_groups = bp.groups;
+  if (num_slices <= kScatterThreads)
+    e = launch_scatter<false, 1, kScatterGroup, true>(hashes, n, bp.chunk, bp.groups, num_blocks, slice_shift, 0u,
+                                                       num_slices, keys, L, stream, Bk);
+  else
+    e = launch_scatter<false, 2, 4, true>(hashes, n, bp.chunk, bp.groups, num_blocks, slice_shift, 0u, num_slices,
+                                          keys, L, stream, Bk);
+  if (e != hipSuccess) return e;
+  if (lanes == 4) {
+    e = launch_bucket_insert<4>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
+    return e != hipSuccess ? e : launch_overflow_insert<4>(Bk, words, num_blocks, stream);
+  }
+  if (lanes == 16) {
+    e = launch_bucket_insert<16>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
+    return e != hipSuccess ? e : launch_overflow_insert<16>(Bk, words, num_blocks, stream);
+  }
+  e = launch_bucket_insert<8>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
+  return e != hipSuccess ? e : launch_overflow_insert<8>(Bk, words, num_blocks, stream);
+}
+
 // One level: the n keys all lie in the num_slices slices from slice_base.
 hipError_t insert_level(const uint64_t *hashes, uint32_t n, uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
                         uint32_t slice_base, uint32_t num_slices, void *workspace, uint32_t max_groups, uint32_t keys,
@@ -1046,7 +1296,12 @@ uint64_t partition_max_keys() { return 1ull << 31; }
 uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max_groups, bool lookup) {
   uint32_t chunk, groups;
   chunking(n, max_groups, lookup, &chunk, &groups);
-  if (num_slices <= kOneLevelSlices) return layout(nullptr, n, num_slices, groups, lookup).bytes;
+  if (num_slices <= kOneLevelSlices) {
+    const uint64_t counted = layout(nullptr, n, num_slices, groups, lookup).bytes;
+    BucketPlan bp;
+    if (!lookup && bucket_plan(n, num_slices, max_groups, &bp)) return std::max(counted, bp.bytes);
+    return counted;
+  }
   // level 1, then level 2 for at most all n keys in one group
   const uint32_t g = (num_slices + kGroupSlices - 1u) >> kGroupShift;
   return layout(nullptr, n, g, groups, lookup).bytes + partition_workspace_bytes(n, kGroupSlices, max_groups, lookup);
@@ -1059,9 +1314,14 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   if (lanes != 4 && lanes != 8 && lanes != 16) return hipErrorInvalidValue;
   const uint32_t num_slices = slices_of(num_blocks, slice_shift);
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
-  if (num_slices <= kOneLevelSlices)
+  if (num_slices <= kOneLevelSlices) {
+    BucketPlan bp;
+    if (bucket_plan(n, num_slices, max_groups, &bp))
+      return insert_buckets(hashes, (uint32_t)n, words, num_blocks, slice_shift, num_slices, workspace, bp, keys,
+                            stream, lanes);
     return insert_level(hashes, (uint32_t)n, words, num_blocks, slice_shift, 0u, num_slices, workspace, max_groups,
                         keys, stream, lanes);
+  }
   TwoLevel t = two_level_plan(workspace, n, num_slices, max_groups, false);
   hipError_t e = partition(hashes, (uint32_t)n, num_blocks, slice_shift + kGroupShift, 0u, t.groups, t.chunk,
                            t.chunks, t.L1, false, keys, stream);

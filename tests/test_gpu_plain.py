@@ -388,3 +388,71 @@ def test_partitioned_two_slices_per_thread(P):
     bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
     assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
     f.close()
+
+
+def _skewed(seed, n, B, slices_hot, frac_hot):
+    """n hashes: a fraction frac_hot with high halves inside the first
+    slices_hot slices of 4,096 blocks (so their per-slice runs far exceed an
+    even share), the rest uniform."""
+    h = splitmix64_stream(seed, n)
+    hot = int(n * frac_hot)
+    span = (slices_hot * 4096 << 32) // B  # high halves mapping below block slices_hot * 4096
+    hi = (h[:hot] >> np.uint64(32)) % np.uint64(max(span, 1))
+    h[:hot] = (hi << np.uint64(32)) | (h[:hot] & np.uint64(0xFFFFFFFF))
+    return h
+
+
+@pytest.mark.parametrize("B,slices_hot,frac_hot", [(4096 * 64, 1, 1.0), (4096 * 256 + 9, 3, 0.5),
+                                                   (4096 * 1536 + 7, 1, 0.3)])
+def test_partitioned_insert_skewed(P, B, slices_hot, frac_hot):
+    """Batches whose keys crowd into a few slices: runs longer than a
+    partition bucket holds go through the overflow path; the filter must
+    still equal the oracle's, inserted into a non-empty filter."""
+    h = _skewed(580 + slices_hot, 3_000_000, B, slices_hot, frac_hot)
+    pre = splitmix64_stream(581, 50_000)
+    ref = oracle.build_filter(B, np.concatenate([pre, h]))
+    f = P.Filter(B)
+    f.insert(dev(pre), launch=dict(strategy=1))
+    f.insert(dev(h), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    f.close()
+
+
+def test_partitioned_insert_repeated_hash(P):
+    """Half the batch is one hash repeated: one bucket per partition
+    workgroup overflows, everything else is spread evenly."""
+    B = 4096 * 128
+    h = splitmix64_stream(582, 4_000_000)
+    h[::2] = np.uint64(0x9E3779B97F4A7C15)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    f.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 7, 8, 9, 15, 17, 63, 7167, 7168, 7169])
+def test_partitioned_insert_tiny_batches(P, n):
+    """Batches of a few keys over 40 slices: buckets of one to a few keys
+    (padded to four with copies of their last key)."""
+    B = 4096 * 40 + 3
+    h = splitmix64_stream(583 + n, n)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=4))
+    assert np.array_equal(words_of(f), ref)
+    f.close()
+
+
+@pytest.mark.parametrize("grid", [1, 3, 700, 1500])
+def test_partitioned_insert_grid_sizes(P, grid):
+    """Partition workgroup counts from one (one bucket per slice holding the
+    whole batch's share) to more than a bucketed partition takes (the
+    counted partition then)."""
+    B = 4096 * 300 + 11
+    h = splitmix64_stream(584 + grid, 6_000_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=4, grid_blocks=grid))
+    assert np.array_equal(words_of(f), ref)
+    f.close()
