@@ -226,12 +226,13 @@ struct SliceCursor {
 };
 
 // Fixed-capacity buckets of the count-free insert partition. Scatter
-// workgroup g writes its keys of slice s to bucket g * num_slices + s, which
-// holds up to cap keys (a multiple of 8) from position (g * num_slices + s) *
-// cap; count[g * num_slices + s] is the bucket's key count rounded up to a
-// multiple of four (padded with copies of its last key: a key inserted twice
-// sets the same bits). Keys that find their bucket full go to ovf (ovf_n of
-// them, at most ovf_cap), which a global-atomic pass inserts afterwards.
+// workgroup g (of G = gridDim.x) writes its keys of slice s to bucket
+// s * G + g (a slice's buckets are adjacent), which holds up to cap keys (a
+// multiple of 8) from position (s * G + g) * cap; count[s * G + g] is the
+// bucket's key count rounded up to a multiple of four (padded with copies of
+// its last key: a key inserted twice sets the same bits). Keys that find their
+// bucket full go to ovf (ovf_n of them, at most ovf_cap), which a
+// global-atomic pass inserts afterwards.
 struct Buckets {
   uint32_t cap;
   uint32_t *count;
@@ -241,8 +242,8 @@ struct Buckets {
 };
 
 // End (exclusive) of scatter workgroup g's bucket of slice s.
-__device__ __forceinline__ uint32_t bucket_end(uint32_t g, uint32_t s, uint32_t num_slices, uint32_t cap) {
-  return (g * num_slices + s + 1u) * cap;
+__device__ __forceinline__ uint32_t bucket_end(uint32_t g, uint32_t s, uint32_t cap) {
+  return (s * gridDim.x + g + 1u) * cap;
 }
 
 // One tile of the scatter: rank every key within its slice (LDS atomics),
@@ -323,7 +324,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     // to its end and the rest of the run goes to the overflow list, uncarried.
     bool spill = false;
     if constexpr (kBucket) {
-      const uint32_t cap_end = bucket_end(blockIdx.x, sl, num_slices, Bk.cap);
+      const uint32_t cap_end = bucket_end(blockIdx.x, sl, Bk.cap);
       spill = end > cap_end;
       if (spill) aligned = cap_end;
     }
@@ -363,7 +364,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
         out_keys[k + in.x] = key;
       } else if constexpr (kBucket) {
         // past the bucket's end: to the overflow list (carried keys are not)
-        if (k + in.x >= bucket_end(blockIdx.x, sl, num_slices, Bk.cap)) {
+        if (k + in.x >= bucket_end(blockIdx.x, sl, Bk.cap)) {
           const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (o < Bk.ovf_cap) Bk.ovf[o] = key;
         }
@@ -403,7 +404,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
     if constexpr (kBucket) {
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if (own + r < num_slices) Bk.count[blockIdx.x * num_slices + own + r] = 0u;
+        if (own + r < num_slices) Bk.count[(own + r) * gridDim.x + blockIdx.x] = 0u;
     }
     return;
   }
@@ -416,7 +417,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   for (int r = 0; r < R; ++r) {
     const uint32_t sl = own + r;
     if constexpr (kBucket)
-      C.cursor[r] = bucket_end(blockIdx.x, sl, num_slices, Bk.cap) - Bk.cap;
+      C.cursor[r] = bucket_end(blockIdx.x, sl, Bk.cap) - Bk.cap;
     else
       C.cursor[r] = sl < num_slices ? offsets[sl] + my_start[sl] : 0u;
     C.carry[r] = 0u;
@@ -477,13 +478,13 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
     for (int r = 0; r < R; ++r) {
       const uint32_t sl = own + r;
       if (sl >= num_slices) continue;
-      const uint32_t cap_end = bucket_end(blockIdx.x, sl, num_slices, Bk.cap);
+      const uint32_t cap_end = bucket_end(blockIdx.x, sl, Bk.cap);
       uint32_t end = min(C.cursor[r], cap_end);
       if (C.carry[r] > 0u) {
         const uint64_t last = S.stage[C.carry_at[r] + C.carry[r] - 1u];
         for (; end & 3u; ++end) out_keys[end] = last;
       }
-      Bk.count[blockIdx.x * num_slices + sl] = end - (cap_end - Bk.cap);
+      Bk.count[sl * gridDim.x + blockIdx.x] = end - (cap_end - Bk.cap);
     }
   }
 }
@@ -662,28 +663,32 @@ part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
 }
 
 // Records of one loop step of a bucketed slice: as load_step, over the
-// slice's buckets laid end to end (prefix[g]: keys of the slice's buckets of
-// workgroups before g; counts are multiples of four, so a group of four keys
-// lies in one bucket). Each group's bucket is found by binary search over the
-// prefix in LDS.
+// slice's buckets laid end to end (prefix[g]: keys in the buckets before
+// bucket g; counts are multiples of four, so a group of four keys lies in one
+// bucket). A group at position v finds its bucket from the coarse map
+// (map[m]: the bucket holding position m << map_shift; map[m + 1] bounds the
+// search from above), then a binary search over that range, usually of one
+// or two buckets. part points at the slice's first bucket.
 constexpr uint32_t kMaxBucketGroups = 1024;  // scatter workgroups of a bucketed insert
+constexpr uint32_t kBucketMap = 4096;        // coarse map entries
 
-__device__ __forceinline__ void load_step_buckets(const uint64_t *__restrict__ part, const uint32_t *prefix,
-                                                  uint32_t groups, uint32_t slice, uint32_t num_slices, uint32_t cap,
+__device__ __forceinline__ void load_step_buckets(const uint64_t *__restrict__ part, uint32_t cap,
+                                                  const uint32_t *prefix, const uint16_t *map, uint32_t map_shift,
                                                   uint32_t base, uint32_t last, SliceStep &s) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (uint32_t u = 0; u < kSliceSteps; ++u) {
     const uint32_t v = min(base + 256u * u + 4u * lane, last);
-    // largest g < groups with prefix[g] <= v (prefix[0] = 0)
-    uint32_t g = 0;
-#pragma unroll
-    for (uint32_t step = kMaxBucketGroups / 2u; step > 0u; step >>= 1) {
-      const uint32_t t = g + step;
-      if (t < groups && prefix[t] <= v) g = t;
+    const uint32_t m = v >> map_shift;
+    uint32_t lo = map[m], hi = map[m + 1u];
+    while (lo < hi) {  // largest g in [lo, hi] with prefix[g] <= v
+      const uint32_t mid = (lo + hi + 1u) >> 1;
+      if (prefix[mid] <= v)
+        lo = mid;
+      else
+        hi = mid - 1u;
     }
-    const u64x2 *p =
-        reinterpret_cast<const u64x2 *>(part + (uint64_t)(g * num_slices + slice) * cap + (v - prefix[g]));
+    const u64x2 *p = reinterpret_cast<const u64x2 *>(part + (uint64_t)lo * cap + (v - prefix[lo]));
     const u64x2 a = __builtin_nontemporal_load(p);
     const u64x2 b = __builtin_nontemporal_load(p + 1);
     s.h[u][0] = a.x;
@@ -694,44 +699,60 @@ __device__ __forceinline__ void load_step_buckets(const uint64_t *__restrict__ p
 }
 
 // Slice insert over the fixed-capacity buckets of a count-free partition
-// (one bucket per scatter workgroup): the slice in LDS, the buckets' key
-// counts scanned into a prefix after it, then the slice loop over the
-// buckets as one sequence.
+// (one bucket per scatter workgroup): the slice in LDS, then the buckets' key
+// counts scanned into a prefix and a coarse map after it, then the slice
+// loop over the buckets as one sequence.
 template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ counts, uint32_t groups,
-                          uint32_t cap, uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift,
-                          uint32_t num_slices) {
+                          uint32_t cap, uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift) {
   extern __shared__ uint4 lds4[];
   unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
   const uint32_t slice = blockIdx.x;
   const uint32_t b0 = slice << slice_shift;
   const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
-  uint32_t *prefix = reinterpret_cast<uint32_t *>(lds4 + ((size_t)nb * K) / 4u);  // [groups + 1]
-  uint32_t *wsum = prefix + kMaxBucketGroups + 1u;                               // [16]
+  // after the largest slice: prefix [kMaxBucketGroups + 1], map [kBucketMap + 1], wsum [16]
+  uint32_t *prefix = reinterpret_cast<uint32_t *>(lds4 + (((size_t)1 << slice_shift) * K) / 4u);
+  uint16_t *map = reinterpret_cast<uint16_t *>(prefix + kMaxBucketGroups + 1u);
+  uint32_t *wsum = prefix + kMaxBucketGroups + 1u + (kBucketMap + 2u) / 2u;
+  const uint32_t *my_counts = counts + (uint64_t)slice * groups;
   uint32_t ns;
+  const uint32_t cnt = threadIdx.x < groups ? my_counts[threadIdx.x] : 0u;
+  uint32_t start;
   {
-    const uint32_t c[1] = {threadIdx.x < groups ? counts[threadIdx.x * num_slices + slice] : 0u};
-    const uint32_t run = block_scan_owned<1>(c, wsum, &ns);
-    if (threadIdx.x < groups) prefix[threadIdx.x] = run;
+    const uint32_t c[1] = {cnt};
+    start = block_scan_owned<1>(c, wsum, &ns);
   }
   if (ns == 0) return;  // whole workgroup: the slice is unchanged
+  // Smallest map_shift >= 6 with at most kBucketMap map entries.
+  uint32_t map_shift = 6;
+  while (((ns - 1u) >> map_shift) + 1u > kBucketMap) ++map_shift;
+  const uint32_t entries = ((ns - 1u) >> map_shift) + 1u;
+  if (threadIdx.x < groups) {
+    prefix[threadIdx.x] = start;
+    // map entries whose position lies in this (non-empty) bucket
+    for (uint32_t m = (uint32_t)(((uint64_t)start + (1u << map_shift) - 1u) >> map_shift);
+         ((uint64_t)m << map_shift) < (uint64_t)start + cnt; ++m)
+      map[m] = (uint16_t)threadIdx.x;
+  }
+  if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);  // upper bound for the last entry
   load_slice_to_lds<K>(lds4, words, b0, nb);
   __syncthreads();
 
+  const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
   const uint32_t last = ns - 4u;  // counts are multiples of four
   constexpr uint32_t waves = kPartThreads / kWave;
   constexpr uint32_t stride = waves * 256u * kSliceSteps;
   uint32_t base = wave_index() * 256u * kSliceSteps;
   const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
   SliceStep sa, sb;
-  load_step_buckets(part, prefix, groups, slice, num_slices, cap, base, last, sa);
+  load_step_buckets(part_slice, cap, prefix, map, map_shift, base, last, sa);
   for (uint32_t it = 0; it < steps; it += 2u) {
-    load_step_buckets(part, prefix, groups, slice, num_slices, cap, base + stride, last, sb);
+    load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sb);
     __builtin_amdgcn_sched_barrier(0);
     insert_step<K>(sa, base, ns, num_blocks, b0, nb, lds2);
     base += stride;
-    load_step_buckets(part, prefix, groups, slice, num_slices, cap, base + stride, last, sa);
+    load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sa);
     __builtin_amdgcn_sched_barrier(0);
     insert_step<K>(sb, base, ns, num_blocks, b0, nb, lds2);
     base += stride;
@@ -1161,12 +1182,13 @@ template <uint32_t K>
 hipError_t launch_bucket_insert(const uint64_t *part, const uint32_t *counts, const BucketPlan &bp,
                                 uint32_t num_slices, uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
                                 hipStream_t stream) {
-  const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K + (kMaxBucketGroups + 1u + 16u) * 4u;
+  const size_t lds_bytes =
+      ((size_t)1 << slice_shift) * 4u * K + (kMaxBucketGroups + 1u + (kBucketMap + 2u) / 2u + 16u) * 4u;
   (void)hipFuncSetAttribute((const void *)part_bucket_insert_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes);
   (void)hipGetLastError();
   hipLaunchKernelGGL(part_bucket_insert_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, part,
-                     counts, bp.groups, bp.cap, words, num_blocks, slice_shift, num_slices);
+                     counts, bp.groups, bp.cap, words, num_blocks, slice_shift);
   return hipGetLastError();
 }
 
