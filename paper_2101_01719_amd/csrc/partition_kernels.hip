@@ -718,6 +718,18 @@ part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__r
   const uint32_t *my_counts = counts + (uint64_t)slice * groups;
   uint32_t ns;
   const uint32_t cnt = threadIdx.x < groups ? my_counts[threadIdx.x] : 0u;
+  // The slice's loads are issued before the scan and the map are built (a
+  // slice is at most 128 KiB: eight 16-byte pieces per thread) and stored to
+  // LDS after.
+  static_assert(8u * kPartThreads * 16u >= (128u << 10), "one round of loads holds a slice");
+  const u64x2 *src = reinterpret_cast<const u64x2 *>(words + (uint64_t)b0 * K);
+  const uint32_t count4 = nb * (K / 4u);
+  u64x2 q[8];
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    q[u] = i < count4 ? __builtin_nontemporal_load(src + i) : u64x2{0ull, 0ull};
+  }
   uint32_t start;
   {
     const uint32_t c[1] = {cnt};
@@ -736,7 +748,12 @@ part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__r
       map[m] = (uint16_t)threadIdx.x;
   }
   if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);  // upper bound for the last entry
-  load_slice_to_lds<K>(lds4, words, b0, nb);
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    if (i < count4) lds4[i] = make_uint4((uint32_t)q[u].x, (uint32_t)(q[u].x >> 32), (uint32_t)q[u].y,
+                                         (uint32_t)(q[u].y >> 32));
+  }
   __syncthreads();
 
   const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
@@ -1338,7 +1355,8 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
   if (num_slices > partition_max_slices() || n > partition_max_keys()) return hipErrorInvalidValue;
   if (num_slices <= kOneLevelSlices) {
     BucketPlan bp;
-    if (bucket_plan(n, num_slices, max_groups, &bp))
+    // (the bucketed slice insert loads a slice of at most 128 KiB in one round)
+    if (((uint64_t)4u * lanes << slice_shift) <= (128u << 10) && bucket_plan(n, num_slices, max_groups, &bp))
       return insert_buckets(hashes, (uint32_t)n, words, num_blocks, slice_shift, num_slices, workspace, bp, keys,
                             stream, lanes);
     return insert_level(hashes, (uint32_t)n, words, num_blocks, slice_shift, 0u, num_slices, workspace, max_groups,
