@@ -106,7 +106,9 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
     ci = copies[0]
     f_fetch, f_write = want_kib / fetch[ci][3], want_kib / write[ci][3]
     # Library dispatches after the copy: fill (clear), then the insert
-    # kernels, then the lookup kernels, step after step.
+    # kernels (a bucketed insert starts with a fill of its overflow count and
+    # ends with the overflow pass; a counted one ends with the slice insert),
+    # then the lookup kernels, step after step.
     ops = {"insert": [], "lookup": []}
     cur, cur_op = [], "insert"
     for i in range(ci + 1, len(fetch)):
@@ -117,7 +119,7 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
             cur, cur_op = [], "insert"
             continue
         cur.append((name, fetch[i][3], write[i][3]))
-        if name.startswith(("part_slice_insert", "insert_")):
+        if name.startswith(("part_slice_insert", "part_overflow_insert", "insert_")):
             ops["insert"].append(cur)
             cur, cur_op = [], "lookup"
         elif name.startswith(("part_unpermute", "lookup_kernel")):

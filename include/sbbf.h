@@ -74,13 +74,18 @@ typedef enum sbbf_insert_strategy {
                                workgroup's LDS */
   SBBF_INSERT_PARTITIONED = 4 /* keys split by filter slice (a slice fits one workgroup's
                                LDS), then one workgroup ORs each slice in LDS and stores
-                               it back; no global atomics on the filter. Uses a
-                               stream-ordered device workspace of about 8 bytes per key
-                               (batches above 2^31 keys are processed 2^31 at a time).
-                               Filters of more than 4,096 slices (above 512 MiB) are
-                               partitioned in two levels (by group of 1,024 slices, then
-                               by slice), about twice the workspace, and the call waits
-                               for the stream once to size the second level */
+                               it back; no global atomics on the filter. Filters of up
+                               to 2,048 slices split without counting first: each
+                               partitioning workgroup fills fixed-room buckets per
+                               slice, and keys that find theirs full (skewed batches)
+                               are ORed with global atomics afterwards. Uses a
+                               stream-ordered device workspace of about 22 bytes per
+                               key (8 bytes per key with counting; batches above 2^31
+                               keys are processed 2^31 at a time). Filters of more than
+                               4,096 slices (above 512 MiB) are partitioned in two
+                               levels (by group of 1,024 slices, then by slice), about
+                               twice the workspace, and the call waits for the stream
+                               once to size the second level */
 } sbbf_insert_strategy;
 
 /* Lookup strategies (the `strategy` field of sbbf_launch for lookups). All
