@@ -456,3 +456,59 @@ def test_partitioned_insert_grid_sizes(P, grid):
     f.insert(dev(h), launch=dict(strategy=4, grid_blocks=grid))
     assert np.array_equal(words_of(f), ref)
     f.close()
+
+
+@pytest.mark.parametrize("B,slices_hot,frac_hot", [(4096 * 64, 1, 1.0), (4096 * 1024, 2, 0.4),
+                                                   (4096 * 1536 + 7, 1, 0.2)])
+def test_partitioned_lookup_skewed(P, B, slices_hot, frac_hot):
+    """Lookups crowding into a few slices (members among them): a few slice
+    runs hold most of the batch, the rest are short or empty; bytes and
+    bits both match the oracle."""
+    h = _skewed(590 + slices_hot, 400_000, B, slices_hot, frac_hot)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=1))
+    probes = np.concatenate([_skewed(592 + slices_hot, 2_500_000, B, slices_hot, frac_hot), h[::2]])
+    probes = probes[np.random.default_rng(slices_hot).permutation(probes.size)]
+    want = oracle.lookup(ref, B, probes)
+    assert want.any() and not want.all()
+    got = f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy()
+    assert np.array_equal(got, want)
+    bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
+    f.close()
+
+
+def test_partitioned_lookup_repeated_hash(P):
+    """Every third probe is one member hash: one slice run per chunk holds a
+    third of the chunk's keys; the rest are spread evenly."""
+    B = 4096 * 512
+    h = splitmix64_stream(594, 1_000_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=1))
+    probes = splitmix64_stream(595, 3_000_001)
+    probes[::3] = h[12345]
+    want = oracle.lookup(ref, B, probes)
+    got = f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy()
+    assert np.array_equal(got, want)
+    bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
+    f.close()
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 255, 256, 257, 43_007, 43_008, 43_009, 1_000_003])
+def test_partitioned_lookup_batch_sizes(P, n):
+    """Lookup batches from one key to several partition chunks (ragged last
+    chunk; bit output words across chunk ends)."""
+    B = 4096 * 1000 + 17
+    h = splitmix64_stream(596, 500_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=1))
+    probes = np.concatenate([h[: n // 2], splitmix64_stream(597 + n, n - n // 2)])
+    want = oracle.lookup(ref, B, probes)
+    assert np.array_equal(f.lookup(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy(), want)
+    bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
+    f.close()
