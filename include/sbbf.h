@@ -323,6 +323,10 @@ typedef struct sbbf_grouped_config {
   uint32_t insert_slice_shift;   /* log2 blocks per insert slice (a slice fits one workgroup's LDS) */
   uint32_t xcd_queues;           /* 1: lookup tiles of a filter stay on one XCD queue; 0: one queue */
   uint64_t insert_lds_bytes;     /* filters up to this size are inserted whole by one workgroup */
+  uint32_t lookup_lds_slices;    /* filters of at most this many slices of 4 * lookup_lds_threads blocks are
+                                    looked up from LDS, one slice at a time, by tiles of 16 keys per thread
+                                    held in registers; 0: every filter is looked up by the gather */
+  uint32_t lookup_lds_threads;   /* LDS lookup workgroup size: 256, 512 or 1024 (slices of 32, 64 or 128 KiB) */
 } sbbf_grouped_config;
 
 /* Defaults for the current device. */

@@ -54,6 +54,8 @@ class sbbf_grouped_config(ctypes.Structure):
         ("insert_slice_shift", c_u32),
         ("xcd_queues", c_u32),
         ("insert_lds_bytes", c_u64),
+        ("lookup_lds_slices", c_u32),
+        ("lookup_lds_threads", c_u32),
     ]
 
 

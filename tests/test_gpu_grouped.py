@@ -74,6 +74,11 @@ CONFIGS = [
     dict(lookup_tile_keys=4096, lookup_unroll=4, lookup_threads=128),
     dict(insert_lds_bytes=2048, insert_slice_shift=6),   # every filter above 2 KiB cut into 64-block slices
     dict(insert_lds_bytes=1 << 16, insert_slice_shift=11),
+    dict(lookup_lds_slices=1),                             # filters of one 128 KiB slice from LDS
+    dict(lookup_lds_slices=1024),                          # every filter from LDS, slice by slice
+    dict(lookup_lds_slices=2, lookup_tile_keys=4096, xcd_queues=0),
+    dict(lookup_lds_slices=4, lookup_lds_threads=256),     # slices of 32 KiB
+    dict(lookup_lds_slices=1024, lookup_lds_threads=512),  # slices of 64 KiB
 ]
 
 
@@ -224,4 +229,48 @@ def test_grouped_many_runs_per_slice(P):
         ref = oracle.build_filter(B, ins[ins_off[f]:ins_off[f + 1]])
         assert np.array_equal(filters[f].words.cpu().numpy().view(np.uint32), ref), f
         assert np.array_equal(res[look_off[f]:look_off[f + 1]], oracle.lookup(ref, B, look[look_off[f]:look_off[f + 1]]))
+    g.close()
+
+
+def _multi_slice_workload():
+    """Filters around the LDS slice sizes (1,024, 2,048, 4,096 blocks) and
+    well above them, with ragged lookup counts around the LDS tiles (4,096,
+    8,192, 16,384 keys) and none."""
+    from types import SimpleNamespace
+
+    blocks = [1, 7, 4095, 4096, 4097, 8195, 5 * 4096 + 17, 40_000, 300, 1024, 2049]
+    n_look = [5, 16_385, 16_383, 16_384, 0, 40_000, 70_001, 100_000, 1, 4097, 8191]
+    ins, look = [], []
+    for f, (b, nl) in enumerate(zip(blocks, n_look)):
+        h = splitmix64_stream(700 + f, 24 * b)
+        ins.append(h)
+        m = min(nl // 3, h.size)
+        probes = np.concatenate([h[:m], splitmix64_stream(800 + f, nl - m)])
+        look.append(probes[np.random.default_rng(f).permutation(nl)])
+    off = lambda parts: np.concatenate([[0], np.cumsum([len(a) for a in parts])]).astype(np.uint64)
+    return SimpleNamespace(blocks=np.array(blocks, dtype=np.uint64), num_filters=len(blocks), ins_off=off(ins),
+                           look_off=off(look), inserts=np.concatenate(ins), lookups=np.concatenate(look))
+
+
+@pytest.mark.parametrize("slices,threads", [(0, 1024), (1, 1024), (3, 1024), (1024, 1024), (2, 256), (1024, 256),
+                                            (5, 512)])
+def test_grouped_lds_lookup_multi_slice(P, slices, threads):
+    """LDS lookups of filters of one to ten slices (last slice partial),
+    mixed with gather lookups of the filters above the threshold; bytes
+    identical to the oracle's for every filter, also on graph replays."""
+    w = _multi_slice_workload()
+    filters, g = make_group(P, w, dict(lookup_lds_slices=slices, lookup_lds_threads=threads))
+    ins, look = dev(w.inserts), dev(w.lookups)
+    out = torch.full((look.numel(),), 9, dtype=torch.uint8, device="cuda")
+    g.run(ins, look, out)
+    torch.cuda.synchronize()
+    check_against_oracle(w, filters, out, range(w.num_filters))
+    first = out.clone()
+    for _ in range(2):
+        g.clear()
+        out.fill_(9)
+        torch.cuda.synchronize()
+        g.run(ins, look, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, first)
     g.close()
