@@ -238,8 +238,8 @@ def _multi_slice_workload():
     8,192, 16,384 keys) and none."""
     from types import SimpleNamespace
 
-    blocks = [1, 7, 4095, 4096, 4097, 8195, 5 * 4096 + 17, 40_000, 300, 1024, 2049]
-    n_look = [5, 16_385, 16_383, 16_384, 0, 40_000, 70_001, 100_000, 1, 4097, 8191]
+    blocks = [1, 7, 4095, 4096, 4097, 8195, 5 * 4096 + 17, 40_000, 300, 1024, 2049, 70_000]
+    n_look = [5, 16_385, 16_383, 16_384, 0, 40_000, 70_001, 100_000, 1, 4097, 8191, 5_000]
     ins, look = [], []
     for f, (b, nl) in enumerate(zip(blocks, n_look)):
         h = splitmix64_stream(700 + f, 24 * b)
