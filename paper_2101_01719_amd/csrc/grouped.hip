@@ -854,13 +854,16 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   p.pd.n_ins_tiles = p.n_ins_tiles;
   p.pd.n_parts = (uint32_t)parts.size();
   p.pd.n_slices = (uint32_t)slices.size();
+  // The kernels' dynamic LDS limit is a property of the function, shared by
+  // every group: it is raised to the device's maximum, never lowered to this
+  // plan's need, so that planning another group cannot break this one's graph.
   (void)hipFuncSetAttribute((const void *)grouped_insert_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)insert_kernel_lds(p));
+                            (int)info.lds_per_block);
   (void)hipFuncSetAttribute((const void *)grouped_part_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)kPartLds);
-  if (p.n_lds_tiles)
-    (void)hipFuncSetAttribute(lds_lookup_func(cfg.lookup_lds_threads), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)p.lds_look_bytes);
+                            (int)info.lds_per_block);
+  for (uint32_t t : {256u, 512u, 1024u})
+    (void)hipFuncSetAttribute(lds_lookup_func(t), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)info.lds_per_block);
   (void)hipGetLastError();
   p.planned = true;
   return SBBF_OK;

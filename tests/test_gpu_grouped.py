@@ -274,3 +274,30 @@ def test_grouped_lds_lookup_multi_slice(P, slices, threads):
         torch.cuda.synchronize()
         assert torch.equal(out, first)
     g.close()
+
+
+def test_two_groups_planned_in_turn(P):
+    """Two groups with different LDS needs (large filters: 128 KiB slices;
+    small filters: a few KiB), planned one after the other, then run, the
+    first after the second was planned: planning it must not break the first."""
+    from types import SimpleNamespace
+
+    def workload(blocks, seed):
+        ins = [splitmix64_stream(seed + f, 20 * b) for f, b in enumerate(blocks)]
+        look = [np.concatenate([h[::3], splitmix64_stream(seed + 100 + f, h.size)]) for f, h in enumerate(ins)]
+        off = lambda parts: np.concatenate([[0], np.cumsum([len(a) for a in parts])]).astype(np.uint64)
+        return SimpleNamespace(blocks=np.array(blocks, dtype=np.uint64), num_filters=len(blocks), ins_off=off(ins),
+                               look_off=off(look), inserts=np.concatenate(ins), lookups=np.concatenate(look))
+
+    wa = workload([20_000, 9_000, 4_096], 900)
+    wb = workload([50, 300, 7], 950)
+    fa, ga = make_group(P, wa, dict(lookup_lds_slices=8))
+    fb, gb = make_group(P, wb, dict(lookup_lds_slices=8))
+    for w, filters, g in ((wa, fa, ga), (wb, fb, gb)):
+        ins, look = dev(w.inserts), dev(w.lookups)
+        out = torch.empty(look.numel(), dtype=torch.uint8, device="cuda")
+        g.run(ins, look, out)
+        torch.cuda.synchronize()
+        check_against_oracle(w, filters, out, range(w.num_filters))
+    ga.close()
+    gb.close()
