@@ -181,6 +181,57 @@ def _kernel_summary(stats_csv: str, out_md: str, title: str, command: str) -> in
     return 0
 
 
+def _counter_summary(out_md: str, csvs, title: str, commands) -> int:
+    """Markdown table of hardware counters per library kernel from one or more
+    rocprofv3 --pmc runs (counter_collection.csv): each counter's mean per
+    dispatch, and the derived L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)),
+    share of 32-byte memory read requests, and atomics per dispatch."""
+    import collections
+    import csv
+
+    per = collections.OrderedDict()  # kernel -> counter -> [sum, dispatches]
+    for path in csvs:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if "sbbf" not in r["Kernel_Name"]:
+                    continue
+                k = _short_kernel(r["Kernel_Name"])
+                acc = per.setdefault(k, collections.OrderedDict()).setdefault(r["Counter_Name"], [0.0, 0])
+                acc[0] += float(r["Counter_Value"])
+                acc[1] += 1
+    names = []
+    for cs in per.values():
+        for c in cs:
+            if c not in names:
+                names.append(c)
+
+    def mean(cs, c):
+        return cs[c][0] / cs[c][1] if c in cs and cs[c][1] else None
+
+    lines = [f"# {title}", "", "Commands (from the repository root, on one MI355X; one counter set per run):", "",
+             "```"] + list(commands) + ["```", "",
+             "Source: rocprofv3 `counter_collection.csv` of those runs; library kernels only. Counters are means per "
+             "dispatch over every dispatch of the kernel in the run. L2 hit = TCC_HIT / (TCC_HIT + TCC_MISS); "
+             "32B rd = TCC_EA0_RDREQ_32B / TCC_EA0_RDREQ (share of the L2's memory read requests that are 32 "
+             "bytes); a dash: not counted for that kernel.", "",
+             "| kernel | " + " | ".join(names) + " | L2 hit | 32B rd |",
+             "|---|" + "---:|" * (len(names) + 2)]
+    for k, cs in per.items():
+        cells = []
+        for c in names:
+            v = mean(cs, c)
+            cells.append("-" if v is None else f"{v:.4g}")
+        hit, miss = mean(cs, "TCC_HIT"), mean(cs, "TCC_MISS")
+        rd, rd32 = mean(cs, "TCC_EA0_RDREQ"), mean(cs, "TCC_EA0_RDREQ_32B")
+        hr = f"{hit / (hit + miss):.3f}" if hit is not None and miss is not None and hit + miss > 0 else "-"
+        r32 = f"{rd32 / rd:.3f}" if rd and rd32 is not None else "-"
+        lines.append(f"| `{k}` | " + " | ".join(cells) + f" | {hr} | {r32} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
 def _ensure_built():
     lib = os.path.join(ROOT, "paper_2101_01719_amd", "libsbbf.so")
     if not os.path.exists(lib):
@@ -574,8 +625,11 @@ def main(argv=None):
     ap.add_argument("--traffic-commands", nargs="*", default=[], help="the commands of those runs, recorded")
     ap.add_argument("--kernel-summary", nargs=2, metavar=("STATS_CSV", "OUT_MD"),
                     help="write a markdown kernel-time summary of a rocprofv3 kernel_stats.csv, then exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="PATH",
+                    help="OUT_MD then one or more rocprofv3 --pmc counter_collection.csv files: write a markdown "
+                         "table of counters per library kernel (with --summary-command once per run), then exit")
     ap.add_argument("--summary-title", default="Kernel time summary")
-    ap.add_argument("--summary-command", default="")
+    ap.add_argument("--summary-command", action="append", default=[])
     ap.add_argument("--strategy-sweep", metavar="OUT_MD",
                     help="time the gather and partitioned lookups and the atomic and partitioned inserts over filter "
                          "sizes of 1 to 64 MiB and batches of 1M to 64M keys, write a markdown table, then exit")
@@ -587,7 +641,12 @@ def main(argv=None):
     if a.strategy_sweep:
         return _strategy_sweep(a.strategy_sweep)
     if a.kernel_summary:
-        return _kernel_summary(a.kernel_summary[0], a.kernel_summary[1], a.summary_title, a.summary_command)
+        return _kernel_summary(a.kernel_summary[0], a.kernel_summary[1], a.summary_title,
+                               a.summary_command[0] if a.summary_command else "")
+    if a.counter_summary:
+        if len(a.counter_summary) < 2:
+            ap.error("--counter-summary needs OUT_MD and at least one CSV")
+        return _counter_summary(a.counter_summary[0], a.counter_summary[1:], a.summary_title, a.summary_command)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only. Independent filters would shard across GPUs as whole "
