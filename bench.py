@@ -499,7 +499,7 @@ def _ceilings(P, torch, w, look_launch, ins_launch, reps=5):
     return res
 
 
-def _grouped(P, torch, autotune=True, reps=5):
+def _grouped(P, torch, autotune=True, reps=5, cfg=None):
     """The grouped workload: 2,048 filters with key counts log-uniform in
     [1e3, 1e6], 10.5 bits per key, four lookups per inserted key at a 25 %
     member rate; one graph launch against one plain launch per filter per
@@ -509,9 +509,9 @@ def _grouped(P, torch, autotune=True, reps=5):
 
     w = grouped_workload(num_filters=2048, backend="torch", device="cuda")
     filters = [P.Filter(int(b)) for b in w.blocks]
-    g = P.Group(filters, w.ins_off, w.look_off)
+    g = P.Group(filters, w.ins_off, w.look_off, cfg)
     out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
-    tuned = g.autotune(w.inserts, w.lookups, out, reps=3) if autotune else g.config()
+    tuned = g.autotune(w.inserts, w.lookups, out, reps=3) if autotune and cfg is None else g.config()
 
     def timed(fn, n):
         ts = []
@@ -615,6 +615,8 @@ def main(argv=None):
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-select", action="store_true", help="skip the select, union, key-hashing and block-variant measurements")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--grouped-config", metavar="JSON",
+                    help="grouped plan settings over the defaults, e.g. '{\"xcd_queues\": 0}' (no autotuning)")
     ap.add_argument("--serving-requests", type=int, default=50_000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the steps, copy this many MiB once with a plain device copy (a kernel of known "
@@ -789,7 +791,7 @@ def main(argv=None):
     del w, out, f
     torch.cuda.empty_cache()
     if not a.no_grouped:
-        result["grouped"] = _grouped(P, torch)
+        result["grouped"] = _grouped(P, torch, cfg=json.loads(a.grouped_config) if a.grouped_config else None)
     if not a.no_serving:
         result["serving"] = _serving(P, torch, a.serving_requests)
     print(json.dumps(result), flush=True)
