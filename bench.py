@@ -578,6 +578,18 @@ def _serving(P, torch, num_requests=50_000):
         return st
 
     cap = run(0)
+    # Baseline with the same results: one plain call per request, in order.
+    ref_out = d_out.clone()
+    d_out.zero_()
+    s = P.sbbf_server_create(cfg)
+    for b in L.blocks.tolist():
+        P.sbbf_server_add_filter(s, b)
+    torch.cuda.synchronize()
+    per_request_s = P.sbbf_server_replay_per_request(s, P.serving_requests(L, d_payload, d_out))
+    P.sbbf_server_destroy(s)
+    identical = bool(torch.equal(d_out, ref_out))
+    del ref_out
+    keys = int(L.key_off[-1])
     mean_keys = float(L.n.mean())
     points = []
     for frac in (0.25, 0.5, 0.9):
@@ -591,6 +603,9 @@ def _serving(P, torch, num_requests=50_000):
         "workload": f"4,096 filters ({int(L.blocks.sum()) * 32 / 2**20:.1f} MiB resident), {num_requests:,} requests "
                     f"({int(L.key_off[-1]):,} keys), 20 % inserts, sizes log-uniform 1..65,536",
         "capacity_gkeys_per_s": cap["gkeys_per_s"],
+        "per_request_gkeys_per_s": keys / per_request_s / 1e9,
+        "speedup_vs_per_request": cap["gkeys_per_s"] / (keys / per_request_s / 1e9),
+        "identical_outputs_vs_per_request": identical,
         "p50_us": half["p50_us"],
         "p99_us": half["p99_us"],
         "at_load": points,

@@ -429,6 +429,17 @@ sbbf_status sbbf_server_request_times(const sbbf_server *s, uint64_t req_id, uin
  * log[0] (ids are consecutive). */
 sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t count, int realtime,
                                uint64_t *first_id);
+/* Baseline with the same results as sbbf_server_replay: waits for queued work,
+ * then issues every request of the log in order as one plain call on the
+ * server's stream (sbbf_insert_batch_ex with 32-bit atomics, or
+ * sbbf_lookup_batch_ex with the gather) against the resident filters, with no
+ * batching and no arrival times; waits for the stream and returns the wall
+ * time from the first call to the end in *seconds. Filter ids must be
+ * resident and ops 0 or 1 (else SBBF_EINVAL, nothing issued). Each request
+ * sees exactly the requests before it, so the filters and lookup outputs equal
+ * the serving loop's on the same log. */
+sbbf_status sbbf_server_replay_per_request(sbbf_server *s, const sbbf_request *log, uint64_t count,
+                                           double *seconds);
 sbbf_status sbbf_server_stats(const sbbf_server *s, sbbf_serving_stats *out);
 /* Checkpoint / restore one filter's bytes (waits for all queued work first). */
 sbbf_status sbbf_server_snapshot(sbbf_server *s, uint32_t filter_id, void *host_dst);

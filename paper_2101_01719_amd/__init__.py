@@ -525,6 +525,19 @@ def sbbf_server_replay(s: int, requests, realtime: bool = True) -> int:
     return first.value
 
 
+def sbbf_server_replay_per_request(s: int, requests) -> float:
+    """The same log as one plain call per request, in order, with no batching
+    (the baseline); returns its wall time in seconds."""
+    import numpy as np
+
+    req = np.ascontiguousarray(requests)
+    if req.dtype != np.dtype(REQUEST_DTYPE):
+        raise TypeError("requests must use REQUEST_DTYPE")
+    sec = ctypes.c_double()
+    _check(_L().sbbf_server_replay_per_request(s, ctypes.c_void_p(req.ctypes.data), req.size, ctypes.byref(sec)))
+    return sec.value
+
+
 def sbbf_server_stats(s: int) -> dict:
     st = sbbf_serving_stats()
     _check(_L().sbbf_server_stats(s, ctypes.byref(st)))

@@ -153,6 +153,7 @@ SIGNATURES = {
     "sbbf_server_poll": (c_int, [c_vp, ctypes.POINTER(c_u64), c_u32, ctypes.POINTER(c_u32)]),
     "sbbf_server_request_times": (c_int, [c_vp, c_u64, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64)]),
     "sbbf_server_replay": (c_int, [c_vp, c_vp, c_u64, c_int, ctypes.POINTER(c_u64)]),
+    "sbbf_server_replay_per_request": (c_int, [c_vp, c_vp, c_u64, ctypes.POINTER(ctypes.c_double)]),
     "sbbf_server_stats": (c_int, [c_vp, ctypes.POINTER(sbbf_serving_stats)]),
     "sbbf_server_snapshot": (c_int, [c_vp, c_u32, c_vp]),
     "sbbf_server_restore": (c_int, [c_vp, c_u32, c_vp]),

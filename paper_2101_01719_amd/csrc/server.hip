@@ -671,6 +671,48 @@ sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t
   return SBBF_OK;
 }
 
+sbbf_status sbbf_server_replay_per_request(sbbf_server *s, const sbbf_request *log, uint64_t count,
+                                           double *seconds) {
+  if (!s || (count && !log)) return set_error(SBBF_EINVAL, "server or log is NULL");
+  for (uint64_t i = 0; i < count; ++i) {
+    const sbbf_request &q = log[i];
+    if (q.filter_id >= s->filters.size() || !s->filters[q.filter_id].live)
+      return set_error(SBBF_EINVAL, "unknown filter id in the log");
+    if (q.op > 1) return set_error(SBBF_EINVAL, "op must be 0 (insert) or 1 (lookup)");
+  }
+  sbbf_status st = sbbf_server_drain(s);
+  if (st != SBBF_OK) return st;
+  // Borrowed handles on the resident filters' words (nothing is copied).
+  std::vector<sbbf_filter *> h(s->filters.size(), nullptr);
+  auto release = [&h]() {
+    for (auto *f : h)
+      if (f) (void)sbbf_destroy(f);
+  };
+  for (size_t f = 0; f < s->filters.size(); ++f) {
+    if (!s->filters[f].live) continue;
+    if ((st = sbbf_create_wrapped(s->filters[f].words, s->filters[f].num_blocks, &h[f])) != SBBF_OK) {
+      release();
+      return st;
+    }
+  }
+  sbbf_launch ins_cfg{0, 0, 0, SBBF_INSERT_ATOMIC32, 0};
+  sbbf_launch look_cfg{0, 0, 0, SBBF_LOOKUP_GATHER, 0};
+  const uint64_t t0 = now_ns();
+  for (uint64_t i = 0; i < count && st == SBBF_OK; ++i) {
+    const sbbf_request &q = log[i];
+    sbbf_filter *f = h[q.filter_id];
+    st = q.op == 0 ? sbbf_insert_batch_ex(f, q.d_hashes, q.n, &ins_cfg, s->stream)
+                   : sbbf_lookup_batch_ex(f, q.d_hashes, q.n, q.d_out, nullptr, &look_cfg, s->stream);
+  }
+  const hipError_t e = hipStreamSynchronize(s->stream);
+  const uint64_t t1 = now_ns();
+  release();
+  if (st != SBBF_OK) return st;
+  if (e != hipSuccess) return hip_error(e, "replay per request");
+  if (seconds) *seconds = (double)(t1 - t0) / 1e9;
+  return SBBF_OK;
+}
+
 sbbf_status sbbf_server_stats(const sbbf_server *s, sbbf_serving_stats *out) {
   if (!s || !out) return set_error(SBBF_EINVAL, "server or out is NULL");
   memset(out, 0, sizeof(*out));

@@ -199,3 +199,25 @@ def test_one_large_filter_spreads(P):
     P.sbbf_server_replay(s, P.serving_requests(L, d_payload, d_out), realtime=False)
     check(P, s, L, d_out, ref)
     P.sbbf_server_destroy(s)
+
+
+def test_per_request_baseline_equals_oracle(P, small_log, small_ref):
+    """The baseline that issues every request of the log as one plain call,
+    in order, ends with the same filters and lookup bytes as the oracle's
+    replay (and so as the serving loop's); an unknown filter id is refused
+    before anything is issued."""
+    L = small_log
+    s = make_server(P, L)
+    d_payload, d_out = staged(L)
+    req = P.serving_requests(L, d_payload, d_out)
+    sec = P.sbbf_server_replay_per_request(s, req)
+    assert sec > 0
+    check(P, s, L, d_out, small_ref)
+    bad = req[:3].copy()
+    bad["filter_id"][2] = L.num_filters + 5
+    before = snapshot_all(P, s, L)
+    with pytest.raises(P.SbbfError):
+        P.sbbf_server_replay_per_request(s, bad)
+    for f, words in enumerate(snapshot_all(P, s, L)):
+        assert np.array_equal(words, before[f]), f
+    P.sbbf_server_destroy(s)
