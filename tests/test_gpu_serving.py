@@ -221,3 +221,38 @@ def test_per_request_baseline_equals_oracle(P, small_log, small_ref):
     for f, words in enumerate(snapshot_all(P, s, L)):
         assert np.array_equal(words, before[f]), f
     P.sbbf_server_destroy(s)
+
+
+def test_request_larger_than_a_step_grows_the_slot(P):
+    """Steps of at most one request and 64 keys (tile tables of a few hundred
+    64-key tiles): requests of 65,536 keys run alone in steps whose tile table
+    has to grow, between small requests on the same filters; results equal
+    the oracle's replay."""
+    from types import SimpleNamespace
+
+    from synth import splitmix64_stream
+
+    blocks = np.array([3000, 41_000, 17], dtype=np.uint64)
+    # (filter, op, n): big inserts and lookups around small ones
+    spec = [(1, 0, 65_536), (0, 0, 100), (1, 1, 65_536), (0, 1, 3), (2, 0, 65_536), (1, 0, 5), (2, 1, 65_536),
+            (1, 1, 70_000), (0, 1, 65_536)]
+    filt = np.array([f for f, _, _ in spec], dtype=np.uint32)
+    op = np.array([o for _, o, _ in spec], dtype=np.uint32)
+    n = np.array([k for _, _, k in spec], dtype=np.uint64)
+    key_off = np.concatenate([[0], np.cumsum(n)]).astype(np.uint64)
+    payload = splitmix64_stream(31, int(key_off[-1]))
+    # lookups ask for some earlier inserted hashes too
+    payload[int(key_off[2]):int(key_off[2]) + 1000] = payload[:1000]
+    out_n = np.where(op == 1, n, 0)
+    out_off = np.concatenate([[0], np.cumsum(out_n)]).astype(np.uint64)
+    L = SimpleNamespace(num_requests=len(spec), num_filters=len(blocks), blocks=blocks, filter=filt, op=op, n=n,
+                        key_off=key_off, out_off=out_off, payload=payload,
+                        arrival_ns=np.arange(len(spec), dtype=np.uint64) * 1000)
+    ref = oracle.replay_requests(L.blocks, L.filter, L.op, L.key_off, L.payload, L.out_off)
+    s = make_server(P, L, max_step_keys=64, max_step_requests=1, tile_keys=64)
+    d_payload, d_out = staged(L)
+    P.sbbf_server_replay(s, P.serving_requests(L, d_payload, d_out), realtime=False)
+    st = P.sbbf_server_stats(s)
+    assert st["requests_done"] == L.num_requests and st["steps"] == L.num_requests
+    check(P, s, L, d_out, ref)
+    P.sbbf_server_destroy(s)
