@@ -84,6 +84,10 @@ def _launch(launch):
     if isinstance(launch, sbbf_launch):
         return ctypes.byref(launch)
     if isinstance(launch, dict):
+        names = {name for name, _ in sbbf_launch._fields_}
+        unknown = sorted(set(launch) - names)
+        if unknown:
+            raise ValueError(f"unknown launch settings {unknown}; known: {sorted(names)}")
         return ctypes.byref(sbbf_launch(**launch))
     raise TypeError("launch must be an sbbf_launch or a dict of its fields")
 
@@ -362,7 +366,10 @@ def _cfg_struct(cfg):
     if isinstance(cfg, sbbf_grouped_config):
         return ctypes.byref(cfg)
     base = sbbf_grouped_default_config()
+    names = {name for name, _ in sbbf_grouped_config._fields_}
     for k, v in dict(cfg).items():
+        if k not in names:
+            raise ValueError(f"unknown grouped setting {k!r}; known: {sorted(names)}")
         setattr(base, k, v)
     return ctypes.byref(base)
 
@@ -451,7 +458,10 @@ def sbbf_server_default_config() -> sbbf_server_config:
 
 def sbbf_server_create(cfg=None) -> int:
     c = sbbf_server_default_config()
+    names = {name for name, _ in sbbf_server_config._fields_}
     for k, v in dict(cfg or {}).items():
+        if k not in names:
+            raise ValueError(f"unknown server setting {k!r}; known: {sorted(names)}")
         setattr(c, k, v)
     h = ctypes.c_void_p()
     _check(_L().sbbf_server_create(ctypes.byref(c), ctypes.byref(h)))

@@ -100,3 +100,13 @@ def test_missing_library_fails_loudly(tmp_path):
     ) % (ROOT, str(tmp_path / "nope.so"))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert "IMPORT_ERROR" in r.stdout, r.stdout + r.stderr
+
+
+def test_binding_rejects_unknown_settings():
+    """A misspelt setting in a launch, grouped or server dict is an error in
+    the binding (ctypes structures would otherwise take it silently)."""
+    import paper_2101_01719_amd as P
+
+    with pytest.raises(ValueError, match="unknown launch settings"):
+        P._launch(dict(strategy=1, unrol=4))
+    assert P._launch(dict(strategy=1, unroll=4)) is not None
