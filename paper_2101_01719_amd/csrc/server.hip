@@ -286,6 +286,9 @@ struct sbbf_server {
   uint64_t steps = 0, keys_done = 0, req_done = 0;
   uint64_t first_arrival = UINT64_MAX, last_done = 0;
   uint64_t step_tiles_max = 0;
+  // step assembly scratch, reused from step to step
+  std::vector<sbbf::STile> step_ins;
+  std::vector<sbbf::STile> step_lq[sbbf::kServeXcds];
 };
 
 namespace sbbf {
@@ -348,8 +351,10 @@ sbbf_status server_harvest(sbbf_server *s, bool block) {
 sbbf_status server_launch_step(sbbf_server *s, Slot &sl, uint64_t *taken) {
   *taken = 0;
   const uint32_t T = s->cfg.tile_keys;
-  std::vector<STile> ins;
-  std::vector<STile> lq[kServeXcds];  // lookup tiles per XCD queue
+  std::vector<STile> &ins = s->step_ins;
+  std::vector<STile> *lq = s->step_lq;  // lookup tiles per XCD queue
+  ins.clear();
+  for (uint32_t k = 0; k < kServeXcds; ++k) lq[k].clear();
   uint64_t lq_keys[kServeXcds] = {};
   uint64_t keys = 0;
   uint32_t nreq = 0;
@@ -399,12 +404,8 @@ sbbf_status server_launch_step(sbbf_server *s, Slot &sl, uint64_t *taken) {
   // padded with empty tiles (count 0: the workgroup does nothing).
   size_t qmax = 0;
   for (uint32_t k = 0; k < kServeXcds; ++k) qmax = std::max(qmax, lq[k].size());
-  std::vector<STile> look;
-  look.reserve(qmax * kServeXcds);
-  for (size_t i = 0; i < qmax; ++i)
-    for (uint32_t k = 0; k < kServeXcds; ++k)
-      look.push_back(i < lq[k].size() ? lq[k][i] : STile{nullptr, nullptr, nullptr, 1u, 0u});
-  const size_t nt = ins.size() + look.size();
+  const size_t nlook = qmax * kServeXcds;
+  const size_t nt = ins.size() + nlook;
   if (nt > sl.cap) {  // one request larger than the step budget: grow this slot's buffers (the slot is idle)
     (void)hipHostFree(sl.host);
     sl.host = nullptr;
@@ -416,14 +417,17 @@ sbbf_status server_launch_step(sbbf_server *s, Slot &sl, uint64_t *taken) {
   // The slot is idle (its previous step has completed), so its table may be
   // rewritten; the kernels launched below read it in place.
   memcpy(sl.host, ins.data(), ins.size() * sizeof(STile));
-  memcpy(sl.host + ins.size(), look.data(), look.size() * sizeof(STile));
+  STile *dst = sl.host + ins.size();
+  for (size_t i = 0; i < qmax; ++i)
+    for (uint32_t k = 0; k < kServeXcds; ++k)
+      *dst++ = i < lq[k].size() ? lq[k][i] : STile{nullptr, nullptr, nullptr, 1u, 0u};
   hipError_t e = hipSuccess;
   if (!ins.empty()) {
     hipLaunchKernelGGL(serve_insert_kernel, dim3((uint32_t)ins.size()), dim3(kServeThreads), 0, s->stream, sl.dev);
     if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "server insert");
   }
-  if (!look.empty()) {
-    hipLaunchKernelGGL(serve_lookup_kernel, dim3((uint32_t)look.size()), dim3(kServeThreads), 0, s->stream,
+  if (nlook > 0) {
+    hipLaunchKernelGGL(serve_lookup_kernel, dim3((uint32_t)nlook), dim3(kServeThreads), 0, s->stream,
                        sl.dev + ins.size());
     if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "server lookup");
   }
