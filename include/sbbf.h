@@ -425,8 +425,9 @@ sbbf_status sbbf_server_poll(sbbf_server *s, uint64_t *done_ids, uint32_t cap, u
 sbbf_status sbbf_server_request_times(const sbbf_server *s, uint64_t req_id, uint64_t *arrival_ns, uint64_t *done_ns);
 /* Drive a request log (sorted by arrival_ns) through the loop from this thread:
  * with realtime != 0 each request is queued when its arrival time is reached,
- * else all at once. Returns when all have completed; *first_id is the id of
- * log[0] (ids are consecutive). */
+ * else all are due at once (queued 2,048 per round of the loop, so that steps
+ * start while the rest are queued; arrival time = when queued). Returns when
+ * all have completed; *first_id is the id of log[0] (ids are consecutive). */
 sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t count, int realtime,
                                uint64_t *first_id);
 /* Baseline with the same results as sbbf_server_replay: waits for queued work,

@@ -41,6 +41,8 @@ constexpr uint32_t kServeLdsBlocks = 1024;
 // XCD, so a filter's blocks are cached in one L2 instead of eight.
 constexpr uint32_t kServeXcds = 8;
 constexpr uint64_t kServeSlack = 65536;
+// Requests a replay without arrival times admits per round of its loop.
+constexpr uint64_t kReplayAdmitBatch = 2048;
 
 struct STile {
   const uint64_t *keys;
@@ -653,8 +655,11 @@ sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t
   uint64_t next = 0;
   while (next < count || s->pending > 0 || s->inflight > 0) {
     const uint64_t t = now_ns();
-    // admit every request whose arrival time has passed (all at once when not realtime)
-    while (next < count && (!realtime || t0 + log[next].arrival_ns <= t)) {
+    // Admit every request whose arrival time has passed; when not realtime
+    // (all requests arrive at once), at most kReplayAdmitBatch per round, so
+    // that the first steps run on the device while the rest are admitted.
+    const uint64_t admit_end = realtime ? count : std::min<uint64_t>(count, next + kReplayAdmitBatch);
+    while (next < admit_end && (!realtime || t0 + log[next].arrival_ns <= t)) {
       const sbbf_request &q = log[next];
       sbbf_status st = server_enqueue(s, q.filter_id, q.op, q.d_hashes, q.n, q.d_out,
                                       realtime ? t0 + q.arrival_ns : t, nullptr);
