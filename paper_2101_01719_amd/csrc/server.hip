@@ -652,6 +652,9 @@ sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t
     if (log[i].arrival_ns < log[i - 1].arrival_ns) return set_error(SBBF_EINVAL, "log must be sorted by arrival");
   const uint64_t t0 = now_ns();
   if (first_id) *first_id = s->reqs.size();
+  // room for the whole log up front (no reallocation while admitting)
+  s->reqs.reserve(s->reqs.size() + count);
+  s->completed.reserve(s->completed.size() + count);
   uint64_t next = 0;
   while (next < count || s->pending > 0 || s->inflight > 0) {
     const uint64_t t = now_ns();
