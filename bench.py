@@ -549,7 +549,7 @@ def _grouped(P, torch, autotune=True, reps=5, cfg=None):
     return res
 
 
-def _serving(P, torch, num_requests=50_000):
+def _serving(P, torch, num_requests=50_000, capacity_only=False):
     """The serving workload: 4,096 resident filters sized like the grouped
     workload (seed 5), Poisson arrivals, 20 % insert / 80 % lookup requests of
     log-uniform size 1..65,536, uniform filter choice; capacity with every
@@ -580,6 +580,8 @@ def _serving(P, torch, num_requests=50_000):
 
     run(0)  # warm-up (first use of the arena, the pinned tile tables and the kernels), not reported
     cap = run(0)
+    if capacity_only:
+        return {"capacity_gkeys_per_s": cap["gkeys_per_s"], "steps": cap["steps"], "config": cfg}
     # Baseline with the same results: one plain call per request, in order.
     ref_out = d_out.clone()
     d_out.zero_()
@@ -635,6 +637,8 @@ def main(argv=None):
     ap.add_argument("--grouped-config", metavar="JSON",
                     help="grouped plan settings over the defaults, e.g. '{\"xcd_queues\": 0}' (no autotuning)")
     ap.add_argument("--serving-requests", type=int, default=50_000)
+    ap.add_argument("--serving-capacity-only", action="store_true",
+                    help="serving leg: the capacity replays only (no baseline, no load levels), for profiling")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the steps, copy this many MiB once with a plain device copy (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -810,7 +814,7 @@ def main(argv=None):
     if not a.no_grouped:
         result["grouped"] = _grouped(P, torch, cfg=json.loads(a.grouped_config) if a.grouped_config else None)
     if not a.no_serving:
-        result["serving"] = _serving(P, torch, a.serving_requests)
+        result["serving"] = _serving(P, torch, a.serving_requests, capacity_only=a.serving_capacity_only)
     print(json.dumps(result), flush=True)
     return 0
 
