@@ -332,7 +332,8 @@ typedef struct sbbf_grouped_config {
 /* Defaults for the current device. */
 sbbf_status sbbf_grouped_default_config(sbbf_grouped_config *out);
 /* A group over filters[0 .. num_filters) (handles are borrowed; they must outlive
- * the group). */
+ * the group). Their memory must not overlap (a filter appears once): else
+ * SBBF_EINVAL. */
 sbbf_status sbbf_grouped_create(sbbf_filter *const *filters, uint32_t num_filters, sbbf_group **out);
 sbbf_status sbbf_grouped_destroy(sbbf_group *g);
 /* Build the plan from host offsets (num_filters + 1 entries each, non-decreasing;

@@ -1171,6 +1171,20 @@ sbbf_status sbbf_grouped_create(sbbf_filter *const *filters, uint32_t num_filter
       return set_error(SBBF_EUNSUPPORTED, "filter " + std::to_string(f) + " is a block variant; groups take "
                                           "eight-word blocks only");
   }
+  // The filters' memory must not overlap: a slice of a filter is loaded,
+  // updated and stored back whole by one workgroup, so two entries over the
+  // same words would lose each other's inserts.
+  {
+    std::vector<std::pair<uintptr_t, uintptr_t>> span(num_filters);
+    for (uint32_t f = 0; f < num_filters; ++f) {
+      const uintptr_t b = reinterpret_cast<uintptr_t>(filters[f]->words);
+      span[f] = {b, b + (uintptr_t)filters[f]->num_blocks * 32u};
+    }
+    std::sort(span.begin(), span.end());
+    for (uint32_t f = 1; f < num_filters; ++f)
+      if (span[f].first < span[f - 1].second)
+        return set_error(SBBF_EINVAL, "filters of a group must not share memory (each filter appears once)");
+  }
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");

@@ -301,3 +301,24 @@ def test_two_groups_planned_in_turn(P):
         check_against_oracle(w, filters, out, range(w.num_filters))
     ga.close()
     gb.close()
+
+
+def test_group_rejects_shared_memory(P):
+    """A filter may appear once in a group, and two handles over overlapping
+    words are refused: a slice is stored back whole by one workgroup."""
+    a, b = P.Filter(300), P.Filter(20)
+    off = np.zeros(3, dtype=np.uint64)
+    with pytest.raises(P.SbbfError) as e:
+        P.Group([a, b, a], np.zeros(4, dtype=np.uint64), np.zeros(4, dtype=np.uint64))
+    assert e.value.status == P.SBBF_EINVAL
+    words = torch.zeros(8 * 100, dtype=torch.int32, device="cuda")
+    h1 = P.sbbf_create_wrapped(words, 60)
+    h2 = P.sbbf_create_wrapped(words[8 * 50:], 50)  # blocks 50..99 overlap blocks 50..59 of h1
+    with pytest.raises(P.SbbfError):
+        P.sbbf_grouped_create([h1, h2])
+    g = P.Group([a, b], off, off)  # distinct filters are fine
+    g.close()
+    P.sbbf_destroy(h1)
+    P.sbbf_destroy(h2)
+    a.close()
+    b.close()
