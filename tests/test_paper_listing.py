@@ -1,7 +1,7 @@
 """Third implementation: the paper's own appendix code, compiled at test time.
 
-When the paper's LaTeX source is present (it is not on GPU machines) and the
-host has AVX2, this test extracts the C code of the appendix figure from the
+When the environment variable SBBF_PAPER_SOURCE names a copy of the paper's
+LaTeX source (never available on GPU machines) and the host has AVX2, this test extracts the C code of the appendix figure from the
 source at run time, compiles it unchanged together with a small driver written
 here, and compares its filter bytes, lookups and worked examples with the
 oracle. Nothing of the listing is stored in this repository. Skipped otherwise.
@@ -18,7 +18,8 @@ import oracle
 from conftest import read_golden
 from synth import plain_workload, splitmix64_stream
 
-PAPER = "/root/reference/PAPER.md"
+# Path of the paper's LaTeX source, e.g. SBBF_PAPER_SOURCE=/path/to/paper.tex.
+PAPER = os.environ.get("SBBF_PAPER_SOURCE", "")
 
 DRIVER = r"""
 #include <stdio.h>
@@ -65,8 +66,8 @@ def _has_avx2():
 
 @pytest.fixture(scope="module")
 def paper_binary(tmp_path_factory):
-    if not os.path.exists(PAPER):
-        pytest.skip("the paper's source is not available on this machine")
+    if not PAPER or not os.path.exists(PAPER):
+        pytest.skip("SBBF_PAPER_SOURCE does not name the paper's source on this machine")
     if not _has_avx2():
         pytest.skip("host has no AVX2")
     with open(PAPER) as f:
