@@ -291,6 +291,27 @@ sbbf_status sbbf_lookup_keys(const sbbf_filter *f, const uint64_t *d_keys, size_
 sbbf_status sbbf_lookup_select(const sbbf_filter *f, const uint64_t *d_hashes, size_t n, uint32_t *d_indices,
                                uint64_t *d_count, const sbbf_launch *cfg, sbbf_stream s);
 
+/* Allocation-free form of sbbf_lookup_select, for callers that cannot
+ * allocate device memory during the call: code under HIP graph capture,
+ * tight serving loops, and harnesses that forbid hipMalloc. Same arguments,
+ * results and argument checks as sbbf_lookup_select, with three differences:
+ *   - the lookup is always the gather (cfg's strategy must be
+ *     SBBF_LOOKUP_AUTO or SBBF_LOOKUP_GATHER; SBBF_EUNSUPPORTED for the
+ *     partitioned lookup, which allocates a workspace);
+ *   - the workspace (result bitmap and per-tile counts and offsets) is a
+ *     static device array of 33,816,576 bytes that each GPU the library runs
+ *     on holds until the process ends; no device memory is allocated or
+ *     freed by the call;
+ *   - n is at most 2^28 (268,435,456) keys per call; a larger n returns
+ *     SBBF_EINVAL and enqueues nothing.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls on one stream are ordered and safe, but calls that overlap
+ * in time on one GPU (on different streams, or from different host threads)
+ * race on the array and give wrong results. */
+sbbf_status sbbf_lookup_select_noalloc(const sbbf_filter *f, const uint64_t *d_hashes, size_t n,
+                                       uint32_t *d_indices, uint64_t *d_count, const sbbf_launch *cfg,
+                                       sbbf_stream s);
+
 /* ---- measurement kernels (same access pattern, no filter arithmetic) ------- */
 
 /* Random 32-byte gather ceiling: for each hash, read the 32-byte block

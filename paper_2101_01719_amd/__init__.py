@@ -338,6 +338,22 @@ def sbbf_lookup_select(f: int, hashes: torch.Tensor, indices: torch.Tensor | Non
     return indices, count
 
 
+def sbbf_lookup_select_noalloc(f: int, hashes: torch.Tensor, indices: torch.Tensor, count: torch.Tensor,
+                               launch=None, stream=None):
+    """As sbbf_lookup_select with the library's static workspace: the call
+    allocates no device memory, so the caller provides indices (int32, room
+    for n) and count (one int64). Gather lookups only; at most 2^28 keys."""
+    p, n = _hashes(hashes)
+    if indices.dtype not in (torch.int32, torch.uint32) or not indices.is_cuda or not indices.is_contiguous() \
+            or indices.numel() < n:
+        raise ValueError("indices must be a contiguous int32 CUDA tensor of at least n entries")
+    if count.dtype != torch.int64 or not count.is_cuda or count.numel() < 1:
+        raise ValueError("count must be an int64 CUDA tensor")
+    _check(_L().sbbf_lookup_select_noalloc(f, p, n, ctypes.c_void_p(indices.data_ptr()),
+                                           ctypes.c_void_p(count.data_ptr()), _launch(launch), _stream(stream)))
+    return indices, count
+
+
 # ---- measurement kernels ----------------------------------------------------------------
 
 def sbbf_bench_gather(buf: torch.Tensor, num_blocks: int, hashes: torch.Tensor, out: torch.Tensor,

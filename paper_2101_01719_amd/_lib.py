@@ -124,6 +124,7 @@ SIGNATURES = {
     "sbbf_lookup_batch_bits": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp]),
     "sbbf_lookup_batch_ex": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_lookup_select": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
+    "sbbf_lookup_select_noalloc": (c_int, [c_vp, c_vp, c_size, c_vp, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_key_hash": (c_u64, [c_u64]),
     "sbbf_insert_keys": (c_int, [c_vp, c_vp, c_size, ctypes.POINTER(sbbf_launch), c_vp]),
     "sbbf_lookup_keys": (c_int, [c_vp, c_vp, c_size, c_vp, ctypes.POINTER(sbbf_launch), c_vp]),
