@@ -276,3 +276,27 @@ def grouped_workload(num_filters: int = 2048, log10_min: float = 3.0, log10_max:
         del both, src
     return GroupedWorkload(num_filters=F, n=n, blocks=blocks, ins_off=ins_off, look_off=look_off,
                            inserts=inserts, lookups=lookups, is_member=is_member)
+
+
+def grouped_filter_inputs(n: np.ndarray, f: int, nonmembers_per_member: int = 3):
+    """Filter ``f``'s inserts and lookups of the grouped workload (numpy),
+    equal to ``grouped_workload``'s slices ``inserts[ins_off[f]:ins_off[f+1]]``
+    and ``lookups[look_off[f]:look_off[f+1]]`` for the same per-filter counts
+    ``n``, built from that filter's stream ranges alone.
+
+    The workload's shuffle sorts by (filter << 40) | (G(3)[i] >> 24) over the
+    whole lookup array; inside one filter's range the filter part is constant,
+    so the filter's order is the stable sort of its own G(3)[i] >> 24.
+    """
+    k = nonmembers_per_member
+    n = np.asarray(n, dtype=np.int64)
+    ins0 = int(n[:f].sum())
+    nf = int(n[f])
+    look0 = ins0 * (1 + k)
+    members = splitmix64_stream(SEED_MEMBERS, nf, start=ins0)
+    non = splitmix64_stream(SEED_NONMEMBERS, k * nf, start=k * ins0)
+    shuffle = splitmix64_stream(SEED_SHUFFLE, (1 + k) * nf, start=look0) >> np.uint64(24)
+    perm = np.argsort(shuffle, kind="stable")
+    lookups = np.concatenate([members, non])[perm]
+    is_member = perm < nf
+    return members, lookups, is_member

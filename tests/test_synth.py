@@ -132,3 +132,42 @@ def test_serving_log_stream_positions():
 
     pos = np.array([0, 1, 17, 999, 123456], dtype=np.int64)
     assert np.array_equal(_stream_at(11, pos), splitmix64_stream(11, 123457)[pos])
+
+
+def test_grouped_filter_inputs_equal_the_workload_slices():
+    from synth.workloads import grouped_filter_inputs
+
+    w = grouped_workload(num_filters=12, log10_min=2.0, log10_max=4.0)
+    for f in range(12):
+        m, look, mem = grouped_filter_inputs(w.n, f)
+        assert np.array_equal(m, w.inserts[w.ins_off[f]:w.ins_off[f + 1]])
+        assert np.array_equal(look, w.lookups[w.look_off[f]:w.look_off[f + 1]])
+        assert np.array_equal(mem, w.is_member[w.look_off[f]:w.look_off[f + 1]])
+
+
+@pytest.mark.parametrize("chunk", [3, 5000, 1 << 25])
+def test_serving_log_pieces_and_backends_agree(monkeypatch, chunk):
+    """Member draws taken a piece at a time give the same log for any piece
+    size, and the torch backend gives the numpy backend's payload bit for bit
+    (its unsigned modulo and unit doubles are exact)."""
+    torch = pytest.importorskip("torch")
+    import synth.serving as S
+
+    ref = S.serving_log(64, 3000, max_size=4096)
+    monkeypatch.setattr(S, "_DRAW_CHUNK", chunk)
+    a = S.serving_log(64, 3000, max_size=4096)
+    b = S.serving_log(64, 3000, max_size=4096, backend="torch", device="cpu")
+    for name in ("arrival_ns", "filter", "op", "n", "key_off", "out_off", "payload"):
+        assert np.array_equal(getattr(a, name), getattr(ref, name)), name
+    assert np.array_equal(b.payload.numpy().view(np.uint64), ref.payload)
+    assert isinstance(b.payload, torch.Tensor)
+
+
+def test_unsigned_modulo_of_bit_views():
+    torch = pytest.importorskip("torch")
+    from synth.serving import _umod_torch
+
+    z = splitmix64_stream(77, 20_000)
+    m = (splitmix64_stream(78, 20_000) % np.uint64((1 << 31) - 1)).astype(np.int64) + 1
+    got = _umod_torch(torch.from_numpy(z.view(np.int64)), torch.from_numpy(m)).numpy()
+    assert np.array_equal(got, (z % m.astype(np.uint64)).astype(np.int64))
