@@ -329,12 +329,23 @@ sbbf_status sbbf_bench_stream(const uint64_t *d_hashes, size_t n, uint8_t *d_out
                               sbbf_stream s);
 
 /* ---- grouped: many filters in one launch ----------------------------------- */
-/* A group holds F filters. A plan fixes, for one batch shape, how many keys each
- * filter inserts and looks up (CSR offsets: filter f inserts d_ins[ins_off[f] ..
- * ins_off[f+1]) and looks up d_look[look_off[f] .. look_off[f+1]), writing
- * d_out[look_off[f] ..]). A run performs every filter's inserts, then every
- * filter's lookups, as one HIP graph launch (three kernel nodes); results are
- * identical to one plain insert and one plain lookup per filter. */
+/* A group holds F filters. A run performs every filter's inserts, then every
+ * filter's lookups (each filter as in the appendix figure's insert and lookup
+ * routines), as one HIP graph launch of a few kernel nodes; results are
+ * identical to one plain insert and one plain lookup per filter. Key ranges are
+ * CSR offsets: filter f inserts d_ins[ins_off[f] .. ins_off[f+1]) and looks up
+ * d_look[look_off[f] .. look_off[f+1]), writing d_out[look_off[f] ..].
+ *
+ * Two kinds of plan:
+ *   - fixed shape (sbbf_grouped_plan): the offsets are given on the host once
+ *     and every sbbf_grouped_run uses them;
+ *   - capacity (sbbf_grouped_plan_capacity): the plan fixes, per filter, the
+ *     most keys one run may insert and look up; every sbbf_grouped_run_offsets
+ *     brings its own offsets in device memory, read by the kernels when the
+ *     graph runs. Changing the counts needs no host planning and no graph
+ *     rebuild (the graph is updated only when a buffer pointer changes), so a
+ *     caller whose per-filter counts change on every call rewrites the offset
+ *     buffers on the device and launches again. */
 
 typedef struct sbbf_grouped_config {
   uint32_t lookup_tile_keys;     /* keys per lookup tile, a multiple of 64 */
@@ -361,16 +372,49 @@ sbbf_status sbbf_grouped_destroy(sbbf_group *g);
  * at most 2^32 - 1 insert keys per filter). cfg NULL = defaults. Synchronous. */
 sbbf_status sbbf_grouped_plan(sbbf_group *g, const uint64_t *h_ins_offsets, const uint64_t *h_look_offsets,
                               const sbbf_grouped_config *cfg);
+/* Build a capacity plan: h_ins_cap[f] and h_look_cap[f] (num_filters entries
+ * each, host memory) are the most keys filter f inserts and looks up in one
+ * run (at most 2^32 - 1 insert keys per filter). Tiles, queues and the
+ * partitioned-key region are sized for these capacities; a run with fewer keys
+ * skips the work it does not have. cfg NULL = defaults. Synchronous. */
+sbbf_status sbbf_grouped_plan_capacity(sbbf_group *g, const uint64_t *h_ins_cap, const uint64_t *h_look_cap,
+                                       const sbbf_grouped_config *cfg);
 /* The configuration of the current plan. */
 sbbf_status sbbf_grouped_get_config(const sbbf_group *g, sbbf_grouped_config *out);
 /* Inserts, then lookups, of the planned batch as one graph launch on the stream. */
 sbbf_status sbbf_grouped_run(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
                              sbbf_stream s);
-/* The two phases as separate kernel launches (no graph). */
+/* One run under a capacity plan: d_ins_offsets and d_look_offsets are
+ * num_filters + 1 uint64 each in device memory (8-byte aligned, caller-owned),
+ * read by the kernels when the run executes, so they may be written on the
+ * stream just before it. Filter f inserts d_ins[d_ins_offsets[f] ..
+ * d_ins_offsets[f+1]) and looks up d_look[d_look_offsets[f] ..
+ * d_look_offsets[f+1]), writing d_out at the same positions. d_ins, d_look
+ * and d_out must hold the ranges the offsets name. A filter whose range is
+ * decreasing or longer than its capacity has only its first capacity keys
+ * processed (no access beyond them); the run records the lowest such filter
+ * for sbbf_grouped_check. SBBF_EINVAL on a group with a fixed-shape plan. */
+sbbf_status sbbf_grouped_run_offsets(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_ins_offsets,
+                                     const uint64_t *d_look, const uint64_t *d_look_offsets, uint8_t *d_out,
+                                     sbbf_stream s);
+/* Waits for the stream, then reports whether every run since the last check
+ * kept its key ranges within the plan's capacities: SBBF_OK and *first_bad =
+ * 0xFFFFFFFF if so, else SBBF_EINVAL, *first_bad = the lowest offending filter,
+ * and the record is cleared. first_bad may be NULL. */
+sbbf_status sbbf_grouped_check(sbbf_group *g, sbbf_stream s, uint32_t *first_bad);
+/* Host work done for the group so far: plans built (autotuning builds one per
+ * candidate), graphs instantiated, and graph updates (a run with different
+ * buffer pointers than the graph holds). Any pointer may be NULL. */
+sbbf_status sbbf_grouped_counters(const sbbf_group *g, uint64_t *plans, uint64_t *graph_builds,
+                                  uint64_t *graph_updates);
+/* The two phases as separate kernel launches (no graph). This, the per-filter
+ * baseline, the output digest and the autotuner need a fixed-shape plan
+ * (SBBF_EINVAL on a capacity plan). */
 sbbf_status sbbf_grouped_insert(sbbf_group *g, const uint64_t *d_ins, sbbf_stream s);
 sbbf_status sbbf_grouped_lookup(sbbf_group *g, const uint64_t *d_look, uint8_t *d_out, sbbf_stream s);
-/* Baseline with the same results: one plain launch per filter per operation
- * (32-bit atomic insert, gather lookup). */
+/* Baseline with the same results: one plain launch per filter per operation,
+ * each with the library's default strategy (as sbbf_insert_batch and
+ * sbbf_lookup_batch choose it for that filter and key count). */
 sbbf_status sbbf_grouped_run_per_filter(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look,
                                         uint8_t *d_out, sbbf_stream s);
 /* 64-bit digest of every filter's words (in group order) and of d_out over the

@@ -428,6 +428,47 @@ def sbbf_grouped_plan(g: int, ins_offsets, look_offsets, cfg=None) -> None:
     _check(_L().sbbf_grouped_plan(g, iop, lop, _cfg_struct(cfg)))
 
 
+def sbbf_grouped_plan_capacity(g: int, ins_capacity, look_capacity, cfg=None) -> None:
+    """Plan for at most ins_capacity[f] inserts and look_capacity[f] lookups
+    of filter f per run (host arrays of num_filters entries)."""
+    ic, icp = _offsets(ins_capacity)
+    lc, lcp = _offsets(look_capacity)
+    _check(_L().sbbf_grouped_plan_capacity(g, icp, lcp, _cfg_struct(cfg)))
+
+
+def _offsets_tensor(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype not in (torch.int64, torch.uint64) \
+            or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int64 CUDA tensor of num_filters + 1 offsets")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sbbf_grouped_run_offsets(g: int, d_ins, d_ins_offsets, d_look, d_look_offsets, d_out, stream=None) -> None:
+    """One run under a capacity plan; the offsets are int64 CUDA tensors read
+    by the kernels when the run executes (nothing is synchronised)."""
+    _check(_L().sbbf_grouped_run_offsets(g, _dptr(d_ins), _offsets_tensor(d_ins_offsets, "d_ins_offsets"),
+                                         _dptr(d_look), _offsets_tensor(d_look_offsets, "d_look_offsets"),
+                                         _dptr(d_out), _stream(stream)))
+
+
+def sbbf_grouped_check(g: int, stream=None):
+    """None when every run since the last check kept within the plan's
+    capacities, else the lowest offending filter (the record is cleared)."""
+    bad = ctypes.c_uint32(0xFFFFFFFF)
+    st = _L().sbbf_grouped_check(g, _stream(stream), ctypes.byref(bad))
+    if st == SBBF_OK:
+        return None
+    if st == SBBF_EINVAL and bad.value != 0xFFFFFFFF:
+        return int(bad.value)
+    _check(st)
+
+
+def sbbf_grouped_counters(g: int) -> dict:
+    v = [ctypes.c_uint64() for _ in range(3)]
+    _check(_L().sbbf_grouped_counters(g, *[ctypes.byref(x) for x in v]))
+    return dict(plans=v[0].value, graph_builds=v[1].value, graph_updates=v[2].value)
+
+
 def sbbf_grouped_get_config(g: int) -> dict:
     c = sbbf_grouped_config()
     _check(_L().sbbf_grouped_get_config(g, ctypes.byref(c)))
@@ -663,10 +704,33 @@ class Group:
         self.handle = sbbf_grouped_create([f.handle for f in self.filters])
         self.ins_offsets = ins_offsets
         self.look_offsets = look_offsets
-        sbbf_grouped_plan(self.handle, ins_offsets, look_offsets, cfg)
+        self.capacity = None
+        if ins_offsets is not None:
+            sbbf_grouped_plan(self.handle, ins_offsets, look_offsets, cfg)
+
+    @classmethod
+    def with_capacity(cls, filters, ins_capacity, look_capacity, cfg=None):
+        """A group planned for per-filter key capacities; its runs take device
+        offsets (run_offsets)."""
+        g = cls(filters, None, None)
+        g.capacity = (ins_capacity, look_capacity)
+        sbbf_grouped_plan_capacity(g.handle, ins_capacity, look_capacity, cfg)
+        return g
 
     def replan(self, cfg=None):
-        sbbf_grouped_plan(self.handle, self.ins_offsets, self.look_offsets, cfg)
+        if self.capacity is not None:
+            sbbf_grouped_plan_capacity(self.handle, self.capacity[0], self.capacity[1], cfg)
+        else:
+            sbbf_grouped_plan(self.handle, self.ins_offsets, self.look_offsets, cfg)
+
+    def run_offsets(self, d_ins, d_ins_offsets, d_look, d_look_offsets, d_out, stream=None):
+        sbbf_grouped_run_offsets(self.handle, d_ins, d_ins_offsets, d_look, d_look_offsets, d_out, stream)
+
+    def check(self, stream=None):
+        return sbbf_grouped_check(self.handle, stream)
+
+    def counters(self) -> dict:
+        return sbbf_grouped_counters(self.handle)
 
     def config(self) -> dict:
         return sbbf_grouped_get_config(self.handle)

@@ -135,7 +135,11 @@ SIGNATURES = {
     "sbbf_grouped_create": (c_int, [ctypes.POINTER(c_vp), c_u32, ctypes.POINTER(c_vp)]),
     "sbbf_grouped_destroy": (c_int, [c_vp]),
     "sbbf_grouped_plan": (c_int, [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64), _CFGP]),
+    "sbbf_grouped_plan_capacity": (c_int, [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64), _CFGP]),
     "sbbf_grouped_get_config": (c_int, [c_vp, _CFGP]),
+    "sbbf_grouped_run_offsets": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "sbbf_grouped_check": (c_int, [c_vp, c_vp, ctypes.POINTER(c_u32)]),
+    "sbbf_grouped_counters": (c_int, [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u64), ctypes.POINTER(c_u64)]),
     "sbbf_grouped_run": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "sbbf_grouped_insert": (c_int, [c_vp, c_vp, c_vp]),
     "sbbf_grouped_lookup": (c_int, [c_vp, c_vp, c_vp, c_vp]),

@@ -96,8 +96,7 @@ struct GPart {
 };
 
 struct GChunk {
-  uint64_t begin;  // first insert key (index into the insert hash array)
-  uint32_t count;  // keys, at most kPartChunk
+  uint32_t k;     // the chunk's place in its filter: keys k * kPartChunk .. of the call
   uint32_t part;
 };
 
@@ -113,15 +112,19 @@ struct GSlice {
 };
 
 struct GLookTile {
-  uint64_t begin;  // first lookup key (index into the lookup hash array)
-  uint32_t count;  // keys in the tile
+  uint64_t begin;  // first key, relative to the filter's first lookup key of the call
+  uint32_t count;  // keys in the tile at the filter's planned capacity (fewer when the call has fewer)
   uint32_t filter;
 };
 
 // Device-side plan: pointers into one allocation (part_keys is a second one).
 struct GPlanDev {
   const GFilter *filters;
-  const uint64_t *ins_off;   // [F + 1]
+  const uint64_t *ins_off;   // [F + 1] the call's insert key ranges (device memory)
+  const uint64_t *look_off;  // [F + 1] the call's lookup key ranges (device memory)
+  const uint64_t *ins_cap;   // [F] planned insert keys per filter (the most one call may bring)
+  const uint64_t *look_cap;  // [F] planned lookup keys per filter
+  uint32_t *bad;             // lowest filter whose call range broke its capacity, else 0xFFFFFFFF
   const GInsTile *ins_tiles; // [n_ins_tiles]
   const GLookTile *look_tiles;
   const uint32_t *queue_begin;  // [kQueues + 1] tile ranges per queue
@@ -140,6 +143,22 @@ struct GPlanDev {
   uint32_t n_slices;
   uint32_t pad;
 };
+
+// Keys of filter f in this call, from the call's offsets: off[f + 1] - off[f],
+// at most the planned capacity cap[f]. A decreasing range or a count above
+// the capacity is recorded (the lowest such filter, in *bad) and clamped, so
+// no kernel touches more keys of a filter than were planned for it.
+__device__ __forceinline__ uint64_t call_range(const uint64_t *off, const uint64_t *cap, uint32_t f, uint32_t *bad,
+                                               uint64_t *begin) {
+  const uint64_t b = off[f], e = off[f + 1], c = cap[f];
+  uint64_t n = e > b ? e - b : 0u;
+  if (e < b || n > c) {
+    __hip_atomic_fetch_min(bad, f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    n = n < c ? n : c;
+  }
+  *begin = b;
+  return n;
+}
 
 // ---- insert -----------------------------------------------------------------
 
@@ -171,13 +190,18 @@ grouped_part_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes) {
   const GChunk ch = plan.chunks[blockIdx.x];
   const GPart pt = plan.parts[ch.part];
   const uint32_t B = plan.filters[pt.filter].num_blocks;
-  const uint32_t ns = pt.nslices, n = ch.count;
+  uint64_t kb;
+  const uint64_t nf = call_range(plan.ins_off, plan.ins_cap, pt.filter, plan.bad, &kb);
+  const uint64_t first = (uint64_t)ch.k * kPartChunk;
+  if (first >= nf) return;  // this call brings the filter fewer keys (the whole workgroup leaves)
+  const uint32_t ns = pt.nslices, n = (uint32_t)min((uint64_t)kPartChunk, nf - first);
+  const uint64_t *src = hashes + kb + first;
   if (threadIdx.x < ns) hist[threadIdx.x] = 0u;
   uint64_t h[kPartPer];
 #pragma unroll
   for (uint32_t t = 0; t < kPartPer; ++t) {
     const uint32_t i = t * kInsertThreads + threadIdx.x;
-    h[t] = load_hash<0>(hashes + ch.begin + (i < n ? i : n - 1u));
+    h[t] = load_hash<0>(src + (i < n ? i : n - 1u));
   }
   __syncthreads();
   uint32_t s[kPartPer], rank[kPartPer];
@@ -247,12 +271,19 @@ grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint32
     if (t >= plan.n_ins_tiles) break;
     const GInsTile tile = plan.ins_tiles[t];
     const GFilter flt = plan.filters[tile.filter];
+    // Keys of the tile in this call: a stream tile's filter range, or a
+    // partitioned slice's runs. A tile with none leaves its slice untouched.
+    uint64_t kb = 0;
+    uint32_t n = 0, nr = 0;
+    if (tile.slice == kStreamTile)
+      n = (uint32_t)call_range(plan.ins_off, plan.ins_cap, tile.filter, plan.bad, &kb);
+    else
+      nr = plan.nruns[tile.slice];
+    if (n == 0 && nr == 0) continue;
     const uint4 *src4 = reinterpret_cast<const uint4 *>(flt.words + (uint64_t)tile.b0 * 8u);
     for (uint32_t i = threadIdx.x; i < tile.nb * 2u; i += kInsertThreads) lds4[i] = src4[i];
     __syncthreads();
     if (tile.slice == kStreamTile) {
-      const uint64_t kb = plan.ins_off[tile.filter];
-      const uint32_t n = (uint32_t)(plan.ins_off[tile.filter + 1] - kb);
       const uint64_t *keys = hashes + kb;
       for (uint32_t base = wave * kStep; base < n; base += waves * kStep) {
         uint64_t hv[U];
@@ -266,7 +297,6 @@ grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint32
           or_key(lds2, hv[u], base + 64u * u + lane < n, flt.num_blocks, tile.b0, tile.nb);
       }
     } else {
-      const uint32_t nr = plan.nruns[tile.slice];
       const GRun *runs = plan.runs + plan.slices[tile.slice].run_off;
       for (uint32_t r0 = 0; r0 < nr; r0 += kRunBatch) {
         // Runs r0 .. r0 + m - 1 as one sequence: pre[k] is where run k starts
@@ -335,10 +365,13 @@ grouped_lookup_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint8_
       __syncthreads();
       if (t >= qn) break;
       const GLookTile tile = plan.look_tiles[qb + t];
+      uint64_t lb;
+      const uint64_t nf = call_range(plan.look_off, plan.look_cap, tile.filter, plan.bad, &lb);
+      if (tile.begin >= nf) continue;  // past the filter's keys in this call
       const GFilter flt = plan.filters[tile.filter];
-      const uint64_t *keys = hashes + tile.begin;
-      uint8_t *res = out + tile.begin;
-      const uint32_t n = tile.count;
+      const uint64_t *keys = hashes + lb + tile.begin;
+      uint8_t *res = out + lb + tile.begin;
+      const uint32_t n = (uint32_t)min((uint64_t)tile.count, nf - tile.begin);
       for (uint32_t base = wave * kChunk; base < n; base += waves * kChunk) {
         uint32_t blk[U], lo[U];
 #pragma unroll
@@ -401,9 +434,12 @@ grouped_lds_lookup_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, ui
       __syncthreads();
       if (t >= qn) break;
       const GLookTile tile = plan.lds_tiles[qb + t];
+      uint64_t lb;
+      const uint64_t nf = call_range(plan.look_off, plan.look_cap, tile.filter, plan.bad, &lb);
+      if (tile.begin >= nf) continue;  // past the filter's keys in this call
       const GFilter flt = plan.filters[tile.filter];
-      const uint32_t B = flt.num_blocks, n = tile.count;
-      const uint64_t *keys = hashes + tile.begin;
+      const uint32_t B = flt.num_blocks, n = (uint32_t)min((uint64_t)tile.count, nf - tile.begin);
+      const uint64_t *keys = hashes + lb + tile.begin;
       const uint4 *src4 = reinterpret_cast<const uint4 *>(flt.words);
       // Per key: its block, and its eight bit indices packed five bits each
       // (words 0..5 in ia, 6 and 7 in ib), computed once for all passes.
@@ -469,7 +505,7 @@ grouped_lds_lookup_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, ui
         }
         if (B - b0 <= S) break;
       }
-      uint8_t *dst = out + tile.begin;
+      uint8_t *dst = out + lb + tile.begin;
 #pragma unroll
       for (uint32_t p = 0; p < kLdsLookPer; ++p) {
         const uint32_t i = p * T + threadIdx.x;
@@ -528,7 +564,10 @@ __global__ void digest_tail_kernel(const uint8_t *p, uint32_t n, unsigned long l
 // ---- host side ------------------------------------------------------------------
 
 struct GroupedPlanHost {
-  std::vector<uint64_t> ins_off, look_off;
+  std::vector<uint64_t> ins_cap, look_cap;  // planned keys per filter
+  std::vector<uint64_t> ins_off, look_off;  // host offsets of a fixed-shape plan (empty for a capacity plan)
+  bool capacity = false;                     // key ranges come from device offsets at every run
+  uint64_t ins_total = 0, look_total = 0;    // sums of the capacities
   sbbf_grouped_config cfg;
   bool planned = false;
   uint32_t n_ins_tiles = 0, n_look_tiles = 0, n_chunks = 0, n_lds_tiles = 0;
@@ -544,6 +583,7 @@ struct GroupedPlanHost {
   hipGraphNode_t n_reset = nullptr, n_part = nullptr, n_ins = nullptr, n_look_lds = nullptr, n_look = nullptr;
   const void *g_ins = nullptr, *g_look = nullptr;
   void *g_out = nullptr;
+  const void *g_ins_off = nullptr, *g_look_off = nullptr;
 };
 
 }  // namespace sbbf
@@ -552,6 +592,7 @@ struct sbbf_group {
   std::vector<sbbf_filter *> filters;
   int device = 0;
   sbbf::GroupedPlanHost plan;
+  uint64_t plans = 0, graph_builds = 0, graph_updates = 0;  // host work done for this group
 };
 
 namespace sbbf {
@@ -572,6 +613,7 @@ void free_plan(GroupedPlanHost &p) {
   p.planned = false;
   p.g_ins = p.g_look = nullptr;
   p.g_out = nullptr;
+  p.g_ins_off = p.g_look_off = nullptr;
 }
 
 sbbf_grouped_config default_config(const sbbf_device_info &info) {
@@ -664,20 +706,38 @@ static dim3 reset_grid(const GroupedPlanHost &p) {
   return dim3((n + 255u) / 256u);
 }
 
-// Build tiles and queues for the group and copy them to the device.
-sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uint64_t *look_off,
-                               const sbbf_grouped_config &cfg, const sbbf_device_info &info) {
+// Build tiles and queues for the group from per-filter capacities (keys
+// inserted and looked up per call, at most) and copy them to the device.
+// Tiles are relative to each filter's key ranges, which the kernels read from
+// device offsets when they run: the plan's own copy of host offsets for a
+// fixed-shape plan (ins_off and look_off given), the caller's per-call
+// offsets for a capacity plan (both NULL).
+sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_cap, const uint64_t *look_cap,
+                               const uint64_t *ins_off, const uint64_t *look_off, const sbbf_grouped_config &cfg,
+                               const sbbf_device_info &info) {
   GroupedPlanHost &p = g->plan;
   free_plan(p);
   const uint32_t F = (uint32_t)g->filters.size();
-  p.ins_off.assign(ins_off, ins_off + F + 1);
-  p.look_off.assign(look_off, look_off + F + 1);
-  for (uint32_t f = 0; f < F; ++f) {
-    if (p.ins_off[f + 1] < p.ins_off[f] || p.look_off[f + 1] < p.look_off[f])
-      return set_error(SBBF_EINVAL, "offsets must be non-decreasing");
-    if (p.ins_off[f + 1] - p.ins_off[f] > 0xFFFFFFFFull)
-      return set_error(SBBF_EUNSUPPORTED, "a filter takes at most 2^32 - 1 insert keys per grouped call");
+  p.ins_cap.assign(ins_cap, ins_cap + F);
+  p.look_cap.assign(look_cap, look_cap + F);
+  p.capacity = ins_off == nullptr;
+  if (p.capacity) {
+    p.ins_off.clear();
+    p.look_off.clear();
+  } else {
+    p.ins_off.assign(ins_off, ins_off + F + 1);
+    p.look_off.assign(look_off, look_off + F + 1);
   }
+  p.ins_total = p.look_total = 0;
+  for (uint32_t f = 0; f < F; ++f) {
+    if (p.ins_cap[f] > 0xFFFFFFFFull)
+      return set_error(SBBF_EUNSUPPORTED, "a filter takes at most 2^32 - 1 insert keys per grouped call");
+    p.ins_total += p.ins_cap[f];
+    p.look_total += p.look_cap[f];
+    if (p.ins_total < p.ins_cap[f] || p.look_total < p.look_cap[f])
+      return set_error(SBBF_EINVAL, "key capacities overflow 64 bits");
+  }
+  ++g->plans;
   p.cfg = cfg;
 
   // Insert tiles. A filter that fits insert_lds_bytes is one stream tile. A
@@ -697,7 +757,7 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   size_t max_lds = 32;
   const uint32_t S = 1u << cfg.insert_slice_shift;
   for (uint32_t f = 0; f < F; ++f) {
-    const uint64_t n = p.ins_off[f + 1] - p.ins_off[f];
+    const uint64_t n = p.ins_cap[f];
     if (n == 0) continue;
     const uint32_t B = g->filters[f]->num_blocks;
     if ((uint64_t)B * 32u <= cfg.insert_lds_bytes) {
@@ -712,8 +772,7 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
       const uint32_t n_chunks = (uint32_t)((n + kPartChunk - 1u) / kPartChunk);
       parts.push_back({part_keys, f, (uint32_t)slices.size(), ns, cfg.insert_slice_shift});
       part_chunks.emplace_back();
-      for (uint64_t at = 0; at < n; at += kPartChunk)
-        part_chunks.back().push_back({p.ins_off[f] + at, (uint32_t)std::min<uint64_t>(kPartChunk, n - at), pi});
+      for (uint32_t k = 0; k < n_chunks; ++k) part_chunks.back().push_back({k, pi});
       part_keys += n;
       for (uint32_t k = 0; k < ns; ++k) {
         slices.push_back({(uint32_t)run_total, n_chunks});
@@ -751,9 +810,7 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   // Lookup tiles, filters assigned to queues greedily by work (largest first).
   std::vector<uint32_t> order(F);
   std::iota(order.begin(), order.end(), 0u);
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-    return p.look_off[a + 1] - p.look_off[a] > p.look_off[b + 1] - p.look_off[b];
-  });
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return p.look_cap[a] > p.look_cap[b]; });
   // Filters of at most lookup_lds_slices LDS slices take LDS tiles (their own
   // queues, balanced separately), the rest gather tiles.
   const int nq = cfg.xcd_queues ? kQueues : 1;
@@ -762,7 +819,7 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   std::vector<uint64_t> load(kQueues, 0), load_lds(kQueues, 0);
   uint32_t lds_max_blocks = 0;
   for (uint32_t f : order) {
-    const uint64_t n = p.look_off[f + 1] - p.look_off[f];
+    const uint64_t n = p.look_cap[f];
     if (n == 0) continue;
     const uint32_t B = g->filters[f]->num_blocks;
     const uint64_t nsl = ((uint64_t)B + (1u << p.lds_look_shift) - 1u) >> p.lds_look_shift;
@@ -775,7 +832,7 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
     const uint32_t tk = lds ? kLdsLookPer * cfg.lookup_lds_threads : cfg.lookup_tile_keys;
     for (uint64_t at = 0; at < n; at += tk) {
       const uint32_t c = (uint32_t)std::min<uint64_t>(tk, n - at);
-      (lds ? qlds : qt)[best].push_back({p.look_off[f] + at, c, f});
+      (lds ? qlds : qt)[best].push_back({at, c, f});
     }
     if (lds) lds_max_blocks = std::max(lds_max_blocks, std::min(B, 1u << p.lds_look_shift));
   }
@@ -799,14 +856,19 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   std::vector<GFilter> ft(F);
   for (uint32_t f = 0; f < F; ++f) ft[f] = {g->filters[f]->words, g->filters[f]->num_blocks, 0u};
 
-  // One device allocation: filters | ins_off | ins tiles | look tiles |
-  // queue_begin | LDS look tiles | LDS queue_begin | counters | parts | chunks
-  // | slices | runs | nruns | tops; the partitioned keys are a second one.
+  // One device allocation: filters | ins_off | look_off | ins_cap | look_cap |
+  // bad | ins tiles | look tiles | queue_begin | LDS look tiles | LDS
+  // queue_begin | counters | parts | chunks | slices | runs | nruns | tops;
+  // the partitioned keys are a second one.
   auto up = [](size_t v) { return (v + 255u) & ~(size_t)255u; };
   auto at_least1 = [](size_t v) { return std::max<size_t>(1, v); };
   const size_t o_f = 0;
   const size_t o_io = o_f + up(F * sizeof(GFilter));
-  const size_t o_it = o_io + up((F + 1) * sizeof(uint64_t));
+  const size_t o_lo = o_io + up((F + 1) * sizeof(uint64_t));
+  const size_t o_ic = o_lo + up((F + 1) * sizeof(uint64_t));
+  const size_t o_lc = o_ic + up(F * sizeof(uint64_t));
+  const size_t o_bad = o_lc + up(F * sizeof(uint64_t));
+  const size_t o_it = o_bad + up(sizeof(uint32_t));
   const size_t o_lt = o_it + up(at_least1(ins.size()) * sizeof(GInsTile));
   const size_t o_qb = o_lt + up(at_least1(look.size()) * sizeof(GLookTile));
   const size_t o_ll = o_qb + up((kQueues + 1) * sizeof(uint32_t));
@@ -821,7 +883,14 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   const size_t total = o_tp + up(at_least1(parts.size()) * sizeof(unsigned long long));
   std::vector<char> host(o_rn, 0);  // runs, nruns and tops are written on the device
   memcpy(host.data() + o_f, ft.data(), F * sizeof(GFilter));
-  memcpy(host.data() + o_io, p.ins_off.data(), (F + 1) * sizeof(uint64_t));
+  if (!p.capacity) {
+    memcpy(host.data() + o_io, p.ins_off.data(), (F + 1) * sizeof(uint64_t));
+    memcpy(host.data() + o_lo, p.look_off.data(), (F + 1) * sizeof(uint64_t));
+  }
+  memcpy(host.data() + o_ic, p.ins_cap.data(), F * sizeof(uint64_t));
+  memcpy(host.data() + o_lc, p.look_cap.data(), F * sizeof(uint64_t));
+  const uint32_t no_bad = 0xFFFFFFFFu;
+  memcpy(host.data() + o_bad, &no_bad, sizeof(no_bad));
   for (size_t i = 0; i < ins.size(); ++i) memcpy(host.data() + o_it + i * sizeof(GInsTile), &ins[i].t, sizeof(GInsTile));
   if (!look.empty()) memcpy(host.data() + o_lt, look.data(), look.size() * sizeof(GLookTile));
   memcpy(host.data() + o_qb, qbegin.data(), (kQueues + 1) * sizeof(uint32_t));
@@ -840,7 +909,12 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_off, const uin
   }
   char *d = static_cast<char *>(p.dev);
   p.pd.filters = reinterpret_cast<const GFilter *>(d + o_f);
-  p.pd.ins_off = reinterpret_cast<const uint64_t *>(d + o_io);
+  // A capacity plan's kernels take the offsets of each run instead.
+  p.pd.ins_off = p.capacity ? nullptr : reinterpret_cast<const uint64_t *>(d + o_io);
+  p.pd.look_off = p.capacity ? nullptr : reinterpret_cast<const uint64_t *>(d + o_lo);
+  p.pd.ins_cap = reinterpret_cast<const uint64_t *>(d + o_ic);
+  p.pd.look_cap = reinterpret_cast<const uint64_t *>(d + o_lc);
+  p.pd.bad = reinterpret_cast<uint32_t *>(d + o_bad);
   p.pd.ins_tiles = reinterpret_cast<const GInsTile *>(d + o_it);
   p.pd.look_tiles = reinterpret_cast<const GLookTile *>(d + o_lt);
   p.pd.queue_begin = reinterpret_cast<const uint32_t *>(d + o_qb);
@@ -1015,6 +1089,9 @@ static sbbf_status build_graph(sbbf_group *g, const uint64_t *d_ins, const uint6
   p.g_ins = d_ins;
   p.g_look = d_look;
   p.g_out = d_out;
+  p.g_ins_off = p.pd.ins_off;
+  p.g_look_off = p.pd.look_off;
+  ++g->graph_builds;
   return SBBF_OK;
 }
 
@@ -1027,16 +1104,29 @@ static sbbf_status update_graph(sbbf_group *g, const uint64_t *d_ins, const uint
   p.g_ins = d_ins;
   p.g_look = d_look;
   p.g_out = d_out;
+  p.g_ins_off = p.pd.ins_off;
+  p.g_look_off = p.pd.look_off;
+  ++g->graph_updates;
   return SBBF_OK;
 }
 
+// One graph launch. A capacity plan takes the run's device offsets; the
+// graph's kernel nodes hold them (and the data pointers) as arguments and are
+// updated only when a pointer changes, never re-planned: new counts in the
+// same offset buffers need no host work at all.
 sbbf_status grouped_run_graph(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
-                              hipStream_t s, const sbbf_device_info &info) {
+                              hipStream_t s, const sbbf_device_info &info, const uint64_t *d_ins_off = nullptr,
+                              const uint64_t *d_look_off = nullptr) {
   GroupedPlanHost &p = g->plan;
+  if (p.capacity) {
+    p.pd.ins_off = d_ins_off;
+    p.pd.look_off = d_look_off;
+  }
   sbbf_status st = SBBF_OK;
   if (!p.exec) {
     st = build_graph(g, d_ins, d_look, d_out, info);
-  } else if (p.g_ins != d_ins || p.g_look != d_look || p.g_out != d_out) {
+  } else if (p.g_ins != d_ins || p.g_look != d_look || p.g_out != d_out || p.g_ins_off != p.pd.ins_off ||
+             p.g_look_off != p.pd.look_off) {
     st = update_graph(g, d_ins, d_look, d_out, info);
   }
   if (st != SBBF_OK) return st;
@@ -1061,7 +1151,7 @@ static sbbf_status group_digest(sbbf_group *g, const uint8_t *d_out, hipStream_t
     // Chain filters so that swapping two equal-sized filters changes the digest.
     hipLaunchKernelGGL(digest_chain_kernel, dim3(1), dim3(1), 0, s, acc, (unsigned long long)f);
   }
-  const uint64_t nl = g->plan.look_off.empty() ? 0 : g->plan.look_off.back();
+  const uint64_t nl = g->plan.look_off.empty() ? 0 : g->plan.look_off.back();  // 0 for a capacity plan
   if (d_out && nl) {
     // Bytes are digested as 32-bit words plus the ragged tail.
     digest_launch(reinterpret_cast<const uint32_t *>(d_out), nl / 4, acc + 1, s);
@@ -1093,7 +1183,7 @@ namespace {
 std::string tune_key(const sbbf_device_info &info, const sbbf_group *g) {
   int rt = 0;
   (void)hipRuntimeGetVersion(&rt);
-  uint64_t ins = g->plan.ins_off.back(), look = g->plan.look_off.back();
+  uint64_t ins = g->plan.ins_total, look = g->plan.look_total;
   uint32_t maxb = 0;
   for (auto *f : g->filters) maxb = std::max(maxb, f->num_blocks);
   auto lg = [](uint64_t v) { int k = 0; while (v > 1) { v >>= 1; ++k; } return k; };
@@ -1143,8 +1233,18 @@ sbbf_status need_plan(const sbbf_group *g) {
   return SBBF_OK;
 }
 
+// Entry points that take no offsets need a plan made from host offsets.
+sbbf_status need_fixed_plan(const sbbf_group *g) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK) return st;
+  if (g->plan.capacity)
+    return set_error(SBBF_EINVAL, "the group has a capacity plan: its runs take device offsets "
+                                  "(sbbf_grouped_run_offsets)");
+  return SBBF_OK;
+}
+
 sbbf_status check_io(const sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, const uint8_t *d_out) {
-  const uint64_t ni = g->plan.ins_off.back(), nl = g->plan.look_off.back();
+  const uint64_t ni = g->plan.ins_total, nl = g->plan.look_total;
   if (ni && (!d_ins || ((uintptr_t)d_ins & 7))) return set_error(SBBF_EINVAL, "d_ins is NULL or not 8-byte aligned");
   if (nl && (!d_look || ((uintptr_t)d_look & 7))) return set_error(SBBF_EINVAL, "d_look is NULL or not 8-byte aligned");
   if (nl && !d_out) return set_error(SBBF_EINVAL, "d_out is NULL");
@@ -1214,7 +1314,67 @@ sbbf_status sbbf_grouped_plan(sbbf_group *g, const uint64_t *h_ins_offsets, cons
   if (!info) return st;
   const sbbf_grouped_config c = cfg ? *cfg : default_config(*info);
   if ((st = check_config(c, *info)) != SBBF_OK) return st;
-  return grouped_build_plan(g, h_ins_offsets, h_look_offsets, c, *info);
+  const size_t F = g->filters.size();
+  std::vector<uint64_t> ic(F), lc(F);
+  for (size_t f = 0; f < F; ++f) {
+    if (h_ins_offsets[f + 1] < h_ins_offsets[f] || h_look_offsets[f + 1] < h_look_offsets[f])
+      return set_error(SBBF_EINVAL, "offsets must be non-decreasing");
+    ic[f] = h_ins_offsets[f + 1] - h_ins_offsets[f];
+    lc[f] = h_look_offsets[f + 1] - h_look_offsets[f];
+  }
+  return grouped_build_plan(g, ic.data(), lc.data(), h_ins_offsets, h_look_offsets, c, *info);
+}
+
+sbbf_status sbbf_grouped_plan_capacity(sbbf_group *g, const uint64_t *h_ins_cap, const uint64_t *h_look_cap,
+                                       const sbbf_grouped_config *cfg) {
+  if (!g || !h_ins_cap || !h_look_cap) return set_error(SBBF_EINVAL, "group or capacities is NULL");
+  sbbf_status st;
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  const sbbf_grouped_config c = cfg ? *cfg : default_config(*info);
+  if ((st = check_config(c, *info)) != SBBF_OK) return st;
+  return grouped_build_plan(g, h_ins_cap, h_look_cap, nullptr, nullptr, c, *info);
+}
+
+sbbf_status sbbf_grouped_run_offsets(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_ins_offsets,
+                                     const uint64_t *d_look, const uint64_t *d_look_offsets, uint8_t *d_out,
+                                     sbbf_stream s) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
+  if (!g->plan.capacity)
+    return set_error(SBBF_EINVAL, "the group's plan has fixed offsets (use sbbf_grouped_run, or plan with "
+                                  "sbbf_grouped_plan_capacity)");
+  if (!d_ins_offsets || !d_look_offsets || ((uintptr_t)d_ins_offsets & 7) || ((uintptr_t)d_look_offsets & 7))
+    return set_error(SBBF_EINVAL, "d_ins_offsets and d_look_offsets must be 8-byte aligned device pointers");
+  const sbbf_device_info *info = current_device_info(&st);
+  if (!info) return st;
+  return grouped_run_graph(g, d_ins, d_look, d_out, (hipStream_t)s, *info, d_ins_offsets, d_look_offsets);
+}
+
+sbbf_status sbbf_grouped_check(sbbf_group *g, sbbf_stream s, uint32_t *first_bad) {
+  sbbf_status st = need_plan(g);
+  if (st != SBBF_OK) return st;
+  uint32_t bad = 0xFFFFFFFFu;
+  hipStream_t stream = (hipStream_t)s;
+  hipError_t e = hipMemcpyAsync(&bad, g->plan.pd.bad, sizeof(bad), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_error(e, "sbbf_grouped_check");
+  if (first_bad) *first_bad = bad;
+  if (bad == 0xFFFFFFFFu) return SBBF_OK;
+  e = launch_fill(g->plan.pd.bad, 1, 0xFFFFFFFFu, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_error(e, "sbbf_grouped_check (reset)");
+  return set_error(SBBF_EINVAL, "filter " + std::to_string(bad) + " had a key range above its planned capacity "
+                                "(or decreasing offsets) in a run; its keys past the capacity were not processed");
+}
+
+sbbf_status sbbf_grouped_counters(const sbbf_group *g, uint64_t *plans, uint64_t *graph_builds,
+                                  uint64_t *graph_updates) {
+  if (!g) return set_error(SBBF_EINVAL, "group is NULL");
+  if (plans) *plans = g->plans;
+  if (graph_builds) *graph_builds = g->graph_builds;
+  if (graph_updates) *graph_updates = g->graph_updates;
+  return SBBF_OK;
 }
 
 sbbf_status sbbf_grouped_get_config(const sbbf_group *g, sbbf_grouped_config *out) {
@@ -1227,7 +1387,7 @@ sbbf_status sbbf_grouped_get_config(const sbbf_group *g, sbbf_grouped_config *ou
 
 sbbf_status sbbf_grouped_run(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
                              sbbf_stream s) {
-  sbbf_status st = need_plan(g);
+  sbbf_status st = need_fixed_plan(g);
   if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
   const sbbf_device_info *info = current_device_info(&st);
   if (!info) return st;
@@ -1235,9 +1395,9 @@ sbbf_status sbbf_grouped_run(sbbf_group *g, const uint64_t *d_ins, const uint64_
 }
 
 sbbf_status sbbf_grouped_insert(sbbf_group *g, const uint64_t *d_ins, sbbf_stream s) {
-  sbbf_status st = need_plan(g);
+  sbbf_status st = need_fixed_plan(g);
   if (st != SBBF_OK) return st;
-  if (g->plan.ins_off.back() && (!d_ins || ((uintptr_t)d_ins & 7)))
+  if (g->plan.ins_total && (!d_ins || ((uintptr_t)d_ins & 7)))
     return set_error(SBBF_EINVAL, "d_ins is NULL or not 8-byte aligned");
   const sbbf_device_info *info = current_device_info(&st);
   if (!info) return st;
@@ -1245,9 +1405,9 @@ sbbf_status sbbf_grouped_insert(sbbf_group *g, const uint64_t *d_ins, sbbf_strea
 }
 
 sbbf_status sbbf_grouped_lookup(sbbf_group *g, const uint64_t *d_look, uint8_t *d_out, sbbf_stream s) {
-  sbbf_status st = need_plan(g);
+  sbbf_status st = need_fixed_plan(g);
   if (st != SBBF_OK) return st;
-  const uint64_t nl = g->plan.look_off.back();
+  const uint64_t nl = g->plan.look_total;
   if (nl && (!d_look || ((uintptr_t)d_look & 7) || !d_out))
     return set_error(SBBF_EINVAL, "d_look or d_out is NULL, or d_look is not 8-byte aligned");
   const sbbf_device_info *info = current_device_info(&st);
@@ -1257,17 +1417,16 @@ sbbf_status sbbf_grouped_lookup(sbbf_group *g, const uint64_t *d_look, uint8_t *
 
 sbbf_status sbbf_grouped_run_per_filter(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look,
                                         uint8_t *d_out, sbbf_stream s) {
-  sbbf_status st = need_plan(g);
+  sbbf_status st = need_fixed_plan(g);
   if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
   const auto &io = g->plan.ins_off, &lo = g->plan.look_off;
-  sbbf_launch ins_cfg{0, 0, 0, SBBF_INSERT_ATOMIC32, 0};
-  sbbf_launch look_cfg{0, 0, 0, SBBF_LOOKUP_GATHER, 0};
+  // The library's own choice per call, as a caller of plain launches gets it.
   for (size_t f = 0; f < g->filters.size(); ++f) {
-    st = sbbf_insert_batch_ex(g->filters[f], d_ins + io[f], io[f + 1] - io[f], &ins_cfg, s);
+    st = sbbf_insert_batch_ex(g->filters[f], d_ins + io[f], io[f + 1] - io[f], nullptr, s);
     if (st != SBBF_OK) return st;
   }
   for (size_t f = 0; f < g->filters.size(); ++f) {
-    st = sbbf_lookup_batch_ex(g->filters[f], d_look + lo[f], lo[f + 1] - lo[f], d_out + lo[f], nullptr, &look_cfg, s);
+    st = sbbf_lookup_batch_ex(g->filters[f], d_look + lo[f], lo[f + 1] - lo[f], d_out + lo[f], nullptr, nullptr, s);
     if (st != SBBF_OK) return st;
   }
   return SBBF_OK;
@@ -1275,22 +1434,24 @@ sbbf_status sbbf_grouped_run_per_filter(sbbf_group *g, const uint64_t *d_ins, co
 
 sbbf_status sbbf_grouped_digest(sbbf_group *g, const uint8_t *d_out, sbbf_stream s, uint64_t *digest) {
   if (!g || !digest) return set_error(SBBF_EINVAL, "group or digest is NULL");
-  if (d_out && !g->plan.planned) return set_error(SBBF_EINVAL, "output digest needs a plan");
+  if (d_out && (!g->plan.planned || g->plan.capacity))
+    return set_error(SBBF_EINVAL, "an output digest needs a plan made from host offsets");
   return group_digest(g, d_out, (hipStream_t)s, digest);
 }
 
 sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const uint64_t *d_look, uint8_t *d_out,
                                   uint32_t reps, const char *cache_path, int force, sbbf_grouped_config *best) {
-  sbbf_status st = need_plan(g);
+  sbbf_status st = need_fixed_plan(g);
   if (st != SBBF_OK || (st = check_io(g, d_ins, d_look, d_out)) != SBBF_OK) return st;
   const sbbf_device_info *info = current_device_info(&st);
   if (!info) return st;
   const std::string key = tune_key(*info, g);
   const std::vector<uint64_t> ins_off = g->plan.ins_off, look_off = g->plan.look_off;
+  const std::vector<uint64_t> ins_cap = g->plan.ins_cap, look_cap = g->plan.look_cap;
   if (cache_path && !force) {
     sbbf_grouped_config c;
     if (cache_lookup(cache_path, key, &c) && check_config(c, *info) == SBBF_OK) {
-      if ((st = grouped_build_plan(g, ins_off.data(), look_off.data(), c, *info)) != SBBF_OK) return st;
+      if ((st = grouped_build_plan(g, ins_cap.data(), look_cap.data(), ins_off.data(), look_off.data(), c, *info)) != SBBF_OK) return st;
       if (best) *best = c;
       return SBBF_OK;
     }
@@ -1357,7 +1518,7 @@ sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const ui
   float best_ms = 1e30f;
   sbbf_grouped_config best_cfg = cur;
   auto measure = [&](const sbbf_grouped_config &c, float *ms) -> sbbf_status {
-    sbbf_status r = grouped_build_plan(g, ins_off.data(), look_off.data(), c, *info);
+    sbbf_status r = grouped_build_plan(g, ins_cap.data(), look_cap.data(), ins_off.data(), look_off.data(), c, *info);
     if (r != SBBF_OK) return r;
     std::vector<float> t;
     for (uint32_t k = 0; k <= reps; ++k) {
@@ -1412,7 +1573,7 @@ sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const ui
   (void)hipStreamDestroy(s);
   if (st != SBBF_OK) return st;
   if (es != hipSuccess) return hip_error(es, "autotune synchronise");
-  if ((st = grouped_build_plan(g, ins_off.data(), look_off.data(), best_cfg, *info)) != SBBF_OK) return st;
+  if ((st = grouped_build_plan(g, ins_cap.data(), look_cap.data(), ins_off.data(), look_off.data(), best_cfg, *info)) != SBBF_OK) return st;
   if (cache_path) cache_store(cache_path, key, best_cfg);
   if (best) *best = best_cfg;
   return SBBF_OK;

@@ -182,17 +182,46 @@ def test_grouped_edge_cases(P, cfg):
     g.close()
 
 
+def _golden_digest(name):
+    from conftest import read_golden
+
+    rows = {r[0]: r for r in read_golden("full_digests.txt")}
+    return rows[name][1], int(rows[name][2]), int(rows[name][3])
+
+
+def _sha256_filters(filters):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in filters:
+        h.update(f.words.cpu().numpy().tobytes())
+    return h.hexdigest()
+
+
+def _sha256_bytes(t):
+    import hashlib
+
+    return hashlib.sha256(t.cpu().numpy().tobytes()).hexdigest()
+
+
 def test_grouped_full_workload(P):
     """The 2,048-filter workload (key counts log-uniform in [1e3, 1e6], 10.5
     bits per key, four lookups per inserted key) in the launch shape the
-    benchmark times: all outputs equal the per-filter plain launches, and a
-    sample of filters (the two largest, the two smallest and 16 others) equals
-    the oracle exactly."""
+    benchmark times: every filter's bytes and every lookup byte equal the
+    oracle's (SHA-256 of both against digests the oracle wrote,
+    tests/golden/full_digests.txt), a sample of filters equals the oracle
+    directly, and the per-filter plain launches give the same outputs."""
     w = grouped_workload(num_filters=2048, backend="torch", device="cuda")
     filters, g = make_group(P, w)
     out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
     g.run(w.inserts, w.lookups, out)
     torch.cuda.synchronize()
+    sha_f, nbytes_f, _ = _golden_digest("grouped_2048_filters")
+    sha_l, nbytes_l, positives = _golden_digest("grouped_2048_lookups")
+    assert sum(f.words.numel() * 4 for f in filters) == nbytes_f and out.numel() == nbytes_l
+    assert int(out.sum(dtype=torch.int64).item()) == positives
+    assert _sha256_filters(filters) == sha_f
+    assert _sha256_bytes(out) == sha_l
     digest = g.digest(out)
     order = np.argsort(w.n)
     rng = np.random.default_rng(7)
@@ -322,3 +351,126 @@ def test_group_rejects_shared_memory(P):
     P.sbbf_destroy(h2)
     a.close()
     b.close()
+
+
+# ---- capacity plans: per-run key ranges from device offsets -------------------------
+
+# Filters covering every tile kind: stream-inserted (whole filter in LDS),
+# partitioned by slice, LDS lookups (at most four 128 KiB slices) and gathers.
+CAP_BLOCKS = [50, 700, 4096, 9000, 16_384, 40_000, 3, 2_500, 70_000]
+CAP_INS = [2_000, 30_000, 90_000, 200_000, 400_000, 900_000, 10, 50_000, 1_500_000]
+CAP_LOOK = [9_000, 1_000, 300_000, 50_000, 500_000, 800_000, 40, 70_001, 1_000_000]
+
+
+def _count_vectors():
+    rng = np.random.default_rng(11)
+    full = (np.array(CAP_INS), np.array(CAP_LOOK))
+    part = (rng.integers(0, np.array(CAP_INS) + 1), rng.integers(0, np.array(CAP_LOOK) + 1))
+    part[0][1] = 0
+    part[1][4] = 0
+    tiny = (np.where(np.arange(len(CAP_INS)) == 5, CAP_INS[5], np.arange(len(CAP_INS)) % 3),
+            np.where(np.arange(len(CAP_LOOK)) == 8, CAP_LOOK[8], np.arange(len(CAP_LOOK)) % 4))
+    return [full, part, tiny]
+
+
+def _csr(n):
+    off = np.zeros(len(n) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(n)
+    return off
+
+
+def _cap_inputs(step, n_ins, n_look):
+    """Inserts and lookups of one run: fresh hashes per filter, lookups mixing
+    the filter's members of this run with fresh hashes."""
+    ins_off, look_off = _csr(n_ins), _csr(n_look)
+    ins = splitmix64_stream(820 + step, int(ins_off[-1]))
+    look = splitmix64_stream(830 + step, int(look_off[-1]))
+    for f in range(len(n_ins)):
+        m = min(int(n_ins[f]), int(n_look[f]) // 2)
+        look[look_off[f]:look_off[f] + m] = ins[ins_off[f]:ins_off[f] + m]
+    return ins, look, ins_off, look_off
+
+
+def test_capacity_plan_three_count_vectors(P):
+    """One capacity plan and one graph, replayed with three different
+    per-filter count vectors written into the same device offset buffers:
+    every run equals the oracle, and no run does host planning or touches the
+    graph (one plan, one graph instantiation, no updates)."""
+    filters = [P.Filter(b) for b in CAP_BLOCKS]
+    g = P.Group.with_capacity(filters, CAP_INS, CAP_LOOK)
+    d_ins = torch.empty(sum(CAP_INS), dtype=torch.int64, device="cuda")
+    d_look = torch.empty(sum(CAP_LOOK), dtype=torch.int64, device="cuda")
+    d_out = torch.empty(sum(CAP_LOOK), dtype=torch.uint8, device="cuda")
+    d_ioff = torch.empty(len(CAP_BLOCKS) + 1, dtype=torch.int64, device="cuda")
+    d_loff = torch.empty(len(CAP_BLOCKS) + 1, dtype=torch.int64, device="cuda")
+    for step, (n_ins, n_look) in enumerate(_count_vectors()):
+        ins, look, ins_off, look_off = _cap_inputs(step, n_ins, n_look)
+        print(f"capacity run {step}: inserts {n_ins.tolist()} lookups {n_look.tolist()}", flush=True)
+        g.clear()
+        d_out.fill_(7)
+        d_ins[:ins.size].copy_(dev(ins))
+        d_look[:look.size].copy_(dev(look))
+        d_ioff.copy_(torch.from_numpy(ins_off))
+        d_loff.copy_(torch.from_numpy(look_off))
+        g.run_offsets(d_ins, d_ioff, d_look, d_loff, d_out)
+        assert g.check() is None
+        out = d_out[:look.size].cpu().numpy()
+        for f, B in enumerate(CAP_BLOCKS):
+            ref = oracle.build_filter(B, ins[ins_off[f]:ins_off[f + 1]])
+            assert np.array_equal(filters[f].words.cpu().numpy().view(np.uint32), ref), (step, f)
+            assert np.array_equal(out[look_off[f]:look_off[f + 1]],
+                                  oracle.lookup(ref, B, look[look_off[f]:look_off[f + 1]])), (step, f)
+        assert bool((d_out[look.size:] == 7).all()), step  # nothing written past the run's lookups
+    c = g.counters()
+    assert c == dict(plans=1, graph_builds=1, graph_updates=0), c
+    g.close()
+
+
+def test_capacity_plan_over_capacity_is_clamped_and_reported(P):
+    """A run whose offsets give one filter more keys than planned (and another
+    a decreasing range) processes only the planned keys of those filters, the
+    rest exactly, and sbbf_grouped_check names the lowest offending filter."""
+    blocks, cap_ins, cap_look = [900, 9000, 300], [5_000, 80_000, 2_000], [6_000, 50_000, 3_000]
+    filters = [P.Filter(b) for b in blocks]
+    g = P.Group.with_capacity(filters, cap_ins, cap_look)
+    n_ins = np.array([5_000, 80_100, 1_000])       # filter 1: 100 keys over its capacity
+    n_look = np.array([6_000, 50_000, 3_000])
+    ins, look, ins_off, look_off = _cap_inputs(9, n_ins, n_look)
+    look_bad = look_off.copy()
+    look_bad[2] = look_off[2] + 10_000             # filter 1's lookups reach past filter 2's start: decreasing for 2
+    d_ioff, d_loff = torch.from_numpy(ins_off).cuda(), torch.from_numpy(look_bad).cuda()
+    d_look = torch.cat([dev(look), torch.zeros(10_000, dtype=torch.int64, device="cuda")])
+    d_out = torch.full((d_look.numel(),), 7, dtype=torch.uint8, device="cuda")
+    g.run_offsets(dev(ins), d_ioff, d_look, d_loff, d_out)
+    assert g.check() == 1
+    assert g.check() is None  # the record was cleared
+    ref1 = oracle.build_filter(9000, ins[ins_off[1]:ins_off[1] + cap_ins[1]])
+    assert np.array_equal(filters[1].words.cpu().numpy().view(np.uint32), ref1)
+    ref0 = oracle.build_filter(900, ins[:ins_off[1]])
+    assert np.array_equal(filters[0].words.cpu().numpy().view(np.uint32), ref0)
+    out = d_out.cpu().numpy()
+    assert np.array_equal(out[:look_off[1]], oracle.lookup(ref0, 900, look[:look_off[1]]))
+    # filter 1 looks up its first 50,000 keys of the (longer) range; filter 2 none
+    assert np.array_equal(out[look_off[1]:look_off[1] + 50_000],
+                          oracle.lookup(ref1, 9000, d_look[look_off[1]:look_off[1] + 50_000].cpu().numpy().view(np.uint64)))
+    assert bool((torch.from_numpy(out[look_off[1] + 50_000:]) == 7).all())
+    ref2 = oracle.build_filter(300, ins[ins_off[2]:ins_off[3]])
+    assert np.array_equal(filters[2].words.cpu().numpy().view(np.uint32), ref2)
+    g.close()
+
+
+def test_capacity_plan_entry_point_rules(P):
+    filters = [P.Filter(64), P.Filter(128)]
+    g = P.Group.with_capacity(filters, [10, 10], [10, 10])
+    x = torch.zeros(20, dtype=torch.int64, device="cuda")
+    out = torch.zeros(20, dtype=torch.uint8, device="cuda")
+    for call in (lambda: g.run(x, x, out), lambda: g.run_per_filter(x, x, out), lambda: g.digest(out),
+                 lambda: P.sbbf_grouped_insert(g.handle, x)):
+        with pytest.raises(P.SbbfError):
+            call()
+    g.close()
+    fixed = P.Group(filters, np.array([0, 5, 10]), np.array([0, 5, 10]))
+    offs = torch.tensor([0, 5, 10], dtype=torch.int64, device="cuda")
+    with pytest.raises(P.SbbfError):
+        fixed.run_offsets(x, offs, x, offs, out)
+    fixed.close()

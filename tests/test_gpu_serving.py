@@ -170,6 +170,41 @@ def test_serving_workload_scale(P):
     P.sbbf_server_destroy(s)
 
 
+def test_serving_full_log_against_oracle_digests(P):
+    """The full serving workload: 4,096 resident filters and a log of 200,000
+    requests (sizes log-uniform in 1..65,536, 20 % inserts, 1,185,987,198
+    keys), generated on the device and replayed through the loop. Every final
+    filter byte and every lookup byte equals the oracle's in-order replay of
+    the same log (SHA-256 against tests/golden/full_digests.txt, written by
+    tests/golden/make_full_digests.py from the oracle alone)."""
+    import hashlib
+
+    from conftest import read_golden
+
+    rows = {r[0]: r for r in read_golden("full_digests.txt")}
+    L = serving_log(num_filters=4096, num_requests=200_000, backend="torch", device="cuda")
+    assert int(L.key_off[-1]) == L.payload.numel() == 1_185_987_198
+    s = make_server(P, L)
+    d_out = torch.full((int(L.out_off[-1]),), 7, dtype=torch.uint8, device="cuda")
+    print(f"serving full log: {L.num_requests} requests, {L.payload.numel()} keys", flush=True)
+    P.sbbf_server_replay(s, P.serving_requests(L, L.payload, d_out), realtime=False)
+    st = P.sbbf_server_stats(s)
+    print("serving stats:", st)
+    assert st["requests_done"] == L.num_requests and st["keys_done"] == L.payload.numel()
+    sha_l, nbytes_l, positives = rows["serving_4096x200000_lookups"][1:4]
+    assert d_out.numel() == int(nbytes_l)
+    assert int(d_out.sum(dtype=torch.int64).item()) == int(positives)
+    assert hashlib.sha256(d_out.cpu().numpy().tobytes()).hexdigest() == sha_l
+    hf = hashlib.sha256()
+    total = 0
+    for words in snapshot_all(P, s, L):
+        hf.update(words.tobytes())
+        total += words.nbytes
+    assert total == int(rows["serving_4096x200000_filters"][2])
+    assert hf.hexdigest() == rows["serving_4096x200000_filters"][1]
+    P.sbbf_server_destroy(s)
+
+
 def test_one_large_filter_spreads(P):
     """Steps whose lookups all hit one large filter (and a few small ones):
     the lookup tiles of that filter move between the per-XCD queues as they
