@@ -43,18 +43,20 @@ PAPER_CONTEXT = {"insert_Mps": 32, "lookup_Mps": 43, "hardware": "not stated (CP
 # Sources of the single-filter path's kernels and their launch choices: a
 # change to any of them invalidates committed hardware-counter traffic.
 PLAIN_SOURCES = ("sbbf_device.h", "internal.h", "plain_kernels.hip", "partition_kernels.hip", "api.cpp")
+# The same for the grouped graph's kernels.
+GROUPED_SOURCES = ("sbbf_device.h", "internal.h", "grouped.hip")
 
 
-def _kernel_source_digest() -> str:
+def _kernel_source_digest(sources=PLAIN_SOURCES) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2101_01719_amd", "csrc")
-    for name in PLAIN_SOURCES:
+    for name in sources:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel: str, workload: str):
+def _traffic(kernel: str, workload: str, sources=PLAIN_SOURCES):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None when
     none exist or the kernels changed since they were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
@@ -62,7 +64,7 @@ def _traffic(kernel: str, workload: str):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_digest") != _kernel_source_digest():
+    if t.get("kernel_source_digest") != _kernel_source_digest(sources):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -105,6 +107,8 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
         raise SystemExit(f"no copy dispatch writing about {copy_mib} MiB found")
     ci = copies[0]
     f_fetch, f_write = want_kib / fetch[ci][3], want_kib / write[ci][3]
+    if workload == "grouped_2048":
+        return _grouped_traffic(fetch, write, ci, f_fetch, f_write, copy_mib, commands)
     # Library dispatches after the copy: fill (clear), then the insert
     # kernels (a bucketed insert starts with a fill of its overflow count and
     # ends with the overflow pass; a counted one ends with the slice insert),
@@ -156,6 +160,55 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
             json.dump(out[op], fh, indent=1)
             fh.write("\n")
     print(json.dumps({op: v["hbm_bytes_per_launch"] for op, v in out.items()}))
+    return 0
+
+
+def _grouped_traffic(fetch, write, ci, f_fetch, f_write, copy_mib, commands) -> int:
+    """HBM bytes per grouped graph launch: the grouped_* kernels from each
+    reset node to the gather lookup node that ends the graph, averaged over
+    launches (the per-filter baseline's and the digest's kernels are not
+    grouped_* and are left out)."""
+    launches, cur = [], None
+    for i in range(ci + 1, len(fetch)):
+        name = _short_kernel(fetch[i][1])
+        if not name.startswith("grouped_"):
+            continue
+        if name.startswith("grouped_reset"):
+            cur = []
+        if cur is None:
+            continue
+        cur.append((name, fetch[i][3], write[i][3]))
+        if name.startswith("grouped_lookup_kernel"):
+            launches.append(cur)
+            cur = None
+    if not launches:
+        raise SystemExit("no grouped graph launch found after the copy")
+    per_kernel = {}
+    for call in launches:
+        for name, fk, wk in call:
+            d = per_kernel.setdefault(name, [0.0, 0.0, 0])
+            d[0] += fk
+            d[1] += wk
+            d[2] += 1
+    kernels = {k: {"fetch_kib_per_call": v[0] / len(launches), "write_kib_per_call": v[1] / len(launches),
+                   "dispatches_per_call": v[2] / len(launches)} for k, v in per_kernel.items()}
+    hbm = sum(1024.0 * (k["fetch_kib_per_call"] * f_fetch + k["write_kib_per_call"] * f_write)
+              for k in kernels.values())
+    out = {
+        "workload": "grouped_2048",
+        "operation": "graph",
+        "calls_averaged": len(launches),
+        "hbm_bytes_per_launch": int(round(hbm)),
+        "kernels": kernels,
+        "calibration": {"copy_mib": copy_mib, "copy_fetch_kib": fetch[ci][3], "copy_write_kib": write[ci][3],
+                        "fetch_scale": f_fetch, "write_scale": f_write},
+        "commands": list(commands),
+        "kernel_source_digest": _kernel_source_digest(GROUPED_SOURCES),
+    }
+    with open(os.path.join(ROOT, "profiles", "traffic_graph_grouped_2048.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps({"graph": out["hbm_bytes_per_launch"]}))
     return 0
 
 
@@ -499,12 +552,62 @@ def _ceilings(P, torch, w, look_launch, ins_launch, reps=5):
     return res
 
 
+def _plain_small(P, torch, name, reps=20):
+    """One of the evaluation table's smaller geometries (4,096 blocks with 1e5
+    inserts, 32,768 blocks with 1e6): median insert and lookup times over
+    `reps` steps with the library's default strategies, and the filter bytes
+    and lookup bytes of the last step compared with the oracle."""
+    import numpy as np
+
+    import oracle
+    from synth import plain_workload
+
+    w = plain_workload(name, backend="torch", device="cuda")
+    f = P.Filter(w.num_blocks)
+    out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    t_ins, t_look = [], []
+    for k in range(reps + 3):
+        f.clear(stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        f.insert(w.inserts, stream=stream)
+        ev[1].record(stream)
+        f.lookup(w.lookups, out=out, stream=stream)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        if k >= 3:
+            t_ins.append(ev[0].elapsed_time(ev[1]))
+            t_look.append(ev[1].elapsed_time(ev[2]))
+    ins_ms, look_ms = float(np.median(t_ins)), float(np.median(t_look))
+    ins_h = w.inserts.cpu().numpy().view(np.uint64)
+    ref = oracle.build_filter(w.num_blocks, ins_h)
+    ref_out = oracle.lookup(ref, w.num_blocks, w.lookups.cpu().numpy().view(np.uint64))
+    same = bool(np.array_equal(f.words.cpu().numpy().view(np.uint32), ref) and
+                np.array_equal(out.cpu().numpy(), ref_out))
+    n_ins, n_look = w.inserts.numel(), w.lookups.numel()
+    fp = int(out[~w.is_member].sum().item())
+    res = {
+        "workload": f"{name}: {w.num_blocks:,} blocks, {n_ins:,} inserts, {n_look:,} lookups",
+        "insert_ms": ins_ms, "lookup_ms": look_ms,
+        "insert_gkeys_per_s": n_ins / ins_ms / 1e6, "lookup_gkeys_per_s": n_look / look_ms / 1e6,
+        "insert_strategy": int(P.sbbf_auto_insert_strategy(f.handle, n_ins)),
+        "lookup_strategy": int(P.sbbf_auto_lookup_strategy(f.handle, n_look)),
+        "false_positive_rate": fp / max(1, int((~w.is_member).sum().item())),
+        "identical_to_oracle": same,
+    }
+    f.close()
+    return res
+
+
 def _grouped(P, torch, autotune=True, reps=5, cfg=None):
     """The grouped workload: 2,048 filters with key counts log-uniform in
     [1e3, 1e6], 10.5 bits per key, four lookups per inserted key at a 25 %
     member rate; one graph launch against one plain launch per filter per
     operation, same data, identical results (digest of every filter and every
     output byte)."""
+    import numpy as np
+
     from synth import grouped_workload
 
     w = grouped_workload(num_filters=2048, backend="torch", device="cuda")
@@ -531,7 +634,25 @@ def _grouped(P, torch, autotune=True, reps=5, cfg=None):
     d_graph = g.digest(out)
     per_ms = timed(lambda: g.run_per_filter(w.inserts, w.lookups, out), max(2, reps // 2))
     d_per = g.digest(out)
-    keys = int(w.ins_off[-1] + w.look_off[-1])
+    # The same batch through a capacity plan: key ranges from device offsets.
+    cap = P.Group.with_capacity(filters, np.diff(w.ins_off), np.diff(w.look_off), tuned)
+    d_ioff = torch.from_numpy(np.asarray(w.ins_off, dtype=np.int64)).cuda()
+    d_loff = torch.from_numpy(np.asarray(w.look_off, dtype=np.int64)).cuda()
+    t_host = []
+
+    def cap_run():
+        t = time.perf_counter()
+        cap.run_offsets(w.inserts, d_ioff, w.lookups, d_loff, out)
+        t_host.append(time.perf_counter() - t)
+
+    cap_ms = timed(cap_run, reps)
+    cap_identical = g.digest(out) == d_graph and cap.check() is None
+    cap_counters = cap.counters()
+    cap.close()
+    n_ins, n_look = int(w.ins_off[-1]), int(w.look_off[-1])
+    keys = n_ins + n_look
+    alg_bytes = INSERT_BYTES_PER_KEY * n_ins + LOOKUP_BYTES_PER_KEY * n_look
+    gbps = alg_bytes / (graph_ms / 1e3) / 1e9
     res = {
         "workload": "2,048 filters, key counts log-uniform in [1e3, 1e6] (SplitMix64 seed 4), 10.5 bits/key, "
                     f"{int(w.ins_off[-1]):,} inserts and {int(w.look_off[-1]):,} lookups (25 % members)",
@@ -541,6 +662,13 @@ def _grouped(P, torch, autotune=True, reps=5, cfg=None):
         "gkeys_per_s": keys / graph_ms / 1e6,
         "per_filter_gkeys_per_s": keys / per_ms / 1e6,
         "identical_results": d_graph == d_per,
+        "per_filter_strategies": "library defaults per filter (sbbf_insert_batch / sbbf_lookup_batch)",
+        "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbps / HBM_PEAK_GBS, "traffic": _traffic("graph", "grouped_2048", GROUPED_SOURCES),
+                     "bytes_per_key": {"insert": INSERT_BYTES_PER_KEY, "lookup": LOOKUP_BYTES_PER_KEY},
+                     "algorithmic_bytes": alg_bytes, "avg_ms": graph_ms, "kernel": "grouped graph launch"},
+        "capacity_plan": {"graph_ms": cap_ms, "identical_results": cap_identical,
+                          "host_us_per_run": 1e6 * float(np.median(t_host)), "counters": cap_counters},
         "config": tuned,
     }
     g.close()
@@ -549,32 +677,89 @@ def _grouped(P, torch, autotune=True, reps=5, cfg=None):
     return res
 
 
-def _serving(P, torch, num_requests=50_000, capacity_only=False):
+class _PinnedHost:
+    """Mapped pinned host memory (hipHostMalloc from the HIP runtime torch
+    loaded), holding a copy of a device tensor; ``device_ptr`` is the address
+    kernels read it through (across PCIe)."""
+
+    def __init__(self, torch, t):
+        import ctypes
+        import re
+
+        import numpy as np
+
+        path = next(p for p in re.findall(r"\S*libamdhip64\.so\S*", open("/proc/self/maps").read()))
+        self.hip = ctypes.CDLL(path)
+        self.nbytes = t.numel() * t.element_size()
+        self.host = ctypes.c_void_p()
+        mapped_portable = 0x2 | 0x1
+        if self.hip.hipHostMalloc(ctypes.byref(self.host), ctypes.c_size_t(self.nbytes), mapped_portable) != 0:
+            raise RuntimeError("hipHostMalloc failed")
+        dev = ctypes.c_void_p()
+        if self.hip.hipHostGetDevicePointer(ctypes.byref(dev), self.host, 0) != 0:
+            raise RuntimeError("hipHostGetDevicePointer failed")
+        self.device_ptr = dev.value
+        buf = (ctypes.c_int64 * t.numel()).from_address(self.host.value)
+        torch.from_numpy(np.frombuffer(buf, dtype=np.int64)).copy_(t)
+        torch.cuda.synchronize()
+
+    def close(self):
+        if self.host:
+            self.hip.hipHostFree(self.host)
+            self.host = None
+
+
+def _steady_latency(P, s, first, L, lo=0.1, hi=0.9):
+    """p50 / p99 / max latency (us) of the requests whose arrival falls in the
+    [lo, hi] part of the log's span: the first steps (empty queues, cold
+    caches) and the drain at the end are left out."""
+    import numpy as np
+
+    n = L.num_requests
+    arr = np.empty(n, dtype=np.float64)
+    done = np.empty(n, dtype=np.float64)
+    for r in range(n):
+        a, d = P.sbbf_server_request_times(s, first + r)
+        arr[r], done[r] = a, d
+    t0 = arr.min()
+    span = arr.max() - t0
+    sel = (arr >= t0 + lo * span) & (arr <= t0 + hi * span)
+    lat = (done[sel] - arr[sel]) / 1e3
+    return {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "max_us": float(lat.max()), "window_requests": int(sel.sum())}
+
+
+def _serving(P, torch, num_requests=200_000, capacity_only=False):
     """The serving workload: 4,096 resident filters sized like the grouped
     workload (seed 5), Poisson arrivals, 20 % insert / 80 % lookup requests of
-    log-uniform size 1..65,536, uniform filter choice; capacity with every
-    request queued at once (after one untimed warm-up replay), then latency at
-    25 / 50 / 90 % of that capacity."""
+    log-uniform size 1..65,536, uniform filter choice, payloads generated on
+    the device; capacity with every request queued at once (after one untimed
+    warm-up replay), then latency at 25 / 50 / 90 % of that capacity over the
+    steady-state window, and the same at 50 % with the payloads in pinned host
+    memory read by the kernels across PCIe (the H2D variant)."""
     import numpy as np
 
     from synth.serving import serving_log
 
     base_rate = 1e6
-    L = serving_log(num_filters=4096, num_requests=num_requests, rate_per_s=base_rate)
-    d_payload = torch.from_numpy(L.payload.view(np.int64)).to("cuda")
+    L = serving_log(num_filters=4096, num_requests=num_requests, rate_per_s=base_rate, backend="torch",
+                    device="cuda")
+    d_payload = L.payload
     d_out = torch.empty(int(L.out_off[-1]), dtype=torch.uint8, device="cuda")
     cfg = dict(max_step_keys=16 << 20, max_step_requests=16384)
 
-    def run(rate):
+    def run(rate, payload=d_payload, steady=False):
         s = P.sbbf_server_create(cfg)
         for b in L.blocks.tolist():
             P.sbbf_server_add_filter(s, b)
-        req = P.serving_requests(L, d_payload, d_out)
+        req = P.serving_requests(L, payload, d_out)
         if rate:
             req["arrival_ns"] = (L.arrival_ns.astype(np.float64) * (base_rate / rate)).astype(np.uint64)
         torch.cuda.synchronize()
-        P.sbbf_server_replay(s, req, realtime=bool(rate))
+        first = P.sbbf_server_replay(s, req, realtime=bool(rate))
         st = P.sbbf_server_stats(s)
+        if steady:
+            st["steady"] = _steady_latency(P, s, first, L)
         P.sbbf_server_destroy(s)
         return st
 
@@ -592,27 +777,47 @@ def _serving(P, torch, num_requests=50_000, capacity_only=False):
     per_request_s = P.sbbf_server_replay_per_request(s, P.serving_requests(L, d_payload, d_out))
     P.sbbf_server_destroy(s)
     identical = bool(torch.equal(d_out, ref_out))
-    del ref_out
     keys = int(L.key_off[-1])
     mean_keys = float(L.n.mean())
     points = []
     for frac in (0.25, 0.5, 0.9):
         rate = frac * cap["gkeys_per_s"] * 1e9 / mean_keys
-        st = run(rate)
+        st = run(rate, steady=True)
         points.append({"load": frac, "requests_per_s": rate, "offered_gkeys_per_s": rate * mean_keys / 1e9,
-                       "p50_us": st["p50_us"], "p99_us": st["p99_us"], "max_us": st["max_us"],
+                       "p50_us": st["steady"]["p50_us"], "p99_us": st["steady"]["p99_us"],
+                       "max_us": st["steady"]["max_us"], "window_requests": st["steady"]["window_requests"],
+                       "p50_us_all": st["p50_us"], "p99_us_all": st["p99_us"],
                        "sustained_gkeys_per_s": st["gkeys_per_s"], "steps": st["steps"]})
     half = points[1]
+    # H2D variant: the same log with its payloads in mapped pinned host memory.
+    host = _PinnedHost(torch, d_payload)
+    try:
+        d_out.zero_()
+        h2d_cap = run(0, payload=host.device_ptr)
+        h2d_identical = bool(torch.equal(d_out, ref_out))
+        rate = 0.5 * h2d_cap["gkeys_per_s"] * 1e9 / mean_keys
+        h2d_half = run(rate, payload=host.device_ptr, steady=True)
+    finally:
+        host.close()
+    del ref_out
     return {
         "workload": f"4,096 filters ({int(L.blocks.sum()) * 32 / 2**20:.1f} MiB resident), {num_requests:,} requests "
-                    f"({int(L.key_off[-1]):,} keys), 20 % inserts, sizes log-uniform 1..65,536",
+                    f"({keys:,} keys), 20 % inserts, sizes log-uniform 1..65,536",
         "capacity_gkeys_per_s": cap["gkeys_per_s"],
         "per_request_gkeys_per_s": keys / per_request_s / 1e9,
         "speedup_vs_per_request": cap["gkeys_per_s"] / (keys / per_request_s / 1e9),
         "identical_outputs_vs_per_request": identical,
         "p50_us": half["p50_us"],
         "p99_us": half["p99_us"],
+        "latency_window": "requests arriving in the middle 80 % of the replay (first steps and final drain left out)",
         "at_load": points,
+        "h2d_payload": {
+            "what": "payloads in mapped pinned host memory, read by the step kernels across PCIe; outputs on the device",
+            "capacity_gkeys_per_s": h2d_cap["gkeys_per_s"],
+            "identical_outputs": h2d_identical,
+            "at_half_load": {"offered_gkeys_per_s": rate * mean_keys / 1e9, **h2d_half["steady"],
+                             "sustained_gkeys_per_s": h2d_half["gkeys_per_s"]},
+        },
         "config": cfg,
     }
 
@@ -622,7 +827,11 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain_100m", choices=["plain_100k", "plain_1m", "plain_100m"])
+    ap.add_argument("--workload", default="plain_100m", choices=["plain_100k", "plain_1m", "plain_100m", "grouped_2048"],
+                    help="the single-filter workload timed (grouped_2048 only names the counter files of "
+                         "--traffic-from for the grouped graph)")
+    ap.add_argument("--grouped-only", action="store_true",
+                    help="run only the grouped leg (after --calibrate-copy-mib's copy), print its JSON")
     ap.add_argument("--insert-strategy", type=int, default=0,
                     help="0 = library choice, 1 atomic32, 2 atomic64, 3 LDS, 4 partitioned")
     ap.add_argument("--lookup-strategy", type=int, default=0, help="0 = library choice, 1 gather, 2 partitioned")
@@ -636,7 +845,7 @@ def main(argv=None):
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--grouped-config", metavar="JSON",
                     help="grouped plan settings over the defaults, e.g. '{\"xcd_queues\": 0}' (no autotuning)")
-    ap.add_argument("--serving-requests", type=int, default=50_000)
+    ap.add_argument("--serving-requests", type=int, default=200_000)
     ap.add_argument("--serving-capacity-only", action="store_true",
                     help="serving leg: the capacity replays only (no baseline, no load levels), for profiling")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -671,6 +880,9 @@ def main(argv=None):
             ap.error("--counter-summary needs OUT_MD and at least one CSV")
         return _counter_summary(a.counter_summary[0], a.counter_summary[1:], a.summary_title, a.summary_command)
 
+    if a.workload == "grouped_2048" and not a.grouped_only:
+        ap.error("--workload grouped_2048 names counter files for --traffic-from; use --grouped-only to run the "
+                 "grouped leg alone")
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only. Independent filters would shard across GPUs as whole "
               "filters, and one large filter by block range with an all-to-all exchange of hashes; "
@@ -684,6 +896,17 @@ def main(argv=None):
     from synth import plain_workload
 
     torch.cuda.set_device(0)
+    if a.grouped_only:
+        if a.calibrate_copy_mib:
+            src = torch.ones(a.calibrate_copy_mib << 18, dtype=torch.int32, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        cfg = json.loads(a.grouped_config) if a.grouped_config else None
+        print(json.dumps({"grouped": _grouped(P, torch, autotune=cfg is None, cfg=cfg)}), flush=True)
+        return 0
     t_gen = time.perf_counter()
     w = plain_workload(a.workload, backend="torch", device="cuda")
     torch.cuda.synchronize()
@@ -811,6 +1034,8 @@ def main(argv=None):
     f.close()
     del w, out, f
     torch.cuda.empty_cache()
+    if not a.no_select:
+        result["plain_small"] = {name: _plain_small(P, torch, name) for name in ("plain_100k", "plain_1m")}
     if not a.no_grouped:
         result["grouped"] = _grouped(P, torch, cfg=json.loads(a.grouped_config) if a.grouped_config else None)
     if not a.no_serving:

@@ -765,15 +765,18 @@ class Group:
 
 def serving_requests(log, d_payload, d_out):
     """The sbbf_request array for a synth ServingLog whose payload is staged in
-    d_payload (int64 view, device) and whose lookup outputs go to d_out (uint8)."""
+    d_payload (int64 view, device; or the integer address of the payload in
+    memory the device can read, such as mapped pinned host memory) and whose
+    lookup outputs go to d_out (uint8)."""
     import numpy as np
 
+    base = int(d_payload) if isinstance(d_payload, int) else d_payload.data_ptr()
     req = np.zeros(log.num_requests, dtype=REQUEST_DTYPE)
     req["arrival_ns"] = log.arrival_ns
     req["filter_id"] = log.filter
     req["op"] = log.op
     req["n"] = log.n
-    req["d_hashes"] = np.uint64(d_payload.data_ptr()) + log.key_off[:-1].astype(np.uint64) * np.uint64(8)
+    req["d_hashes"] = np.uint64(base) + log.key_off[:-1].astype(np.uint64) * np.uint64(8)
     look = log.op == 1
     req["d_out"] = np.where(look, np.uint64(d_out.data_ptr()) + log.out_off[:-1].astype(np.uint64), np.uint64(0))
     return req

@@ -43,6 +43,9 @@ constexpr uint32_t kServeXcds = 8;
 constexpr uint64_t kServeSlack = 65536;
 // Requests a replay without arrival times admits per round of its loop.
 constexpr uint64_t kReplayAdmitBatch = 2048;
+// A realtime replay that sleeps through an idle gap wakes this long (ns)
+// before the next arrival.
+constexpr uint64_t kReplaySleepMargin = 200000;
 
 struct STile {
   const uint64_t *keys;
@@ -674,10 +677,14 @@ sbbf_status sbbf_server_replay(sbbf_server *s, const sbbf_request *log, uint64_t
     if (next >= count && s->pending == 0 && s->inflight > 0) {
       if ((st = server_harvest(s, true)) != SBBF_OK) return st;
     } else if (s->pending == 0 && next < count) {
-      // idle until the next arrival; short sleeps keep completions timely
+      // Idle until the next arrival. A sleep can overshoot its deadline by
+      // tens of microseconds, and that delay lands on the request's latency,
+      // so the loop sleeps only through long idle gaps, waking well before
+      // the arrival, and polls through the rest.
       const uint64_t due = t0 + log[next].arrival_ns;
       const uint64_t now2 = now_ns();
-      if (due > now2 + 20000 && s->inflight == 0) std::this_thread::sleep_for(std::chrono::nanoseconds(due - now2 - 10000));
+      if (due > now2 + kReplaySleepMargin + 50000 && s->inflight == 0)
+        std::this_thread::sleep_for(std::chrono::nanoseconds(due - now2 - kReplaySleepMargin));
     }
   }
   return SBBF_OK;
