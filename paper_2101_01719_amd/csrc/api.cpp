@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -48,6 +49,21 @@ sbbf_status hip_error(hipError_t e, const char *what) {
 }
 
 void clear_error() { t_last_error.clear(); }
+
+bool fault_alloc() {
+  const char *v = getenv("SBBF_FAULT_INJECT");
+  return v != nullptr && strcmp(v, "alloc") == 0;
+}
+
+hipError_t dev_malloc(void **p, size_t bytes) { return fault_alloc() ? hipErrorOutOfMemory : hipMalloc(p, bytes); }
+
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t stream) {
+  return fault_alloc() ? hipErrorOutOfMemory : hipMallocAsync(p, bytes, stream);
+}
+
+hipError_t host_malloc_mapped(void **p, size_t bytes, unsigned int flags) {
+  return fault_alloc() ? hipErrorOutOfMemory : hipHostMalloc(p, bytes, flags);
+}
 
 const sbbf_device_info &device_info(int device) {
   std::lock_guard<std::mutex> lock(g_info_mu);
@@ -136,7 +152,11 @@ using namespace sbbf;
 extern "C" {
 
 const char *sbbf_status_string(sbbf_status s) {
-  switch (s) {
+  // A C caller may pass any integer; its bits are read as one, since loading
+  // an enumerator outside the enumeration's values is undefined in C++.
+  int v;
+  memcpy(&v, &s, sizeof(v));
+  switch (v) {
     case SBBF_OK: return "ok";
     case SBBF_EINVAL: return "invalid argument";
     case SBBF_ENOMEM: return "out of memory";
@@ -185,7 +205,7 @@ sbbf_status sbbf_create_variant(uint32_t num_blocks, uint32_t lanes, sbbf_filter
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
   void *p = nullptr;
   const size_t bytes = (size_t)filter_bytes(num_blocks, lanes);
-  e = hipMalloc(&p, bytes);
+  e = dev_malloc(&p, bytes);
   if (e != hipSuccess) return hip_error(e, "hipMalloc(filter)");
   e = hipMemset(p, 0, bytes);
   if (e != hipSuccess) {
@@ -251,6 +271,11 @@ uint32_t sbbf_lanes(const sbbf_filter *f) { return f ? f->lanes : 0; }
 // outside which the Poisson weight is far below double resolution.
 static double fpr_of_load(double a, uint32_t lanes = 8) {
   if (!(a > 0.0)) return 0.0;
+  // 1 - F(a) is at most K * E[(31/32)^i] = K * exp(-a / 32) under the Poisson
+  // load, below fp64's resolution of 1 from about 2,000 keys per block. Far
+  // above that the sum is not formed: its index would stop advancing in fp64
+  // (and an infinite load would never end the loop).
+  if (a > 1e6) return 1.0;
   const double w = 40.0 * std::sqrt(a) + 50.0;
   const double lo = std::max(1.0, std::floor(a - w)), hi = std::ceil(a + w);
   const double la = std::log(a), l = std::log(31.0 / 32.0);
@@ -503,7 +528,7 @@ static hipError_t workspace_alloc(void **p, size_t bytes, hipStream_t stream, in
       configured[device] = true;
     }
   }
-  return hipMallocAsync(p, bytes, stream);
+  return dev_malloc_async(p, bytes, stream);
 }
 
 // Insert of n hashes, or of n keys hashed on load (key_hash) when keys is 1.

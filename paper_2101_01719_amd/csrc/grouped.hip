@@ -899,12 +899,12 @@ sbbf_status grouped_build_plan(sbbf_group *g, const uint64_t *ins_cap, const uin
   if (!parts.empty()) memcpy(host.data() + o_pt, parts.data(), parts.size() * sizeof(GPart));
   if (!chunks.empty()) memcpy(host.data() + o_ch, chunks.data(), chunks.size() * sizeof(GChunk));
   if (!slices.empty()) memcpy(host.data() + o_sl, slices.data(), slices.size() * sizeof(GSlice));
-  hipError_t e = hipMalloc(&p.dev, total);
+  hipError_t e = dev_malloc(&p.dev, total);
   if (e != hipSuccess) return hip_error(e, "hipMalloc(grouped plan)");
   e = hipMemcpy(p.dev, host.data(), o_rn, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_error(e, "hipMemcpy(grouped plan)");
   if (part_keys) {
-    e = hipMalloc(&p.keys, part_keys * sizeof(uint64_t));
+    e = dev_malloc(&p.keys, part_keys * sizeof(uint64_t));
     if (e != hipSuccess) return hip_error(e, "hipMalloc(grouped partitioned keys)");
   }
   char *d = static_cast<char *>(p.dev);
@@ -1142,7 +1142,7 @@ static void digest_launch(const uint32_t *words, uint64_t n, unsigned long long 
 // Digest of all filters (in group order) and of the planned lookup outputs.
 static sbbf_status group_digest(sbbf_group *g, const uint8_t *d_out, hipStream_t s, uint64_t *digest) {
   unsigned long long *acc = nullptr;
-  hipError_t e = hipMallocAsync((void **)&acc, sizeof(unsigned long long) * 2, s);
+  hipError_t e = dev_malloc_async((void **)&acc, sizeof(unsigned long long) * 2, s);
   if (e != hipSuccess) return hip_error(e, "hipMallocAsync(digest)");
   hipLaunchKernelGGL(fill_kernel_u32, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(acc), 4u);
   unsigned long long h = 0x243f6a8885a308d3ull;
@@ -1467,7 +1467,7 @@ sbbf_status sbbf_grouped_autotune(sbbf_group *g, const uint64_t *d_ins, const ui
   uint64_t total = 0;
   for (auto *f : g->filters) total += (uint64_t)f->num_blocks * 32u;
   char *snap = nullptr;
-  e = hipMalloc((void **)&snap, total);
+  e = dev_malloc((void **)&snap, total);
   if (e != hipSuccess) {
     (void)hipStreamDestroy(s);
     return hip_error(e, "hipMalloc(autotune snapshot)");

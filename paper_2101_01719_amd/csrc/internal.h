@@ -28,6 +28,16 @@ struct Shape {
   uint32_t lanes;    // 32-bit words per block (8, or 4 or 16 for the block variants)
 };
 
+// Allocation-failure injection, for tests of the error paths: while the
+// environment variable SBBF_FAULT_INJECT is "alloc", every device, stream-
+// ordered or pinned host allocation the library makes fails with
+// hipErrorOutOfMemory (the call returns SBBF_ENOMEM) without being attempted.
+// These wrappers are the library's only allocation calls.
+bool fault_alloc();
+hipError_t dev_malloc(void **p, size_t bytes);
+hipError_t dev_malloc_async(void **p, size_t bytes, hipStream_t stream);
+hipError_t host_malloc_mapped(void **p, size_t bytes, unsigned int flags);
+
 // Cached device facts (per device, queried once).
 const sbbf_device_info &device_info(int device);
 const sbbf_device_info *current_device_info(sbbf_status *st);

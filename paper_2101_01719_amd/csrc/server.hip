@@ -201,7 +201,7 @@ struct Arena {
     const uint64_t size = std::max(bytes, std::min(chunk_bytes, budget - reserved));
     if (reserved + size > budget) return set_error(SBBF_EBUDGET, "HBM budget exhausted");
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, size);
+    hipError_t e = dev_malloc(&p, size);
     if (e != hipSuccess) return hip_error(e, "hipMalloc(arena chunk)");
     reserved += size;
     Chunk ch{static_cast<char *>(p), size, {}};
@@ -301,7 +301,7 @@ namespace {
 
 // A slot's tile table of `tiles` entries in mapped, coherent pinned memory.
 sbbf_status slot_alloc(Slot &sl, size_t tiles) {
-  hipError_t e = hipHostMalloc((void **)&sl.host, tiles * sizeof(STile), hipHostMallocMapped | hipHostMallocCoherent);
+  hipError_t e = host_malloc_mapped((void **)&sl.host, tiles * sizeof(STile), hipHostMallocMapped | hipHostMallocCoherent);
   if (e != hipSuccess) {
     sl.host = nullptr;
     return hip_error(e, "hipHostMalloc(server slot)");
