@@ -9,8 +9,9 @@
 //   count     workgroup g counts the keys of chunk g per slice -> hist[g][s]
 //   colsum    column sums of hist over blocks of 256 rows
 //   colscan   start[g][s] = sum of hist[< g][s]; tot[s] = sum over g
-//   offsets   offsets[s] = sum of round4(tot[< s]): slice s's keys begin at a
-//             multiple of four keys (32 bytes)
+//   offsets   offsets[s] = sum of tot[< s], each rounded up to a multiple of
+//             four keys for inserts (32 bytes) and of 32 for lookups (whole
+//             words of the result bitmap)
 //   scatter   workgroup g walks chunk g in tiles, sorts each tile by slice in
 //             LDS and writes each slice's run with consecutive lanes at the
 //             slice cursor offsets[s] + start[g][s] + (keys already written);
@@ -19,10 +20,22 @@
 //   slice     one workgroup per slice loads the slice into LDS; insert ORs the
 //             slice's keys into it and stores it back with plain stores,
 //             lookup tests the slice's keys against it and writes one result
-//             byte per key in partitioned order
-//   unpermute lookups only: workgroup g writes out[i] = result[pos[i]] for
-//             chunk g; each slice's results for chunk g are one contiguous
-//             run, read front to back
+//             bit per key in partitioned order
+//   unpermute lookups only: a workgroup takes up to eight consecutive chunks,
+//             gathers each chunk's results into an LDS bitmap (the runs of
+//             consecutive chunks in one slice are adjacent, so each slice's
+//             span is read once) and writes out[i] = result[pos[i]]
+//
+// Lookups into at most 2,048 slices skip count, colsum, colscan and offsets
+// (a read of the batch): scatter workgroup w writes its keys of slice s into
+// a bucket of fixed room, its chunks' runs one after another, and key i's
+// result position in its chunk is s * room + (its rank in the chunk's run),
+// so no prefix over the chunk is needed; the slice lookup walks a slice's
+// buckets, and the unpermute copies each run into its slot. Keys past a
+// run's room go to an overflow list that a gather pass looks up last
+// (skewed batches stay exact, only slower). Inserts into at most 2,048
+// slices likewise write fixed-room buckets without a count (overflowing keys
+// inserted with global atomics).
 //
 // No global atomics touch the filter or the partition. The partition order
 // is deterministic up to the order of equal-slice keys inside one tile, and a
@@ -54,6 +67,14 @@ constexpr uint32_t kSliceSteps = 2;    // 256-key steps per wave per slice-loop 
 // Lookup chunks are at most this many keys so that one chunk's result bytes
 // fit one workgroup's LDS in the unpermute kernel and positions fit 16 bits.
 constexpr uint32_t kLookupChunk = 65536u;
+// Lookup runs are padded to multiples of this many keys: a run's results are
+// whole 32-bit words of the result bitmap.
+constexpr uint32_t kLookupAlign = 32u;
+// Lookup chunks one unpermute workgroup restores (their result runs in a
+// slice are adjacent, so it reads each slice's runs as one span).
+constexpr uint32_t kUnpermuteChunks = 8u;
+// LDS of one bucketed-lookup unpermute workgroup (two per compute unit).
+constexpr size_t kUnpermuteLds = 78u << 10;
 
 __device__ __forceinline__ uint32_t slice_of(uint64_t h, uint32_t num_blocks, uint32_t slice_shift) {
   return block_of((uint32_t)(h >> 32), num_blocks) >> slice_shift;
@@ -159,16 +180,20 @@ part_colscan_kernel(const uint32_t *__restrict__ hist, uint32_t groups, uint32_t
   if (blockIdx.y == gridDim.y - 1u && seg == 15u) tot[col] = run;
 }
 
-// One workgroup: offsets[s] = sum of round4(tot[< s]); offsets[num_slices] is
-// the padded total. Thread t owns slices 4t .. 4t+3 (num_slices <= 4096).
+// One workgroup: offsets[s] = sum of round(tot[< s]) with every run rounded
+// up to a multiple of `align` keys (a power of two: 4 for inserts, so a slice
+// kernel reads a run with 16-byte loads; 32 for lookups, so a run's results
+// fill whole 32-bit words of the result bitmap); offsets[num_slices] is the
+// padded total. Thread t owns slices 4t .. 4t+3 (num_slices <= 4096).
 __global__ void __launch_bounds__(kPartThreads)
-part_offsets_kernel(const uint32_t *__restrict__ tot, uint32_t num_slices, uint32_t *__restrict__ offsets) {
+part_offsets_kernel(const uint32_t *__restrict__ tot, uint32_t num_slices, uint32_t align,
+                    uint32_t *__restrict__ offsets) {
   __shared__ uint32_t wsum[16];
   uint32_t c[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const uint32_t s = threadIdx.x * 4u + r;
-    c[r] = s < num_slices ? (tot[s] + 3u) & ~3u : 0u;
+    c[r] = s < num_slices ? (tot[s] + align - 1u) & ~(align - 1u) : 0u;
   }
   uint32_t run = block_scan_owned<4>(c, wsum);
 #pragma unroll
@@ -196,6 +221,9 @@ struct ScatterLds {
   uint32_t *hist;   // [P] keys per slice in the tile (ranks come from it)
   uint32_t *sbase;  // [P] staged position of the tile's first key of slice s
   uint32_t *pdelta; // [P] (lookups) chunk result position of staged position k is k + pdelta[s]
+  // [P] (bucketed lookups, in place of sbase and pdelta) (sbase, low 16 bits
+  // of pdelta | the rank from which the tile's keys of slice s overflow << 16)
+  uint2 *sp;
   uint32_t *wsum;   // [16]
 };
 
@@ -223,6 +251,11 @@ __device__ __forceinline__ void load_tile(const uint64_t *__restrict__ hashes, u
 template <int R>
 struct SliceCursor {
   uint32_t cursor[R], pbase[R], carry[R], carry_at[R];
+  // Bucketed lookups: where the current chunk's run must end (its result
+  // slots and the bucket's room). pbase = s * room + (the chunk's keys of the
+  // slice so far) and cursor = (the run's start) + the same count, so the
+  // run's start is cursor - (pbase - s * room).
+  uint32_t limit[R];
 };
 
 // Fixed-capacity buckets of the count-free insert partition. Scatter
@@ -233,17 +266,52 @@ struct SliceCursor {
 // its last key: a key inserted twice sets the same bits). Keys that find their
 // bucket full go to ovf (ovf_n of them, at most ovf_cap), which a
 // global-atomic pass inserts afterwards.
+//
+// Lookups (count-free lookup partition) use the same buckets, in which each
+// chunk of the workgroup's range continues the previous chunk's run. A key's
+// result position in its chunk is s * room + (its rank among the chunk's keys
+// of slice s), so positions need no count pass; a run keeps at most `room`
+// keys and stops at the bucket's end, and the keys past either limit go to
+// ovf_idx (their batch indices; a gather pass looks them up after the
+// unpermute). runs[c * P + s] = (first position, keys kept) of chunk c's run
+// in slice s.
 struct Buckets {
   uint32_t cap;
   uint32_t *count;
   uint64_t *ovf;
   uint32_t *ovf_n;
   uint32_t ovf_cap;
+  uint32_t room;
+  uint32_t *ovf_idx;
+  uint2 *runs;
 };
 
 // End (exclusive) of scatter workgroup g's bucket of slice s.
 __device__ __forceinline__ uint32_t bucket_end(uint32_t g, uint32_t s, uint32_t cap) {
   return (s * gridDim.x + g + 1u) * cap;
+}
+
+// Bucketed lookups, at a chunk boundary: record the finished chunk's runs
+// (prev, unless ~0u) and start the next chunk's runs where they ended (after
+// a spill, at the run's limit: no keys are carried then), each allowed
+// min(room, bucket room left) keys, result positions from s * room.
+template <int R>
+__device__ __forceinline__ void look_bucket_chunk(SliceCursor<R> &C, uint32_t num_slices, const Buckets &Bk,
+                                                  uint32_t prev) {
+  const uint32_t own = threadIdx.x * R;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t sl = own + r;
+    if (sl >= num_slices) continue;
+    const uint32_t end = min(C.cursor[r], C.limit[r]);
+    if (prev != ~0u) {
+      const uint32_t run_start = C.cursor[r] - (C.pbase[r] - sl * Bk.room);
+      Bk.runs[(uint64_t)prev * num_slices + sl] = make_uint2(run_start, end - run_start);
+    }
+    C.cursor[r] = end;
+    C.limit[r] = end + min(Bk.room, bucket_end(blockIdx.x, sl, Bk.cap) - end);
+    C.pbase[r] = sl * Bk.room;
+  }
 }
 
 // One tile of the scatter: rank every key within its slice (LDS atomics),
@@ -254,7 +322,8 @@ __device__ __forceinline__ uint32_t bucket_end(uint32_t g, uint32_t s, uint32_t 
 // inside the chunk (no per-key guards).
 template <bool kWithPos, int R, uint32_t L, bool kBucket, bool kFull>
 __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
-                                             const uint32_t *__restrict__ new_chunk_hist, uint32_t num_blocks,
+                                             const uint32_t *__restrict__ new_chunk_hist, uint32_t new_chunk,
+                                             uint32_t num_blocks,
                                              uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
                                              uint32_t keys,
                                              const ScatterLds &S, SliceCursor<R> &C, uint64_t *__restrict__ out_keys,
@@ -265,10 +334,14 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     for (uint32_t t = 0; t < kScatterPer; ++t) h[t] = key_hash(h[t]);
   }
   static_assert(L == 1u || R <= 2, "carried groups need at most two slices per thread");
-  static_assert(!kBucket || (L >= 4u && !kWithPos), "buckets are for inserts with carried groups");
+  static_assert(!kBucket || L >= 4u, "buckets are written with carried groups");
   constexpr uint32_t kCarryMax = L > 1u ? L - 1u : 1u;
   const uint32_t own = threadIdx.x * R;
-  if constexpr (kWithPos) {
+  if constexpr (kWithPos && kBucket) {
+    // First tile of a new chunk (new_chunk is uniform): close the previous
+    // chunk's runs.
+    if (new_chunk != ~0u) look_bucket_chunk<R>(C, num_slices, Bk, new_chunk - 1u);
+  } else if constexpr (kWithPos) {
     // First tile of a new chunk: positions restart at that chunk's slice
     // prefix (new_chunk_hist is its count row; it is uniform).
     if (new_chunk_hist != nullptr) {
@@ -300,8 +373,11 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     c[r] = sl < num_slices ? S.hist[sl] : 0u;
     if (sl < num_slices) S.hist[sl] = 0u;  // ready for the next tile (ranked after two more barriers)
     if constexpr (L > 1u) {
+      // (bucketed lookups keep the carried keys' staged position only in
+      // info[s].y, written with them: one register less per slice)
+      const uint32_t cat = kWithPos && kBucket ? (C.carry[r] ? S.info[sl].y : 0u) : C.carry_at[r];
 #pragma unroll
-      for (uint32_t j = 0; j < kCarryMax; ++j) carried[r][j] = j < C.carry[r] ? S.stage[C.carry_at[r] + j] : 0ull;
+      for (uint32_t j = 0; j < kCarryMax; ++j) carried[r][j] = j < C.carry[r] ? S.stage[cat + j] : 0ull;
     }
     m[r] = C.carry[r] + c[r];
   }
@@ -324,33 +400,62 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     // to its end and the rest of the run goes to the overflow list, uncarried.
     bool spill = false;
     if constexpr (kBucket) {
-      const uint32_t cap_end = bucket_end(blockIdx.x, sl, Bk.cap);
+      const uint32_t cap_end = kWithPos ? C.limit[r] : bucket_end(blockIdx.x, sl, Bk.cap);
       spill = end > cap_end;
       if (spill) aligned = cap_end;
     }
     const uint32_t wlen = aligned > first ? aligned - first : 0u;  // keys written by this tile
     if (sl < num_slices) {
       S.info[sl] = make_uint2(first - run, run + wlen);
-      S.sbase[sl] = run + C.carry[r];
-      if constexpr (kWithPos) S.pdelta[sl] = C.pbase[r] - (run + C.carry[r]);
+      const uint32_t sb = run + C.carry[r];
+      if constexpr (kWithPos && kBucket) {
+        // keys of rank >= limit - cursor (none if the run is already full)
+        // are past the run's limit
+        const uint32_t rlim = C.limit[r] > C.cursor[r] ? C.limit[r] - C.cursor[r] : 0u;
+        S.sp[sl] = make_uint2(sb, ((C.pbase[r] - sb) & 0xffffu) | (rlim << 16));
+      } else {
+        S.sbase[sl] = sb;
+        if constexpr (kWithPos) S.pdelta[sl] = C.pbase[r] - sb;
+      }
     }
     C.carry[r] = spill ? 0u : m[r] - wlen;
-    C.carry_at[r] = run + wlen;
+    if constexpr (!(kWithPos && kBucket)) C.carry_at[r] = run + wlen;
     C.cursor[r] = end;
     C.pbase[r] += c[r];
     run += m[r];
   }
   lds_barrier();
+  uint32_t ovm = 0;  // (bucketed lookups) this thread's keys past their run's limit
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
     if (kFull || i < e) {
-      const uint32_t k = S.sbase[s[t]] + rank[t];
-      S.stage[k] = h[t];
       // Positions are read back only by the unpermute kernel, after the
       // slice phase: stored non-temporally (3 % faster lookups on MI355X).
-      if constexpr (kWithPos) __builtin_nontemporal_store((uint16_t)(k + S.pdelta[s[t]]), out_pos + i);
+      if constexpr (kWithPos && kBucket) {
+        const uint2 sp = S.sp[s[t]];
+        const uint32_t k = sp.x + rank[t];
+        S.stage[k] = h[t];
+        const bool over = rank[t] >= (sp.y >> 16);  // past its run's limit
+        ovm |= over ? 1u << t : 0u;
+        // (an overflowing key takes any position of the chunk: the overflow
+        // pass rewrites its result)
+        const uint32_t p = over ? s[t] * Bk.room : (k + sp.y) & 0xffffu;
+        __builtin_nontemporal_store((uint16_t)p, out_pos + i);
+      } else {
+        const uint32_t k = S.sbase[s[t]] + rank[t];
+        S.stage[k] = h[t];
+        if constexpr (kWithPos) __builtin_nontemporal_store((uint16_t)(k + S.pdelta[s[t]]), out_pos + i);
+      }
     }
+  }
+  if constexpr (kWithPos && kBucket) {
+    // Overflowing keys (rare) to the list of the overflow pass.
+    for (uint32_t t = 0; ovm != 0u; ++t, ovm >>= 1)
+      if (ovm & 1u) {
+        const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (o < Bk.ovf_cap) Bk.ovf_idx[o] = t0 + t * kScatterThreads + threadIdx.x;
+      }
   }
   lds_barrier();
 #pragma unroll
@@ -362,7 +467,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
       const uint2 in = S.info[sl];
       if (L == 1u || k < in.y) {
         out_keys[k + in.x] = key;
-      } else if constexpr (kBucket) {
+      } else if constexpr (kBucket && !kWithPos) {
         // past the bucket's end: to the overflow list (carried keys are not)
         if (k + in.x >= bucket_end(blockIdx.x, sl, Bk.cap)) {
           const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -375,10 +480,11 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
   // before they are rewritten.
 }
 
-// Workgroup g partitions chunk g. For lookups it also writes, for every key i
-// of the chunk, the 16-bit position of its result inside the chunk's own
-// results (the chunk's runs of all slices laid end to end in slice order),
-// which is what the unpermute kernel reads back from LDS.
+// Workgroup g partitions chunks g * chunks_per_group onwards. For lookups it
+// also writes, for every key i of a chunk, the 16-bit position of its result
+// inside the chunk's own results, which is what the unpermute kernel reads
+// back from LDS: counted, the chunk's runs of all slices laid end to end in
+// slice order; bucketed, slot s of room positions for slice s.
 template <bool kWithPos, int R, uint32_t L, bool kBucket>
 __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t chunks_per_group,
@@ -394,6 +500,11 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   S.sbase = S.hist + num_slices;
   S.pdelta = S.sbase + num_slices;
   S.wsum = kWithPos ? S.pdelta + num_slices : S.pdelta;
+  if constexpr (kWithPos && kBucket) {  // info [P], sp [P] (8-byte aligned), hist [P], wsum
+    S.sp = S.info + num_slices;
+    S.hist = reinterpret_cast<uint32_t *>(S.sp + num_slices);
+    S.wsum = S.hist + num_slices;
+  }
 
   // This workgroup takes chunks u0 .. u0 + chunks_per_group - 1.
   const uint32_t u0 = blockIdx.x * chunks_per_group;
@@ -410,7 +521,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   }
 
   const uint32_t *my_start = kBucket ? nullptr : start + (uint64_t)u0 * num_slices;
-  const uint32_t *my_hist = kWithPos ? hist_rows + (uint64_t)u0 * num_slices : nullptr;
+  const uint32_t *my_hist = kWithPos && !kBucket ? hist_rows + (uint64_t)u0 * num_slices : nullptr;
   SliceCursor<R> C;
   uint32_t c[R];
 #pragma unroll
@@ -423,10 +534,13 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
     C.carry[r] = 0u;
     C.carry_at[r] = 0u;
     C.pbase[r] = 0u;
-    c[r] = kWithPos && sl < num_slices ? my_hist[sl] : 0u;
+    C.limit[r] = C.cursor[r];
+    c[r] = kWithPos && !kBucket && sl < num_slices ? my_hist[sl] : 0u;
     if (sl < num_slices) S.hist[sl] = 0u;
   }
-  if constexpr (kWithPos) {
+  if constexpr (kWithPos && kBucket) {
+    look_bucket_chunk<R>(C, num_slices, Bk, ~0u);
+  } else if constexpr (kWithPos) {
     uint32_t run = block_scan_owned<R, kScatterThreads>(c, S.wsum);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -444,8 +558,11 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   uint32_t t0 = b, k = 0;
 #define SBBF_SCATTER_TILE(FULL, H)                                                                            \
   scatter_tile<kWithPos, R, L, kBucket, FULL>(                                                                \
-      H, t0, e, kWithPos && t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * num_slices : nullptr, \
-      num_blocks, slice_shift, slice_base, num_slices, keys, S, C, out_keys, out_pos, Bk)
+      H, t0, e,                                                                                               \
+      kWithPos && !kBucket && t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * num_slices  \
+                                                          : nullptr,                                         \
+      kWithPos && kBucket && t0 != b && t0 % chunk == 0u ? t0 / chunk : ~0u, num_blocks, slice_shift,         \
+      slice_base, num_slices, keys, S, C, out_keys, out_pos, Bk)
   for (; k + 2u <= nfull; k += 2u) {
     load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
     SBBF_SCATTER_TILE(true, ha);
@@ -467,13 +584,26 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   // stage (nothing rewrites it after the last tile's staging barrier).
   if constexpr (L > 1u) {
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      for (uint32_t j = 0; j < C.carry[r]; ++j) out_keys[C.cursor[r] - C.carry[r] + j] = S.stage[C.carry_at[r] + j];
+    for (int r = 0; r < R; ++r) {
+      if (C.carry[r] == 0u) continue;
+      const uint32_t cat = kWithPos && kBucket ? S.info[own + r].y : C.carry_at[r];
+      for (uint32_t j = 0; j < C.carry[r]; ++j) out_keys[C.cursor[r] - C.carry[r] + j] = S.stage[cat + j];
+    }
   }
-  // Buckets: pad each to a multiple of four keys with copies of its last
-  // (carried) key and record its count. A bucket with no carry ends at a
-  // multiple of L (or is full), already a multiple of four.
-  if constexpr (kBucket) {
+  // Bucketed lookups: the last chunk's runs, and each bucket's key count.
+  if constexpr (kBucket && kWithPos) {
+    look_bucket_chunk<R>(C, num_slices, Bk, (e - 1u) / chunk);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t sl = own + r;
+      if (sl < num_slices)
+        Bk.count[sl * gridDim.x + blockIdx.x] = C.cursor[r] - (bucket_end(blockIdx.x, sl, Bk.cap) - Bk.cap);
+    }
+  }
+  // Bucketed inserts: pad each bucket to a multiple of four keys with copies
+  // of its last (carried) key and record its count. A bucket with no carry
+  // ends at a multiple of L (or is full), already a multiple of four.
+  if constexpr (kBucket && !kWithPos) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t sl = own + r;
@@ -520,9 +650,9 @@ __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *w
 // keys; lane l of a step takes keys 4l .. 4l+3. A lane whose group starts
 // past the slice's last key reads the last group instead (in bounds: the
 // padded run ends at a multiple of four keys), and keys at or past the
-// slice's count are masked: inserts OR a zero mask; lookups write a group's
-// result word in place when the group starts inside the slice and to a spare
-// word past the last run otherwise. Padding hashes
+// slice's count are masked: inserts OR a zero mask; lookups give them 0
+// bits in the slice's result words (a run starts at a multiple of 32 keys,
+// so its words are its own). Padding hashes
 // are arbitrary, so block indices are clamped into the slice before any LDS
 // access.
 // Index of this wave in its workgroup, as a wave-uniform (scalar) value so
@@ -577,11 +707,15 @@ __device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, u
 }
 
 // Test one step's keys against the slice in LDS (K/4 16-byte reads per key)
-// and write one result word (four result bytes) per group.
+// and write their results as bits: lane l's four keys give a nibble, lanes
+// 8m .. 8m+7 OR theirs into the word of keys base + 32m .. +31 (three lane
+// exchanges), which lane 8m stores when that word starts inside the slice.
+// begin and base are multiples of 32, so words are whole; keys at or past ns
+// give 0 bits.
 template <uint32_t K>
 __device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, uint32_t ns, uint32_t num_blocks,
                                             uint32_t b0, uint32_t nb, const uint4 *lds4, uint32_t begin,
-                                            uint32_t spare, uint32_t *__restrict__ res4) {
+                                            uint32_t *__restrict__ res32) {
   constexpr uint32_t V = K / 4u;  // 16-byte pieces per block
   const uint32_t lane = lane_id();
 #pragma unroll
@@ -603,9 +737,14 @@ __device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, u
       for (uint32_t q = 0; q < V; ++q)
         t &= (w[k][q].x >> bit_of(seed_k(4u * q), x)) & (w[k][q].y >> bit_of(seed_k(4u * q + 1u), x)) &
              (w[k][q].z >> bit_of(seed_k(4u * q + 2u), x)) & (w[k][q].w >> bit_of(seed_k(4u * q + 3u), x));
-      r |= (t & 1u) << (8u * k);
+      r |= (at + k < ns ? t & 1u : 0u) << k;
     }
-    res4[at < ns ? (begin + at) / 4u : spare] = r;
+    uint32_t word = r << (4u * (lane & 7u));
+    word |= (uint32_t)__shfl_xor((int)word, 1);
+    word |= (uint32_t)__shfl_xor((int)word, 2);
+    word |= (uint32_t)__shfl_xor((int)word, 4);
+    const uint32_t first = base + 256u * u + 32u * (lane >> 3);
+    if ((lane & 7u) == 0u && first < ns) res32[(begin + first) / 32u] = word;
   }
 }
 
@@ -779,6 +918,191 @@ part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__r
   for (uint32_t i = threadIdx.x; i < nb * (K / 4u); i += kPartThreads) dst4[i] = lds4[i];
 }
 
+// Bucketed lookups: a slice's buckets are walked as one sequence of 32-key
+// words, each bucket taking ceil(keys / 32) of them (wprefix[g]: words before
+// bucket g; the coarse map over words as for inserts), so that every result
+// word belongs to one bucket: the word of bucket g's keys 32o .. 32o+31 is
+// word (slice * G + g) * cap / 32 + o of the result bitmap (cap is a multiple
+// of 32). One step of a lane: four keys of a word per 256-position step, how
+// many of them are the bucket's (the rest are arbitrary bytes of its room,
+// read in bounds and masked) and the result word they belong to.
+struct BucketLookStep {
+  uint64_t h[kSliceSteps][4];
+  uint32_t valid[kSliceSteps];
+  uint32_t dw[kSliceSteps];
+};
+
+__device__ __forceinline__ void load_step_look_buckets(const uint64_t *__restrict__ part, uint32_t cap,
+                                                       const uint32_t *wprefix, const uint32_t *fill,
+                                                       const uint16_t *map, uint32_t map_shift, uint32_t base,
+                                                       uint32_t ns, uint32_t dw0, BucketLookStep &s) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t u = 0; u < kSliceSteps; ++u) {
+    const uint32_t v0 = base + 256u * u + 4u * lane;
+    const uint32_t v = min(v0, ns - 4u);
+    const uint32_t w = v >> 5;
+    const uint32_t m = w >> map_shift;
+    uint32_t lo = map[m], hi = map[m + 1u];
+    while (lo < hi) {  // largest g in [lo, hi] with wprefix[g] <= w
+      const uint32_t mid = (lo + hi + 1u) >> 1;
+      if (wprefix[mid] <= w)
+        lo = mid;
+      else
+        hi = mid - 1u;
+    }
+    const uint32_t o = w - wprefix[lo];
+    const uint32_t slot = 32u * o + (v & 31u);
+    const uint32_t f = fill[lo];
+    s.valid[u] = v0 < ns && f > slot ? min(4u, f - slot) : 0u;
+    s.dw[u] = dw0 + lo * (cap / 32u) + o;
+    const u64x2 *p = reinterpret_cast<const u64x2 *>(part + (uint64_t)lo * cap + slot);
+    const u64x2 a = p[0];  // through the caches, as the counted slice lookup
+    const u64x2 b = p[1];
+    s.h[u][0] = a.x;
+    s.h[u][1] = a.y;
+    s.h[u][2] = b.x;
+    s.h[u][3] = b.y;
+  }
+}
+
+template <uint32_t K>
+__device__ __forceinline__ void bucket_lookup_step(const BucketLookStep &s, uint32_t base, uint32_t ns,
+                                                   uint32_t num_blocks, uint32_t b0, uint32_t nb, const uint4 *lds4,
+                                                   uint32_t *__restrict__ res32) {
+  constexpr uint32_t V = K / 4u;
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t u = 0; u < kSliceSteps; ++u) {
+    uint4 w[4][V];
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+      const uint32_t bl = min(block_of((uint32_t)(s.h[u][k] >> 32), num_blocks) - b0, nb - 1u);
+#pragma unroll
+      for (uint32_t q = 0; q < V; ++q) w[k][q] = lds4[V * bl + q];
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+      const uint32_t x = (uint32_t)s.h[u][k];
+      uint32_t t = 1u;
+#pragma unroll
+      for (uint32_t q = 0; q < V; ++q)
+        t &= (w[k][q].x >> bit_of(seed_k(4u * q), x)) & (w[k][q].y >> bit_of(seed_k(4u * q + 1u), x)) &
+             (w[k][q].z >> bit_of(seed_k(4u * q + 2u), x)) & (w[k][q].w >> bit_of(seed_k(4u * q + 3u), x));
+      r |= (k < s.valid[u] ? t & 1u : 0u) << k;
+    }
+    uint32_t word = r << (4u * (lane & 7u));
+    word |= (uint32_t)__shfl_xor((int)word, 1);
+    word |= (uint32_t)__shfl_xor((int)word, 2);
+    word |= (uint32_t)__shfl_xor((int)word, 4);
+    const uint32_t first = base + 256u * u + 32u * (lane >> 3);
+    if ((lane & 7u) == 0u && first < ns) res32[s.dw[u]] = word;
+  }
+}
+
+// Slice lookup over the buckets of a count-free lookup partition: the slice
+// in LDS, the buckets' word counts scanned into a prefix and a coarse map
+// after it, then the slice loop over the words of all buckets.
+template <uint32_t K>
+__global__ void __launch_bounds__(kPartThreads)
+part_bucket_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ counts, uint32_t groups,
+                          uint32_t cap, const uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift,
+                          uint32_t slice_base, uint32_t *__restrict__ res32) {
+  extern __shared__ uint4 lds4[];
+  const uint32_t slice = blockIdx.x;
+  const uint32_t b0 = (slice_base + slice) << slice_shift;
+  const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
+  // after the largest slice: wprefix [kMaxBucketGroups + 1], fill [kMaxBucketGroups],
+  // map [kBucketMap + 1], wsum [16]
+  uint32_t *wprefix = reinterpret_cast<uint32_t *>(lds4 + (((size_t)1 << slice_shift) * K) / 4u);
+  uint32_t *fill = wprefix + kMaxBucketGroups + 1u;
+  uint16_t *map = reinterpret_cast<uint16_t *>(fill + kMaxBucketGroups);
+  uint32_t *wsum = fill + kMaxBucketGroups + (kBucketMap + 2u) / 2u;
+  const uint32_t cnt = threadIdx.x < groups ? counts[(uint64_t)slice * groups + threadIdx.x] : 0u;
+  const u64x2 *src = reinterpret_cast<const u64x2 *>(words + (uint64_t)b0 * K);
+  const uint32_t count4 = nb * (K / 4u);
+  u64x2 q[8];
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    q[u] = i < count4 ? __builtin_nontemporal_load(src + i) : u64x2{0ull, 0ull};
+  }
+  uint32_t start, nw;
+  {
+    const uint32_t c[1] = {(cnt + 31u) / 32u};
+    start = block_scan_owned<1>(c, wsum, &nw);
+  }
+  if (nw == 0) return;  // whole workgroup: no keys in this slice
+  uint32_t map_shift = 0;
+  while (((nw - 1u) >> map_shift) + 1u > kBucketMap) ++map_shift;
+  const uint32_t entries = ((nw - 1u) >> map_shift) + 1u;
+  if (threadIdx.x < groups) {
+    wprefix[threadIdx.x] = start;
+    fill[threadIdx.x] = cnt;
+    const uint32_t wc = (cnt + 31u) / 32u;
+    for (uint32_t m = (start + (1u << map_shift) - 1u) >> map_shift; (m << map_shift) < start + wc; ++m)
+      map[m] = (uint16_t)threadIdx.x;
+  }
+  if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    if (i < count4) lds4[i] = make_uint4((uint32_t)q[u].x, (uint32_t)(q[u].x >> 32), (uint32_t)q[u].y,
+                                         (uint32_t)(q[u].y >> 32));
+  }
+  __syncthreads();
+
+  const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
+  const uint32_t dw0 = (uint32_t)(((uint64_t)slice * groups * cap) / 32u);
+  const uint32_t ns = 32u * nw;
+  constexpr uint32_t waves = kPartThreads / kWave;
+  constexpr uint32_t stride = waves * 256u * kSliceSteps;
+  uint32_t base = wave_index() * 256u * kSliceSteps;
+  const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
+  BucketLookStep sa, sb;
+  load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base, ns, dw0, sa);
+  for (uint32_t it = 0; it < steps; it += 2u) {
+    load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base + stride, ns, dw0, sb);
+    __builtin_amdgcn_sched_barrier(0);
+    bucket_lookup_step<K>(sa, base, ns, num_blocks, b0, nb, lds4, res32);
+    base += stride;
+    load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base + stride, ns, dw0, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    bucket_lookup_step<K>(sb, base, ns, num_blocks, b0, nb, lds4, res32);
+    base += stride;
+  }
+}
+
+// Bucketed lookups whose run was full: each key looked up directly in the
+// filter (a gather), its result stored over what the unpermute wrote (bits:
+// one atomic set or clear per key, the unpermute having written whole words).
+template <uint32_t K>
+__global__ void __launch_bounds__(256)
+part_overflow_lookup_kernel(const uint64_t *__restrict__ hashes, uint32_t keys, const uint32_t *__restrict__ ovf_idx,
+                            const uint32_t *__restrict__ ovf_n, uint32_t ovf_cap, const uint32_t *__restrict__ words,
+                            uint32_t num_blocks, uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
+  const uint32_t n = min(*ovf_n, ovf_cap);
+  for (uint32_t j = blockIdx.x * 256u + threadIdx.x; j < n; j += gridDim.x * 256u) {
+    const uint32_t i = ovf_idx[j];
+    uint64_t h = hashes[i];
+    if (keys) h = key_hash(h);
+    const uint32_t x = (uint32_t)h;
+    const uint32_t *blk = words + (uint64_t)block_of((uint32_t)(h >> 32), num_blocks) * K;
+    uint32_t t = 1u;
+#pragma unroll
+    for (uint32_t w = 0; w < K; ++w) t &= blk[w] >> bit_of(seed_k(w), x);
+    t &= 1u;
+    if (out8) {
+      out8[i] = (uint8_t)t;
+    } else if (t) {
+      __hip_atomic_fetch_or(out_bits + i / 32u, 1u << (i & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_fetch_and(out_bits + i / 32u, ~(1u << (i & 31u)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // Keys that found their bucket full, inserted with global atomics after the
 // slice inserts (ovf_n of them; usually none).
 template <uint32_t K>
@@ -800,7 +1124,7 @@ template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ offsets,
                          const uint32_t *__restrict__ tot, const uint32_t *__restrict__ words, uint32_t num_blocks,
-                         uint32_t slice_shift, uint32_t slice_base, uint8_t *__restrict__ res) {
+                         uint32_t slice_shift, uint32_t slice_base, uint32_t *__restrict__ res32) {
   extern __shared__ uint4 lds4[];
   const uint32_t slice = blockIdx.x;
   const uint32_t ns = tot[slice];
@@ -810,169 +1134,307 @@ part_slice_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   load_slice_to_lds<K>(lds4, words, b0, nb);
   __syncthreads();
 
-  const uint32_t begin = offsets[slice];
+  const uint32_t begin = offsets[slice];  // a multiple of 32
   const uint64_t *keys = part + begin;
-  uint32_t *res4 = reinterpret_cast<uint32_t *>(res);  // begin and the padded total are multiples of 4
-  // Lanes whose group starts past the slice write their word to the spare
-  // word after the last slice's run (never read), so stores need no branch.
-  const uint32_t spare = offsets[gridDim.x] / 4u;
   const uint32_t last = ((ns + 3u) & ~3u) - 4u;
   constexpr uint32_t waves = kPartThreads / kWave;
   constexpr bool kCachedKeys = true;
-#define SBBF_LOOKUP_STEP(S, BASE) lookup_step<K>(S, BASE, ns, num_blocks, b0, nb, lds4, begin, spare, res4)
+#define SBBF_LOOKUP_STEP(S, BASE) lookup_step<K>(S, BASE, ns, num_blocks, b0, nb, lds4, begin, res32)
   SBBF_SLICE_LOOP(SBBF_LOOKUP_STEP);
 #undef SBBF_LOOKUP_STEP
 }
 #undef SBBF_SLICE_LOOP
 
-// Workgroup g restores input order for chunk g: it copies the chunk's result
-// run of every slice (res[offsets[s] + start[g][s] ...], hist[g][s] bytes)
-// into LDS end to end in slice order, then writes out[i] = lds[pos[i]] for
-// the chunk, as bytes or packed bits (LSB-first).
-template <bool kBits>
-__global__ void __launch_bounds__(kPartThreads, 8)  // 8 waves per SIMD: two workgroups per CU
-part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint8_t *__restrict__ res,
-                      const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
-                      const uint32_t *__restrict__ hist_rows, uint32_t num_slices, uint32_t n, uint32_t chunk,
-                      uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
-  extern __shared__ uint32_t usmem[];
-  uint32_t *local = usmem;                                 // [num_slices] run start among the chunk's results
-  uint32_t *src = local + num_slices;                      // [num_slices] run start in res (byte index)
-  uint32_t *wsum = src + num_slices;                       // [16]
-  uint8_t *vals = reinterpret_cast<uint8_t *>(wsum + 16);  // [chunk]
-  const uint32_t *row = hist_rows + (uint64_t)blockIdx.x * num_slices;
-  const uint32_t *my_start = start + (uint64_t)blockIdx.x * num_slices;
-  {
-    uint32_t c[4], at[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t s = threadIdx.x * 4u + r;
-      c[r] = s < num_slices ? row[s] : 0u;
-      at[r] = s < num_slices ? offsets[s] + my_start[s] : 0u;
-    }
-    uint32_t run = block_scan_owned<4>(c, wsum);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const uint32_t s = threadIdx.x * 4u + r;
-      if (s < num_slices) {
-        local[s] = run;
-        src[s] = at[r];
-      }
-      run += c[r];
+// Copy `len` bits of the result bitmap res32, from bit `from`, into the LDS
+// bitmap dst from bit `to` (LDS ORs: a destination word can hold the ends of
+// two runs). res32 has two words of padding after its last bit, so the word
+// after a piece's first word can always be read.
+__device__ __forceinline__ void copy_bits(const uint32_t *__restrict__ res32, uint32_t from, uint32_t len,
+                                          uint32_t *dst, uint32_t to) {
+  for (uint32_t i = 0; i < len; i += 32u) {
+    const uint32_t nbits = min(32u, len - i);
+    const uint32_t src = from + i, sw = src >> 5, ss = src & 31u;
+    const uint32_t w0 = res32[sw], w1 = res32[sw + 1u];
+    uint32_t v = ss ? (w0 >> ss) | (w1 << (32u - ss)) : w0;
+    if (nbits < 32u) v &= (1u << nbits) - 1u;
+    const uint32_t d = to + i, dw = d >> 5, ds = d & 31u;
+    if (v) {
+      __hip_atomic_fetch_or(dst + dw, v << ds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (ds && ds + nbits > 32u)
+        __hip_atomic_fetch_or(dst + dw + 1u, v >> (32u - ds), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
-  __syncthreads();
-  // Phase 1: each group of 16 lanes copies the runs of slices q, q + 64, ...
-  // with aligned 8-byte loads and byte stores into LDS. The first 128 bytes
-  // of four runs are loaded back to back; the rest of a longer run (rare:
-  // runs average one result per block of the slice) follows in a loop. res
-  // has at least 8 bytes of padding after its last byte, so the last word
-  // of a run is always inside the workspace.
+}
+
+// Output phase of the unpermute kernels. A workgroup's chunks c0 .. c0 + nc
+// - 1 are the consecutive keys [b, e); chunk c0 + j's results are bitmap j
+// of `maps` (map_words words each) in LDS, and key i takes bit pos[i] of its
+// chunk's bitmap; written as bytes or packed bits (LSB-first). Positions are
+// read kUnpermuteIter steps at a time, the next iteration's loads issued
+// before this one's results are written; the first iteration's are issued by
+// unpermute_load before the kernel fills its bitmaps.
+constexpr uint32_t kUnpermuteIter = 4u;
+
+struct UnpermuteRange {
   uint32_t b, e;
-  chunk_range(blockIdx.x, chunk, n, &b, &e);
-  const uint32_t chunk_keys = e - b;
-  const uint64_t *res8 = reinterpret_cast<const uint64_t *>(res);
-  const uint32_t lane16 = threadIdx.x & 15u;
-  constexpr uint32_t kGroups = kPartThreads / 16u;
-  constexpr uint32_t kBatch = 4;
-  auto put = [&](uint64_t v, uint32_t w, uint32_t from, uint32_t len, uint8_t *dst) {
+};
+
+__device__ __forceinline__ UnpermuteRange unpermute_range(uint32_t c0, uint32_t nc, uint32_t chunk, uint32_t n) {
+  const uint32_t b = c0 * chunk;
+  return UnpermuteRange{b, min(b + nc * chunk, n)};
+}
+
+// Bytes: thread t takes keys i0 + 4t + u * 4T .. +3 (T threads, u <
+// kUnpermuteIter) of an iteration; bits: wave w takes the 256-key spans i0 +
+// 256w + u * 256W (W waves), four keys per lane. i0 starts at b.
+template <bool kBits>
+__device__ __forceinline__ uint32_t unpermute_first(const UnpermuteRange &r) {
+  return kBits ? r.b + (threadIdx.x >> 6) * 256u + 4u * (threadIdx.x & 63u) : r.b + 4u * threadIdx.x;
+}
+
+__device__ __forceinline__ void unpermute_load(const uint16_t *__restrict__ pos, uint32_t i, uint32_t e,
+                                               uint2 (&p2)[kUnpermuteIter]) {
+  constexpr uint32_t kStep = 4u * kPartThreads;  // keys per step, either layout
 #pragma unroll
-    for (uint32_t by = 0; by < 8u; ++by) {
-      const uint32_t at = w * 8u + by;  // byte index into res
-      if (at >= from && at < from + len) dst[at - from] = (uint8_t)(v >> (8u * by));
-    }
-  };
-  for (uint32_t sl0 = threadIdx.x >> 4; sl0 < num_slices; sl0 += kBatch * kGroups) {
-    uint64_t v[kBatch];
-    uint32_t from[kBatch], len[kBatch], w[kBatch];
-#pragma unroll
-    for (uint32_t u = 0; u < kBatch; ++u) {
-      const uint32_t sl = sl0 + u * kGroups;
-      const bool ok = sl < num_slices;
-      from[u] = ok ? src[sl] : 0u;
-      len[u] = ok ? (sl + 1u < num_slices ? local[sl + 1u] : chunk_keys) - local[sl] : 0u;
-      w[u] = (from[u] >> 3) + lane16;
-      v[u] = w[u] < ((from[u] + len[u] + 7u) >> 3) ? res8[w[u]] : 0ull;
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kBatch; ++u) {
-      const uint32_t sl = sl0 + u * kGroups;
-      if (sl >= num_slices) continue;
-      uint8_t *dst = vals + local[sl];
-      const uint32_t w_end = (from[u] + len[u] + 7u) >> 3;
-      if (w[u] < w_end) put(v[u], w[u], from[u], len[u], dst);
-      for (uint32_t ww = w[u] + 16u; ww < w_end; ww += 16u) put(res8[ww], ww, from[u], len[u], dst);
-    }
+  for (uint32_t u = 0; u < kUnpermuteIter; ++u) {
+    const uint32_t k = i + u * kStep;
+    p2[u] = k + 4u <= e ? *reinterpret_cast<const uint2 *>(pos + k) : make_uint2(0u, 0u);
   }
-  __syncthreads();
+}
+
+template <bool kBits>
+__device__ __forceinline__ void unpermute_write(const uint32_t *maps, uint32_t map_words,
+                                                const uint16_t *__restrict__ pos, const UnpermuteRange &r,
+                                                uint32_t chunk, uint2 (&cur)[kUnpermuteIter],
+                                                uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
+  constexpr uint32_t kStep = 4u * kPartThreads;
+  const uint32_t b = r.b, e = r.e;
+  // the bitmap of key i's chunk (four keys of a thread, or a wave's span of
+  // 256, lie in one chunk: chunks are multiples of 256 keys)
+  auto bitmap = [&](uint32_t i) {
+    const uint32_t x = i - b;
+    uint32_t j = 0;
+#pragma unroll
+    for (uint32_t u = 1; u < kUnpermuteChunks; ++u) j += x >= u * chunk ? 1u : 0u;
+    return maps + j * map_words;
+  };
+  auto bit = [](const uint32_t *vals, uint32_t p) { return (vals[p >> 5] >> (p & 31u)) & 1u; };
   const uint32_t lane = threadIdx.x & 63u;
-  if constexpr (!kBits) {
-    // Phase 2 (bytes): four consecutive positions per thread and step, four
-    // steps per iteration; b is a multiple of 4.
-    const bool aligned4 = ((uintptr_t)out8 & 3u) == 0;
-    constexpr uint32_t kStep = 4u * kPartThreads;
-    for (uint32_t i0 = b + 4u * threadIdx.x; i0 < e; i0 += 4u * kStep) {
-      uint2 p2[4];
+  const bool aligned4 = ((uintptr_t)out8 & 3u) == 0;
+  // (bits: the loop test is on the wave's span start, wave-uniform)
+  for (uint32_t i0 = unpermute_first<kBits>(r); i0 - (kBits ? 4u * lane : 0u) < e; i0 += kUnpermuteIter * kStep) {
+    uint2 nxt[kUnpermuteIter];
+    unpermute_load(pos, i0 + kUnpermuteIter * kStep, e, nxt);
 #pragma unroll
-      for (uint32_t u = 0; u < 4u; ++u) {
-        const uint32_t i = i0 + u * kStep;
-        p2[u] = i + 4u <= e ? *reinterpret_cast<const uint2 *>(pos + i) : make_uint2(0u, 0u);
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < 4u; ++u) {
-        const uint32_t i = i0 + u * kStep;
+    for (uint32_t u = 0; u < kUnpermuteIter; ++u) {
+      const uint32_t i = i0 + u * kStep;
+      if constexpr (!kBits) {
         if (i + 4u <= e) {
-          const uint32_t word = (uint32_t)vals[p2[u].x & 0xffffu] | ((uint32_t)vals[p2[u].x >> 16] << 8) |
-                                ((uint32_t)vals[p2[u].y & 0xffffu] << 16) | ((uint32_t)vals[p2[u].y >> 16] << 24);
+          const uint32_t *vals = bitmap(i);
+          const uint32_t word = bit(vals, cur[u].x & 0xffffu) | (bit(vals, cur[u].x >> 16) << 8) |
+                                (bit(vals, cur[u].y & 0xffffu) << 16) | (bit(vals, cur[u].y >> 16) << 24);
           if (aligned4) {
             *reinterpret_cast<uint32_t *>(out8 + i) = word;
           } else {
             for (uint32_t k = 0; k < 4u; ++k) out8[i + k] = (uint8_t)(word >> (8u * k));
           }
         } else {
-          for (uint32_t k = i; k < e; ++k) out8[k] = vals[pos[k]];
+          for (uint32_t k = i; k < e; ++k) out8[k] = (uint8_t)bit(bitmap(k), pos[k]);
+        }
+      } else {
+        // Lanes 8w .. 8w+7 OR their nibbles into the word of keys span +
+        // 32w .. +31, which lane 8w stores when it starts before e (the span
+        // starts at a multiple of 256, so words are whole; keys at or past e
+        // give 0 bits).
+        const uint32_t span = i - 4u * lane;
+        if (span < e) {  // wave-uniform
+          const uint32_t *vals = bitmap(span);
+          uint32_t nib = 0;
+          if (i + 4u <= e) {
+            nib = bit(vals, cur[u].x & 0xffffu) | (bit(vals, cur[u].x >> 16) << 1) |
+                  (bit(vals, cur[u].y & 0xffffu) << 2) | (bit(vals, cur[u].y >> 16) << 3);
+          } else {
+            for (uint32_t k = 0; k < 4u; ++k)
+              if (i + k < e) nib |= bit(vals, pos[i + k]) << k;
+          }
+          uint32_t w = nib << (4u * (lane & 7u));
+          w |= (uint32_t)__shfl_xor((int)w, 1);
+          w |= (uint32_t)__shfl_xor((int)w, 2);
+          w |= (uint32_t)__shfl_xor((int)w, 4);
+          const uint32_t first = span + 32u * (lane >> 3);
+          if ((lane & 7u) == 0 && first < e) out_bits[first / 32u] = w;
         }
       }
     }
-  } else {
-    // Phase 2 (bits): a wave takes 256 positions per step, four consecutive
-    // ones per lane (one 8-byte load of positions), as a nibble; lanes 8w ..
-    // 8w+7 OR their nibbles into the word of positions i0 + 32w .. +31, which
-    // lane 8w stores. i0 is a multiple of 256 (chunks start at multiples of
-    // the 7,168-key tile), so words are whole; positions at or past e give 0
-    // bits, and a word is stored only when it starts before e.
-    constexpr uint32_t kWaveSpan = 256u;
-    const uint32_t wave = threadIdx.x >> 6;
-    for (uint32_t i0 = b + wave * kWaveSpan; i0 < e; i0 += (kPartThreads / 64u) * kWaveSpan) {
-      const uint32_t i = i0 + 4u * lane;
-      uint32_t nib = 0;
-      if (i + 4u <= e) {
-        const uint2 p2 = *reinterpret_cast<const uint2 *>(pos + i);
-        nib = (uint32_t)(vals[p2.x & 0xffffu] != 0) | ((uint32_t)(vals[p2.x >> 16] != 0) << 1) |
-              ((uint32_t)(vals[p2.y & 0xffffu] != 0) << 2) | ((uint32_t)(vals[p2.y >> 16] != 0) << 3);
-      } else {
-        for (uint32_t k = 0; k < 4u; ++k)
-          if (i + k < e) nib |= (uint32_t)(vals[pos[i + k]] != 0) << k;
-      }
-      uint32_t w = nib << (4u * (lane & 7u));
-      w |= (uint32_t)__shfl_xor((int)w, 1);
-      w |= (uint32_t)__shfl_xor((int)w, 2);
-      w |= (uint32_t)__shfl_xor((int)w, 4);
-      const uint32_t start = i0 + 32u * (lane >> 3);
-      if ((lane & 7u) == 0 && start < e) out_bits[start / 32u] = w;
-    }
+#pragma unroll
+    for (uint32_t u = 0; u < kUnpermuteIter; ++u) cur[u] = nxt[u];
   }
+}
+
+// Workgroup w restores input order for chunks c0 .. c0 + per - 1 (c0 =
+// w * per, per at most kUnpermuteChunks). The results are a bitmap in partitioned order:
+// chunk c's results in slice s are bits [offsets[s] + start[c][s], ...
+// + hist[c][s]), so the runs of consecutive chunks in one slice are adjacent
+// and the workgroup reads each slice's span of runs once (a few words where
+// the byte results of one chunk's run took as many 128-byte lines). Pass j
+// (chunk c0 + j): the chunk's slice counts are scanned into each run's place
+// among the chunk's results, and the thread owning slice s copies the run's
+// bits into chunk j's LDS bitmap there. Then every chunk writes out[i] =
+// bit pos[i] of its bitmap for its keys, as bytes or packed bits (LSB-first).
+template <bool kBits>
+__global__ void __launch_bounds__(kPartThreads, 8)  // 8 waves per SIMD: two workgroups per CU
+part_unpermute_kernel(const uint16_t *__restrict__ pos, const uint32_t *__restrict__ res32,
+                      const uint32_t *__restrict__ offsets, const uint32_t *__restrict__ start,
+                      const uint32_t *__restrict__ hist_rows, uint32_t num_slices, uint32_t n, uint32_t chunk,
+                      uint32_t groups, uint32_t per, uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
+  extern __shared__ uint32_t usmem[];
+  uint32_t *wsum = usmem;        // [2][16]: the scans of consecutive passes alternate
+  uint32_t *maps = usmem + 32;   // [per][chunk / 32] result bits of each chunk
+  const uint32_t map_words = chunk / 32u;  // chunk is a multiple of the 7,168-key tile
+  const uint32_t c0 = blockIdx.x * per;
+  const uint32_t nc = min(per, groups - c0);
+  const UnpermuteRange ur = unpermute_range(c0, nc, chunk, n);
+  uint2 first[kUnpermuteIter];
+  unpermute_load(pos, unpermute_first<kBits>(ur), ur.e, first);
+  for (uint32_t i = threadIdx.x; i < nc * map_words; i += kPartThreads) maps[i] = 0u;
+  // Thread t owns slices t * R .. t * R + R - 1; cursor: the bit where its
+  // slice's run of the current chunk starts.
+  constexpr uint32_t R = kMaxSlices / kPartThreads;
+  uint32_t cursor[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t sl = threadIdx.x * R + r;
+    cursor[r] = sl < num_slices ? offsets[sl] + start[(uint64_t)c0 * num_slices + sl] : 0u;
+  }
+  // Slice counts of chunk j in c[], of chunk j + 1 loaded during pass j.
+  auto load_row = [&](uint32_t j, uint32_t (&c)[R]) {
+    const uint32_t *row = hist_rows + (uint64_t)(c0 + j) * num_slices;
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+      const uint32_t sl = threadIdx.x * R + r;
+      c[r] = sl < num_slices && j < nc ? row[sl] : 0u;
+    }
+  };
+  uint32_t c[R], next[R];
+  load_row(0, c);
+  __syncthreads();
+  for (uint32_t j = 0; j < nc; ++j) {
+    load_row(j + 1u, next);
+    // place of the run among chunk j's results
+    uint32_t at = block_scan_owned<R, kPartThreads>(c, wsum + 16u * (j & 1u));
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+      if (c[r]) copy_bits(res32, cursor[r], c[r], maps + j * map_words, at);
+      at += c[r];
+      cursor[r] += c[r];
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) c[r] = next[r];
+  }
+  __syncthreads();
+  unpermute_write<kBits>(maps, map_words, pos, ur, chunk, first, out8, out_bits);
+}
+
+// Unpermute of a count-free lookup partition. Scatter workgroup g's chunks
+// (per_s of them from g * per_s) are split among upw = ceil(per_s / per_u)
+// workgroups of at most per_u consecutive chunks, so the runs of a workgroup's
+// chunks in one slice follow each other in one bucket: runs[c][s] = (first
+// bit, length) in the result bitmap res32, contiguous for consecutive chunks
+// c of one scatter workgroup. Chunk j's LDS bitmap holds num_slices slots of
+// room = 2^room_shift bits (at least 32: whole words), slot s the bits of its
+// run in slice s and zeros after them. First a thread per slice reads its
+// runs (coalesced rows) into the slice's record: the word of the first run's
+// first bit and each run's bit offset from it (16-bit); then the slots are
+// filled slice by slice, so the lanes of a wave read one or two windows of a
+// few words of res32 rather than a line per lane.
+template <bool kBits>
+__global__ void __launch_bounds__(kPartThreads, 8)  // 8 waves per SIMD: two workgroups per CU
+part_unpermute_buckets_kernel(const uint16_t *__restrict__ pos, const uint32_t *__restrict__ res32,
+                              const uint2 *__restrict__ runs, uint32_t num_slices, uint32_t room_shift, uint32_t n,
+                              uint32_t chunk, uint32_t groups, uint32_t per_s, uint32_t per_u,
+                              uint8_t *__restrict__ out8, uint32_t *__restrict__ out_bits) {
+  extern __shared__ uint32_t usmem[];
+  const uint32_t upw = (per_s + per_u - 1u) / per_u;
+  const uint32_t sg = blockIdx.x / upw, part = blockIdx.x - sg * upw;
+  const uint32_t c0 = sg * per_s + part * per_u;
+  if (c0 >= groups) return;  // whole workgroup (the last scatter workgroup may have fewer chunks)
+  const uint32_t nc = min(min(per_u, per_s - part * per_u), groups - c0);
+  const uint32_t slot_shift = room_shift - 5u;  // words per slot: 2^slot_shift
+  const uint32_t map_words = num_slices << slot_shift;
+  uint32_t *maps = usmem;                            // [per_u][map_words]
+  uint32_t *first_word = maps + per_u * map_words;   // [num_slices]
+  uint16_t *pre = reinterpret_cast<uint16_t *>(first_word + num_slices);  // [num_slices][per_u + 1]
+  const uint32_t rec = per_u + 1u;
+  const UnpermuteRange ur = unpermute_range(c0, nc, chunk, n);
+  uint2 first[kUnpermuteIter];
+  unpermute_load(pos, unpermute_first<kBits>(ur), ur.e, first);
+  for (uint32_t sl = threadIdx.x; sl < num_slices; sl += kPartThreads) {
+    uint32_t len[kUnpermuteChunks];
+    uint32_t s0 = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kUnpermuteChunks; ++j) {
+      len[j] = 0u;
+      if (j < nc) {
+        const uint2 r = runs[(uint64_t)(c0 + j) * num_slices + sl];
+        if (j == 0) s0 = r.x;
+        len[j] = r.y;
+      }
+    }
+    uint32_t at = s0 & 31u;
+#pragma unroll
+    for (uint32_t j = 0; j < kUnpermuteChunks; ++j) {
+      if (j < nc) {
+        pre[sl * rec + j] = (uint16_t)at;
+        at += len[j];
+      }
+    }
+    pre[sl * rec + nc] = (uint16_t)at;
+    first_word[sl] = s0 >> 5;
+  }
+  __syncthreads();
+  const uint32_t per_slice = nc << slot_shift;  // words of one slice's slots over the chunks
+  const uint32_t total = num_slices * per_slice;
+  constexpr uint32_t kIn = 4u;
+  for (uint32_t x0 = threadIdx.x; x0 < total; x0 += kIn * kPartThreads) {
+    uint32_t v[kIn], dst[kIn];
+#pragma unroll
+    for (uint32_t u = 0; u < kIn; ++u) {
+      const uint32_t x = x0 + u * kPartThreads;
+      v[u] = 0u;
+      dst[u] = ~0u;
+      if (x < total) {
+        const uint32_t sl = x / per_slice, r = x - sl * per_slice;
+        const uint32_t j = r >> slot_shift, w = r & ((1u << slot_shift) - 1u);
+        dst[u] = j * map_words + (sl << slot_shift) + w;
+        const uint32_t a = pre[sl * rec + j] + 32u * w, end = pre[sl * rec + j + 1u];
+        if (a < end) {
+          const uint32_t sw = first_word[sl] + (a >> 5), ss = a & 31u;
+          const uint32_t nbits = min(32u, end - a);
+          uint32_t wd = res32[sw];
+          if (ss) wd = (wd >> ss) | (res32[sw + 1u] << (32u - ss));
+          v[u] = nbits < 32u ? wd & ((1u << nbits) - 1u) : wd;
+        }
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kIn; ++u)
+      if (dst[u] != ~0u) maps[dst[u]] = v[u];
+  }
+  __syncthreads();
+  unpermute_write<kBits>(maps, map_words, pos, ur, chunk, first, out8, out_bits);
 }
 
 // Workspace sections (each 256-byte aligned): hist[G][P], start[G][P],
 // blocksum[RB][P], tot[P], offsets[P + 1] (u32), keys (u64) and, for
-// lookups, pos[n] (u16) and res (u8). Keys and results are laid out with
-// every slice's run padded to a multiple of four, at most n + 3P entries.
+// lookups, pos[n] (u16) and res (a bitmap of 32-bit words). Keys and results
+// are laid out with every slice's run padded to a multiple of four keys for
+// inserts (at most n + 3P entries) and of kLookupAlign for lookups (at most
+// n + 31P).
 struct PartitionLayout {
   uint32_t *hist, *start, *blocksum, *tot, *offsets;
   uint64_t *keys;
   uint16_t *pos;
-  uint8_t *res;
+  uint32_t *res;
   uint64_t bytes;
   uint32_t scatter_groups;  // lookups: scatter workgroups to spread the chunks over
 };
@@ -982,7 +1444,7 @@ uint32_t row_blocks(uint32_t groups) { return (groups + kScanRows - 1u) / kScanR
 PartitionLayout layout(void *workspace, uint64_t n, uint32_t num_slices, uint32_t groups, bool lookup) {
   auto up = [](uint64_t v) { return (v + 255u) & ~(uint64_t)255u; };
   char *base = static_cast<char *>(workspace);
-  const uint64_t padded = n + 3u * (uint64_t)num_slices;
+  const uint64_t padded = n + (lookup ? kLookupAlign - 1u : 3u) * (uint64_t)num_slices;
   uint64_t off = 0;
   PartitionLayout L{};
   L.hist = reinterpret_cast<uint32_t *>(base + off);
@@ -1000,8 +1462,10 @@ PartitionLayout layout(void *workspace, uint64_t n, uint32_t num_slices, uint32_
   if (lookup) {
     L.pos = reinterpret_cast<uint16_t *>(base + off);
     off += up(n * 2u);
-    L.res = reinterpret_cast<uint8_t *>(base + off);
-    off += up(padded + 8u);  // 8 bytes of padding for the unpermute kernel's word loads
+    L.res = reinterpret_cast<uint32_t *>(base + off);
+    // two words of padding: the unpermute kernel reads the word after each
+    // piece's first
+    off += up(((padded + 31u) / 32u + 2u) * 4u);
   }
   L.bytes = off;
   return L;
@@ -1101,7 +1565,8 @@ hipError_t partition(const uint64_t *hashes, uint32_t n, uint32_t num_blocks, ui
   hipLaunchKernelGGL(part_colscan_kernel, scan_grid, blk, 0, stream, L.hist, groups, num_slices, L.blocksum, L.start,
                      L.tot);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(part_offsets_kernel, dim3(1), blk, 0, stream, L.tot, num_slices, L.offsets);
+  hipLaunchKernelGGL(part_offsets_kernel, dim3(1), blk, 0, stream, L.tot, num_slices, with_pos ? kLookupAlign : 4u,
+                     L.offsets);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (with_pos)
     return launch_scatter_r<true>(hashes, n, chunk, groups, num_blocks, slice_shift, slice_base, num_slices, keys, L,
@@ -1140,21 +1605,26 @@ hipError_t launch_slice_lookup(const PartitionLayout &L, uint32_t num_slices, co
   return hipGetLastError();
 }
 
-// Results of a partition (in partitioned order, L.res) back to input order.
+// Results of a partition (in partitioned order, L.res) back to input order:
+// per chunks per workgroup, enough to fill `slots` workgroups (at most
+// kUnpermuteChunks).
 hipError_t unpermute(const PartitionLayout &L, uint32_t num_slices, uint32_t n, uint32_t chunk, uint32_t groups,
-                     uint8_t *out8, uint32_t *out_bits, hipStream_t stream) {
-  const size_t u_lds = (size_t)num_slices * 8u + 64u + chunk;
+                     uint32_t slots, uint8_t *out8, uint32_t *out_bits, hipStream_t stream) {
+  if (slots == 0) slots = 1;
+  const uint32_t per = std::max(1u, std::min(kUnpermuteChunks, (groups + slots - 1u) / slots));
+  const uint32_t grid = (groups + per - 1u) / per;
+  const size_t u_lds = 128u + (size_t)per * (chunk / 8u);
   (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)u_lds);
   (void)hipFuncSetAttribute((const void *)part_unpermute_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)u_lds);
   (void)hipGetLastError();
   if (out_bits)
-    hipLaunchKernelGGL(part_unpermute_kernel<true>, dim3(groups), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
-                       L.offsets, L.start, L.hist, num_slices, n, chunk, nullptr, out_bits);
+    hipLaunchKernelGGL(part_unpermute_kernel<true>, dim3(grid), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
+                       L.offsets, L.start, L.hist, num_slices, n, chunk, groups, per, nullptr, out_bits);
   else
-    hipLaunchKernelGGL(part_unpermute_kernel<false>, dim3(groups), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
-                       L.offsets, L.start, L.hist, num_slices, n, chunk, out8, nullptr);
+    hipLaunchKernelGGL(part_unpermute_kernel<false>, dim3(grid), dim3(kPartThreads), u_lds, stream, L.pos, L.res,
+                       L.offsets, L.start, L.hist, num_slices, n, chunk, groups, per, out8, nullptr);
   return hipGetLastError();
 }
 
@@ -1247,6 +1717,177 @@ hipError_t insert_buckets(const uint64_t *hashes, uint32_t n, uint32_t *words, u
   return e != hipSuccess ? e : launch_overflow_insert<8>(Bk, words, num_blocks, stream);
 }
 
+// Count-free lookup partition (struct Buckets, lookup side): for one-level
+// lookups into at most 2 * kScatterThreads slices. Results are placed by
+// position in slots of `room` bits per (chunk, slice), room the largest
+// power of two from 32 to 4,096 with slices * room <= 2^16 (16-bit
+// positions); a chunk is
+// the most tiles (at most nine) whose expected run in one slice, plus six
+// standard deviations, fits a slot. Each scatter workgroup takes `per`
+// consecutive chunks into its buckets, of room for their expected keys plus
+// eight standard deviations and 32 keys, rounded up to 32 (whole result
+// words). It skips the count and scan kernels (one read of the batch).
+struct LookPlan {
+  uint32_t chunk, groups;  // lookup chunks
+  uint32_t sgroups, per;   // scatter workgroups (buckets per slice), chunks per scatter workgroup
+  uint32_t cap, room;
+  uint64_t runs_off, count_off, ovfn_off, ovf_off, pos_off, keys_off, res_off, bytes;
+};
+
+bool look_plan(uint64_t n, uint32_t num_slices, uint32_t max_groups, LookPlan *lp) {
+  if (n == 0 || n > UINT32_MAX || num_slices == 0 || num_slices > 2u * kScatterThreads) return false;
+  // room: a power of two (the unpermute splits positions by shifts) of at
+  // most 4,096 (the unpermute keeps run offsets over eight chunks in 16 bits)
+  uint32_t room = 4096u;
+  while (room > 32u && (uint64_t)room * num_slices > 65536u) room >>= 1;
+  if ((uint64_t)room * num_slices > 65536u) return false;
+  // a slice holds at most 1 / (slices - 1) of the blocks (all but the last are whole)
+  const double share = 1.0 / (double)(num_slices > 1u ? num_slices - 1u : 1u);
+  uint32_t tiles = 9u;
+  for (; tiles > 0u; --tiles) {
+    const double mean = tiles * (double)kTile * share;
+    if (mean + 6.0 * std::sqrt(mean) + 1.0 <= (double)room) break;
+  }
+  if (tiles == 0u) return false;
+  lp->room = room;
+  lp->chunk = tiles * kTile;
+  lp->groups = (uint32_t)((n + lp->chunk - 1u) / lp->chunk);
+  const uint32_t slots = std::max(1u, std::min(max_groups, kMaxBucketGroups));
+  lp->per = (lp->groups + slots - 1u) / slots;
+  lp->sgroups = (lp->groups + lp->per - 1u) / lp->per;
+  const double mean = (double)lp->per * lp->chunk * share;
+  const uint64_t cap = ((uint64_t)(mean + 8.0 * std::sqrt(mean) + 32.0) + 31u) & ~(uint64_t)31u;
+  const uint64_t positions = (uint64_t)lp->sgroups * num_slices * cap;
+  if (positions >= (1ull << 32) - 64u) return false;
+  lp->cap = (uint32_t)cap;
+  auto up = [](uint64_t v) { return (v + 255u) & ~(uint64_t)255u; };
+  uint64_t off = 0;
+  lp->runs_off = off;
+  off += up((uint64_t)lp->groups * num_slices * 8u);
+  lp->count_off = off;
+  off += up((uint64_t)lp->sgroups * num_slices * 4u);
+  lp->ovfn_off = off;
+  off += 256u;
+  lp->ovf_off = off;
+  off += up(n * 4u);
+  lp->pos_off = off;
+  off += up(n * 2u);
+  lp->keys_off = off;
+  off += up(positions * 8u);
+  lp->res_off = off;
+  off += up((positions / 32u + 2u) * 4u);  // two words of padding for the unpermute's word pairs
+  lp->bytes = off;
+  return true;
+}
+
+template <uint32_t K>
+hipError_t launch_bucket_lookup(const uint64_t *part, const uint32_t *counts, const LookPlan &lp,
+                                uint32_t num_slices, const uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
+                                uint32_t slice_base, uint32_t *res32, hipStream_t stream) {
+  const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K +
+                           (2u * kMaxBucketGroups + 1u + (kBucketMap + 2u) / 2u + 16u) * 4u;
+  (void)hipFuncSetAttribute((const void *)part_bucket_lookup_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_bytes);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(part_bucket_lookup_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, part,
+                     counts, lp.sgroups, lp.cap, words, num_blocks, slice_shift, slice_base, res32);
+  return hipGetLastError();
+}
+
+template <uint32_t K>
+hipError_t launch_overflow_lookup(const uint64_t *hashes, uint32_t keys, const Buckets &Bk, const uint32_t *words,
+                                  uint32_t num_blocks, uint8_t *out8, uint32_t *out_bits, hipStream_t stream) {
+  hipLaunchKernelGGL(part_overflow_lookup_kernel<K>, dim3(256), dim3(256), 0, stream, hashes, keys, Bk.ovf_idx,
+                     Bk.ovf_n, Bk.ovf_cap, words, num_blocks, out8, out_bits);
+  return hipGetLastError();
+}
+
+template <int R, uint32_t L>
+hipError_t launch_look_scatter(const uint64_t *hashes, uint32_t n, const LookPlan &lp, uint32_t num_blocks,
+                               uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, uint32_t keys,
+                               uint64_t *part, uint16_t *pos, const Buckets &Bk, hipStream_t stream) {
+  const size_t lds = scatter_lds_bytes(num_slices, true, L, R);
+  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<true, R, L, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipGetLastError();
+  hipLaunchKernelGGL((part_scatter_kernel<true, R, L, true>), dim3(lp.sgroups), dim3(kScatterThreads), lds, stream,
+                     hashes, n, lp.chunk, lp.per, num_blocks, slice_shift, slice_base, num_slices, nullptr, nullptr,
+                     nullptr, keys, part, pos, Bk);
+  return hipGetLastError();
+}
+
+// Count-free lookup: scatter into buckets (positions, runs, bucket counts,
+// overflow list), slice lookups over the buckets, unpermute by run, then the
+// overflowing keys.
+hipError_t lookup_buckets(const uint64_t *hashes, uint32_t n, const uint32_t *words, uint32_t num_blocks,
+                          uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, void *workspace,
+                          const LookPlan &lp, uint32_t slots, uint8_t *out8, uint32_t *out_bits, uint32_t keys,
+                          hipStream_t stream, uint32_t lanes) {
+  char *base = static_cast<char *>(workspace);
+  Buckets Bk{};
+  Bk.cap = lp.cap;
+  Bk.count = reinterpret_cast<uint32_t *>(base + lp.count_off);
+  Bk.ovf_n = reinterpret_cast<uint32_t *>(base + lp.ovfn_off);
+  Bk.ovf_cap = n;
+  Bk.room = lp.room;
+  Bk.ovf_idx = reinterpret_cast<uint32_t *>(base + lp.ovf_off);
+  Bk.runs = reinterpret_cast<uint2 *>(base + lp.runs_off);
+  uint16_t *pos = reinterpret_cast<uint16_t *>(base + lp.pos_off);
+  uint64_t *part = reinterpret_cast<uint64_t *>(base + lp.keys_off);
+  uint32_t *res32 = reinterpret_cast<uint32_t *>(base + lp.res_off);
+  hipError_t e = launch_fill(Bk.ovf_n, 1u, 0u, stream);  // a fill kernel, not a memset (graph capture)
+  if (e != hipSuccess) return e;
+  if (num_slices <= kScatterThreads)
+    e = launch_look_scatter<1, kScatterGroup>(hashes, n, lp, num_blocks, slice_shift, slice_base, num_slices, keys,
+                                              part, pos, Bk, stream);
+  else
+    e = launch_look_scatter<2, 4>(hashes, n, lp, num_blocks, slice_shift, slice_base, num_slices, keys, part, pos,
+                                  Bk, stream);
+  if (e != hipSuccess) return e;
+  if (lanes == 4)
+    e = launch_bucket_lookup<4>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
+                                stream);
+  else if (lanes == 16)
+    e = launch_bucket_lookup<16>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
+                                 stream);
+  else
+    e = launch_bucket_lookup<8>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
+                                stream);
+  if (e != hipSuccess) return e;
+  // Unpermute: at most kUnpermuteChunks chunks of one scatter workgroup per
+  // workgroup, as many as fit kUnpermuteLds bytes of LDS (bitmaps and slice
+  // records), so that two workgroups share a compute unit.
+  auto u_lds_of = [&](uint32_t pu) {
+    return ((size_t)pu * num_slices * (lp.room / 8u) + (size_t)num_slices * 4u + (size_t)num_slices * (pu + 1u) * 2u +
+            3u) & ~(size_t)3u;
+  };
+  uint32_t per_u = std::min(kUnpermuteChunks, lp.per);
+  while (per_u > 1u && u_lds_of(per_u) > kUnpermuteLds) --per_u;
+  const uint32_t upw = (lp.per + per_u - 1u) / per_u;
+  const uint32_t grid = lp.sgroups * upw;
+  const size_t u_lds = u_lds_of(per_u);
+  uint32_t room_shift = 5;
+  while ((1u << room_shift) < lp.room) ++room_shift;
+  (void)slots;
+  if (out_bits) {
+    (void)hipFuncSetAttribute((const void *)part_unpermute_buckets_kernel<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)u_lds);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(part_unpermute_buckets_kernel<true>, dim3(grid), dim3(kPartThreads), u_lds, stream, pos, res32,
+                       Bk.runs, num_slices, room_shift, n, lp.chunk, lp.groups, lp.per, per_u, nullptr, out_bits);
+  } else {
+    (void)hipFuncSetAttribute((const void *)part_unpermute_buckets_kernel<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)u_lds);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(part_unpermute_buckets_kernel<false>, dim3(grid), dim3(kPartThreads), u_lds, stream, pos,
+                       res32, Bk.runs, num_slices, room_shift, n, lp.chunk, lp.groups, lp.per, per_u, out8, nullptr);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (lanes == 4) return launch_overflow_lookup<4>(hashes, keys, Bk, words, num_blocks, out8, out_bits, stream);
+  if (lanes == 16) return launch_overflow_lookup<16>(hashes, keys, Bk, words, num_blocks, out8, out_bits, stream);
+  return launch_overflow_lookup<8>(hashes, keys, Bk, words, num_blocks, out8, out_bits, stream);
+}
+
 // One level: the n keys all lie in the num_slices slices from slice_base.
 hipError_t insert_level(const uint64_t *hashes, uint32_t n, uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
                         uint32_t slice_base, uint32_t num_slices, void *workspace, uint32_t max_groups, uint32_t keys,
@@ -1267,6 +1908,10 @@ hipError_t lookup_level(const uint64_t *hashes, uint32_t n, const uint32_t *word
                         uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, void *workspace,
                         uint32_t max_groups, uint8_t *out8, uint32_t *out_bits, uint32_t keys, hipStream_t stream,
                         uint32_t lanes) {
+  LookPlan lp;
+  if (look_plan(n, num_slices, max_groups, &lp))
+    return lookup_buckets(hashes, n, words, num_blocks, slice_shift, slice_base, num_slices, workspace, lp,
+                          max_groups, out8, out_bits, keys, stream, lanes);
   uint32_t chunk, groups;
   chunking(n, max_groups, true, &chunk, &groups);
   PartitionLayout L = layout(workspace, n, num_slices, groups, true);
@@ -1281,7 +1926,7 @@ hipError_t lookup_level(const uint64_t *hashes, uint32_t n, const uint32_t *word
   else
     e = launch_slice_lookup<8>(L, num_slices, words, num_blocks, slice_shift, slice_base, stream);
   if (e != hipSuccess) return e;
-  return unpermute(L, num_slices, n, chunk, groups, out8, out_bits, stream);
+  return unpermute(L, num_slices, n, chunk, groups, max_groups, out8, out_bits, stream);
 }
 
 // Two levels, for filters of more than kOneLevelSlices slices: level 1
@@ -1339,6 +1984,8 @@ uint64_t partition_workspace_bytes(uint64_t n, uint32_t num_slices, uint32_t max
     const uint64_t counted = layout(nullptr, n, num_slices, groups, lookup).bytes;
     BucketPlan bp;
     if (!lookup && bucket_plan(n, num_slices, max_groups, &bp)) return std::max(counted, bp.bytes);
+    LookPlan lp;
+    if (lookup && look_plan(n, num_slices, max_groups, &lp)) return std::max(counted, lp.bytes);
     return counted;
   }
   // level 1, then level 2 for at most all n keys in one group
@@ -1392,17 +2039,18 @@ hipError_t launch_lookup_partitioned(const uint64_t *hashes, uint64_t n, const u
                            t.chunks, t.L1, true, keys, stream);
   std::vector<uint32_t> off, tot;
   if (e == hipSuccess) e = group_counts(t, &off, &tot, stream);
-  // Each group's results go, one byte per key, to its run of the level-1
-  // results (level-1 partitioned order), which level 1 then unpermutes.
+  // Each group's results go, one bit per key, to its run of the level-1
+  // results (level-1 partitioned order; runs start at multiples of 32 keys,
+  // so at whole words), which level 1 then unpermutes.
   for (uint32_t g = 0; g < t.groups && e == hipSuccess; ++g) {
     if (tot[g] == 0) continue;
     const uint32_t base = g << kGroupShift;
     e = lookup_level(t.L1.keys + off[g], tot[g], words, num_blocks, slice_shift, base,
-                     std::min(kGroupSlices, num_slices - base), t.level2, max_groups, t.L1.res + off[g], nullptr, 0u,
-                     stream, lanes);
+                     std::min(kGroupSlices, num_slices - base), t.level2, max_groups, nullptr,
+                     t.L1.res + off[g] / 32u, 0u, stream, lanes);
   }
   if (e != hipSuccess) return e;
-  return unpermute(t.L1, t.groups, (uint32_t)n, t.chunk, t.chunks, out8, out_bits, stream);
+  return unpermute(t.L1, t.groups, (uint32_t)n, t.chunk, t.chunks, max_groups, out8, out_bits, stream);
 }
 
 }  // namespace sbbf
