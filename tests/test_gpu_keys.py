@@ -56,3 +56,22 @@ def test_keys_equal_hashing_first(P):
     assert torch.equal(a.lookup_keys(probes), b.lookup(dev(oracle.key_hash(np.arange(5_000_000, dtype=np.uint64)))))
     a.close()
     b.close()
+
+
+def test_partitioned_lookup_keys_overflow(P):
+    """Keys hashed on load through the count-free lookup partition when most
+    probes are one repeated key: its slice's runs overflow, and the overflow
+    pass hashes those keys itself."""
+    B = 4096 * 600 + 3
+    keys = splitmix64_stream(952, 800_000)
+    ref = oracle.build_filter(B, oracle.key_hash(keys))
+    f = P.Filter(B)
+    f.insert_keys(dev(keys), launch=dict(strategy=4))
+    probes = splitmix64_stream(953, 1_500_001)
+    probes[1::3] = keys[777]
+    probes[2::3] = keys[4242]
+    got = f.lookup_keys(dev(probes), launch=dict(strategy=2)).cpu().numpy()
+    want = oracle.lookup(ref, B, oracle.key_hash(probes))
+    assert want.any() and not want.all()
+    assert np.array_equal(got, want)
+    f.close()

@@ -512,3 +512,23 @@ def test_partitioned_lookup_batch_sizes(P, n):
     bits = f.lookup_bits(dev(probes), launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
     assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
     f.close()
+
+
+@pytest.mark.parametrize("grid", [1, 2, 3, 7, 100, 1024])
+def test_partitioned_lookup_grid_sizes(P, grid):
+    """Lookup partitions over one to 1,024 scatter workgroups: buckets holding
+    many chunks, unpermute workgroups splitting a scatter workgroup's chunks
+    unevenly, and a last scatter workgroup with fewer chunks than the others;
+    bytes and bits."""
+    B = 4096 * 300 + 5
+    h = splitmix64_stream(598, 300_000)
+    ref = oracle.build_filter(B, h)
+    f = P.Filter(B)
+    f.insert(dev(h), launch=dict(strategy=1))
+    probes = np.concatenate([h[::3], splitmix64_stream(599, 500_003)])
+    want = oracle.lookup(ref, B, probes)
+    launch = dict(strategy=2, grid_blocks=grid)
+    assert np.array_equal(f.lookup(dev(probes), launch=launch).cpu().numpy(), want)
+    bits = f.lookup_bits(dev(probes), launch=launch).cpu().numpy().view(np.uint32)
+    assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
+    f.close()
