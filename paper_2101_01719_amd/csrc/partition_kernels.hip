@@ -212,7 +212,7 @@ part_offsets_kernel(const uint32_t *__restrict__ tot, uint32_t num_slices, uint3
 constexpr uint32_t stage_keys(uint32_t L, uint32_t R) { return kTile + (L - 1u) * R * kScatterThreads; }
 
 constexpr size_t scatter_lds_bytes(uint32_t num_slices, bool with_pos, uint32_t L, uint32_t R) {
-  return (size_t)stage_keys(L, R) * 8u + (size_t)num_slices * (with_pos ? 20u : 16u) + 64u;
+  return (size_t)stage_keys(L, R) * 8u + (size_t)num_slices * (with_pos ? 20u : 16u) + 80u;
 }
 
 struct ScatterLds {
@@ -225,6 +225,7 @@ struct ScatterLds {
   // of pdelta | the rank from which the tile's keys of slice s overflow << 16)
   uint2 *sp;
   uint32_t *wsum;   // [16]
+  uint32_t *spilled;  // [1] (bucketed lookups) some slice's run reached its limit in this tile
 };
 
 // Hashes of tile t0 for this thread: index t0 + t * kScatterThreads + thread,
@@ -403,6 +404,8 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
       const uint32_t cap_end = kWithPos ? C.limit[r] : bucket_end(blockIdx.x, sl, Bk.cap);
       spill = end > cap_end;
       if (spill) aligned = cap_end;
+      if constexpr (kWithPos)
+        if (spill) *S.spilled = 1u;
     }
     const uint32_t wlen = aligned > first ? aligned - first : 0u;  // keys written by this tile
     if (sl < num_slices) {
@@ -425,7 +428,6 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     run += m[r];
   }
   lds_barrier();
-  uint32_t ovm = 0;  // (bucketed lookups) this thread's keys past their run's limit
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
@@ -436,12 +438,9 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
         const uint2 sp = S.sp[s[t]];
         const uint32_t k = sp.x + rank[t];
         S.stage[k] = h[t];
-        const bool over = rank[t] >= (sp.y >> 16);  // past its run's limit
-        ovm |= over ? 1u << t : 0u;
-        // (an overflowing key takes any position of the chunk: the overflow
-        // pass rewrites its result)
-        const uint32_t p = over ? s[t] * Bk.room : (k + sp.y) & 0xffffu;
-        __builtin_nontemporal_store((uint16_t)p, out_pos + i);
+        // (the low 16 bits: k + pdelta; rewritten below if the key is past
+        // its run's limit)
+        __builtin_nontemporal_store((uint16_t)(k + sp.y), out_pos + i);
       } else {
         const uint32_t k = S.sbase[s[t]] + rank[t];
         S.stage[k] = h[t];
@@ -450,14 +449,26 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     }
   }
   if constexpr (kWithPos && kBucket) {
-    // Overflowing keys (rare) to the list of the overflow pass.
-    for (uint32_t t = 0; ovm != 0u; ++t, ovm >>= 1)
-      if (ovm & 1u) {
-        const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (o < Bk.ovf_cap) Bk.ovf_idx[o] = t0 + t * kScatterThreads + threadIdx.x;
+    // Some run reached its limit in this tile (rare; a uniform branch): the
+    // keys of rank >= the slice's limit go to the overflow pass's list, with
+    // any position of their chunk (the overflow pass rewrites their results).
+    if (*S.spilled) {
+#pragma unroll
+      for (uint32_t t = 0; t < kScatterPer; ++t) {
+        const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
+        if ((kFull || i < e) && rank[t] >= (S.sp[s[t]].y >> 16)) {
+          const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (o < Bk.ovf_cap) Bk.ovf_idx[o] = i;
+          __builtin_nontemporal_store((uint16_t)(s[t] * Bk.room), out_pos + i);
+        }
       }
+    }
   }
   lds_barrier();
+  // (every thread has read the flag: cleared for the next tile, whose
+  // spills are recorded after two more barriers)
+  if constexpr (kWithPos && kBucket)
+    if (threadIdx.x == 0) *S.spilled = 0u;
 #pragma unroll
   for (uint32_t t = 0; t < kScatterPer + (L - 1u) * R; ++t) {
     const uint32_t k = t * kScatterThreads + threadIdx.x;
@@ -505,6 +516,8 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
     S.hist = reinterpret_cast<uint32_t *>(S.sp + num_slices);
     S.wsum = S.hist + num_slices;
   }
+  S.spilled = S.wsum + 16;
+  if (threadIdx.x == 0) *S.spilled = 0u;  // (ordered before its first use by the barrier below)
 
   // This workgroup takes chunks u0 .. u0 + chunks_per_group - 1.
   const uint32_t u0 = blockIdx.x * chunks_per_group;
