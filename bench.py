@@ -112,7 +112,9 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
     # Library dispatches after the copy: fill (clear), then the insert
     # kernels (a bucketed insert starts with a fill of its overflow count and
     # ends with the overflow pass; a counted one ends with the slice insert),
-    # then the lookup kernels, step after step.
+    # then the lookup kernels (a count-free lookup starts with a fill of its
+    # overflow count and ends with the unpermute and the overflow pass; a
+    # counted one ends with the unpermute), step after step.
     ops = {"insert": [], "lookup": []}
     cur, cur_op = [], "insert"
     for i in range(ci + 1, len(fetch)):
@@ -121,6 +123,9 @@ def _traffic_from_counters(fetch_csv: str, write_csv: str, workload: str, copy_m
             continue
         if name.startswith("fill_kernel"):
             cur, cur_op = [], "insert"
+            continue
+        if name.startswith("part_overflow_lookup") and ops["lookup"] and not cur:
+            ops["lookup"][-1].append((name, fetch[i][3], write[i][3]))  # the count-free lookup's last pass
             continue
         cur.append((name, fetch[i][3], write[i][3]))
         if name.startswith(("part_slice_insert", "part_overflow_insert", "insert_")):
