@@ -1797,6 +1797,22 @@ bool look_plan(uint64_t n, uint32_t num_slices, uint32_t max_groups, LookPlan *l
   return true;
 }
 
+// LDS of a count-free unpermute workgroup of per_u chunks: the bitmaps and
+// the slice records (a word and per_u + 1 16-bit offsets per slice).
+size_t look_unpermute_lds(uint32_t per_u, uint32_t num_slices, uint32_t room) {
+  return ((size_t)per_u * num_slices * (room / 8u) + (size_t)num_slices * 4u + (size_t)num_slices * (per_u + 1u) * 2u +
+          3u) & ~(size_t)3u;
+}
+
+// Chunks per count-free unpermute workgroup: at most kUnpermuteChunks of one
+// scatter workgroup's, as many as fit kUnpermuteLds bytes of LDS, so that two
+// workgroups share a compute unit.
+uint32_t look_unpermute_chunks(const LookPlan &lp, uint32_t num_slices) {
+  uint32_t per_u = std::min(kUnpermuteChunks, lp.per);
+  while (per_u > 1u && look_unpermute_lds(per_u, num_slices, lp.room) > kUnpermuteLds) --per_u;
+  return per_u;
+}
+
 template <uint32_t K>
 hipError_t launch_bucket_lookup(const uint64_t *part, const uint32_t *counts, const LookPlan &lp,
                                 uint32_t num_slices, const uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
@@ -1871,18 +1887,10 @@ hipError_t lookup_buckets(const uint64_t *hashes, uint32_t n, const uint32_t *wo
     e = launch_bucket_lookup<8>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
                                 stream);
   if (e != hipSuccess) return e;
-  // Unpermute: at most kUnpermuteChunks chunks of one scatter workgroup per
-  // workgroup, as many as fit kUnpermuteLds bytes of LDS (bitmaps and slice
-  // records), so that two workgroups share a compute unit.
-  auto u_lds_of = [&](uint32_t pu) {
-    return ((size_t)pu * num_slices * (lp.room / 8u) + (size_t)num_slices * 4u + (size_t)num_slices * (pu + 1u) * 2u +
-            3u) & ~(size_t)3u;
-  };
-  uint32_t per_u = std::min(kUnpermuteChunks, lp.per);
-  while (per_u > 1u && u_lds_of(per_u) > kUnpermuteLds) --per_u;
+  const uint32_t per_u = look_unpermute_chunks(lp, num_slices);
   const uint32_t upw = (lp.per + per_u - 1u) / per_u;
   const uint32_t grid = lp.sgroups * upw;
-  const size_t u_lds = u_lds_of(per_u);
+  const size_t u_lds = look_unpermute_lds(per_u, num_slices, lp.room);
   uint32_t room_shift = 5;
   while ((1u << room_shift) < lp.room) ++room_shift;
   (void)slots;
