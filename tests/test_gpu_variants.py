@@ -198,3 +198,30 @@ def test_variant_errors(P):
     f4.close()
     f8.close()
     big.close()
+
+
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_variant_partitioned_lookup_overflow(P, lanes):
+    """Four- and sixteen-word blocks through the count-free lookup when most
+    probes are two repeated members and the rest crowd into one slice: runs
+    past their room go to the overflow pass, whose gather tests K words.
+    Bytes and bits (bits: the packing of the byte results, LSB first)."""
+    B = 4096 * 300 + 1
+    h = splitmix64_stream(1950 + lanes, 400_000)
+    ref = oracle.variant_build_filter(lanes, B, h)
+    f = P.Filter(B, lanes=lanes)
+    f.insert(dev(h), launch=INSERTS["partitioned"])
+    probes = splitmix64_stream(1960 + lanes, 1_200_001)
+    probes[0::3] = h[99]
+    span = (4096 << 32) // B  # high halves mapping into the first slice
+    probes[1::3] = ((probes[1::3] >> np.uint64(32)) % np.uint64(span) << np.uint64(32)) | \
+        (probes[1::3] & np.uint64(0xFFFFFFFF))
+    want = oracle.variant_lookup(ref, lanes, B, probes)
+    assert want.any() and not want.all()
+    dp = dev(probes)
+    assert np.array_equal(f.lookup(dp, launch=LOOKUPS["partitioned"]).cpu().numpy(), want)
+    bits = f.lookup_bits(dp, launch=LOOKUPS["partitioned"]).cpu().numpy().view(np.uint32)
+    packed = np.packbits(want.astype(np.uint8), bitorder="little")
+    packed = np.concatenate([packed, np.zeros(-packed.size % 4, np.uint8)]).view(np.uint32)
+    assert np.array_equal(bits, packed[: bits.size])
+    f.close()
