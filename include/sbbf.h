@@ -94,10 +94,16 @@ typedef enum sbbf_lookup_strategy {
   SBBF_LOOKUP_AUTO = 0,        /* library choice by filter size and key count */
   SBBF_LOOKUP_GATHER = 1,      /* one block read per key, K lanes per key */
   SBBF_LOOKUP_PARTITIONED = 2  /* keys split by filter slice, each slice tested from one
-                                  workgroup's LDS, results returned to input order; uses a
-                                  stream-ordered device workspace of about 13 bytes per key
-                                  (batches above 2^31 keys are processed 2^31 at a time);
-                                  above 4,096 slices two levels, as for inserts */
+                                  workgroup's LDS, results returned to input order. Filters
+                                  of up to 2,048 slices split without counting first: each
+                                  partitioning workgroup fills fixed-room buckets per slice
+                                  and keys past a run's room (skewed batches) are looked up
+                                  by a gather afterwards. Uses a stream-ordered device
+                                  workspace of about 15 to 20 bytes per key for batches of
+                                  1e8 keys and more (more for small batches over many
+                                  slices: the buckets' room; about 11 with counting; batches
+                                  above 2^31 keys are processed 2^31 at a time); above 4,096
+                                  slices two levels, as for inserts */
 } sbbf_lookup_strategy;
 
 /* Memory-access flags of sbbf_launch (cache policy only; results are

@@ -64,14 +64,14 @@ constexpr uint32_t kTile = kScatterThreads * kScatterPer;
 constexpr uint32_t kScanRows = 256;    // rows per colsum/colscan workgroup (16 segments of 16)
 constexpr uint32_t kScanCols = 64;     // columns per colsum/colscan workgroup
 constexpr uint32_t kSliceSteps = 2;    // 256-key steps per wave per slice-loop iteration
-// Lookup chunks are at most this many keys so that one chunk's result bytes
-// fit one workgroup's LDS in the unpermute kernel and positions fit 16 bits.
+// Counted lookup chunks are at most this many keys so that positions fit 16
+// bits (and a chunk's result bits, 8 KiB, one slot of the unpermute's LDS).
 constexpr uint32_t kLookupChunk = 65536u;
-// Lookup runs are padded to multiples of this many keys: a run's results are
-// whole 32-bit words of the result bitmap.
+// Counted lookup runs are padded to multiples of this many keys: a run's
+// results are whole 32-bit words of the result bitmap.
 constexpr uint32_t kLookupAlign = 32u;
-// Lookup chunks one unpermute workgroup restores (their result runs in a
-// slice are adjacent, so it reads each slice's runs as one span).
+// Most lookup chunks one unpermute workgroup restores (their result runs in
+// a slice are adjacent, so it reads each slice's runs as one span).
 constexpr uint32_t kUnpermuteChunks = 8u;
 // LDS of one bucketed-lookup unpermute workgroup (two per compute unit).
 constexpr size_t kUnpermuteLds = 78u << 10;
