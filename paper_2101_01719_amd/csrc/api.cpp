@@ -495,7 +495,7 @@ static double gather_rate_gkeys(uint64_t bytes) {
 static uint32_t auto_lookup_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
   if (!partition_fits(info, f)) return SBBF_LOOKUP_GATHER;
   const double bytes = (double)filter_bytes(f);
-  double part_us = 50.0 + bytes / 5e6 + 9.0 * (double)n / 1e6;
+  double part_us = 45.0 + bytes / 5e6 + 7.7 * (double)n / 1e6;
   // Filters of more slices than one level takes: a level-1 count and scatter
   // (about 6.2 us per million keys), one wait for the stream and the fixed
   // cost of a one-level call per group of slices.
