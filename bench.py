@@ -460,6 +460,28 @@ def _strategy_sweep(out_md: str) -> int:
             print(json.dumps({"mib": mib, "n": n, "lookup_gather": lg, "lookup_partitioned": lp, "auto_lookup": al,
                               "insert_atomic32": ia, "insert_partitioned": ip, "auto_insert": ai}), flush=True)
         f.close()
+    # Filters above 128 MiB (one level up to 4,096 slices of 128 KiB, two levels above), with 64M keys inserted
+    # and batches of 64M and 200M keys.
+    del h, o
+    h = splitmix64_stream(2, 200_000_000, backend="torch", device="cuda")
+    o = torch.empty(h.numel(), dtype=torch.uint8, device="cuda")
+    big = []
+    for mib in (256, 512, 1536, 4096):
+        B = (mib << 20) // 32
+        f = P.Filter(B)
+        f.insert(h[:64_000_000])
+        torch.cuda.synchronize()
+        for n in (64_000_000, 200_000_000):
+            x, y = h[:n], o[:n]
+            lg = n / timed(lambda: f.lookup(x, out=y, launch=dict(strategy=1)), reps=3) / 1e6
+            lp = n / timed(lambda: f.lookup(x, out=y, launch=dict(strategy=2)), reps=3) / 1e6
+            ia = n / timed(lambda: f.insert(x, launch=dict(strategy=1)), reps=3) / 1e6
+            ip = n / timed(lambda: f.insert(x, launch=dict(strategy=4)), reps=3) / 1e6
+            al, ai = P.sbbf_auto_lookup_strategy(f.handle, n), P.sbbf_auto_insert_strategy(f.handle, n)
+            big.append((mib, n, lg, lp, look_names[al], ia, ip, ins_names[ai]))
+            print(json.dumps({"mib": mib, "n": n, "lookup_gather": lg, "lookup_partitioned": lp, "auto_lookup": al,
+                              "insert_atomic32": ia, "insert_partitioned": ip, "auto_insert": ai}), flush=True)
+        f.close()
     with open(out_md, "w") as fh:
         fh.write("# Strategy sweep: gather vs partitioned lookup, atomic vs partitioned insert\n\n")
         fh.write("Command (from the repository root, on one MI355X):\n\n```\npython bench.py --strategy-sweep "
@@ -469,8 +491,14 @@ def _strategy_sweep(out_md: str) -> int:
                  "picks for that filter and batch (SBBF_*_AUTO). The faster strategy of each pair is in bold.\n\n")
         fh.write("| filter | keys | lookup gather | lookup partitioned | auto | insert atomic32 | insert partitioned "
                  "| auto |\n|---:|---:|---:|---:|---|---:|---:|---|\n")
+        b = lambda v, w: f"**{v:.1f}**" if v >= w else f"{v:.1f}"
         for mib, n, lg, lp, al, ia, ip, ai in rows:
-            b = lambda v, w: f"**{v:.1f}**" if v >= w else f"{v:.1f}"
+            fh.write(f"| {mib} MiB | {n:,} | {b(lg, lp)} | {b(lp, lg)} | {al} | {b(ia, ip)} | {b(ip, ia)} | {ai} |\n")
+        fh.write("\nLarger filters (2,048 to 4,096 slices of 128 KiB take one level, more take two), 64M keys "
+                 "inserted first (SplitMix64 seed 2), mean of 3 calls after one warm-up:\n\n")
+        fh.write("| filter | keys | lookup gather | lookup partitioned | auto | insert atomic32 | insert partitioned "
+                 "| auto |\n|---:|---:|---:|---:|---|---:|---:|---|\n")
+        for mib, n, lg, lp, al, ia, ip, ai in big:
             fh.write(f"| {mib} MiB | {n:,} | {b(lg, lp)} | {b(lp, lg)} | {al} | {b(ia, ip)} | {b(ip, ia)} | {ai} |\n")
     return 0
 

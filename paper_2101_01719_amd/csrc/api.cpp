@@ -466,10 +466,40 @@ static bool partition_fits(const sbbf_device_info &info, const sbbf_filter *f) {
 // that its fixed costs lose to the atomics: measured on MI355X for filters of
 // 1 to 64 MiB) and the filter splits into few enough slices; otherwise global
 // 32-bit atomics.
+// Rate of the 32-bit atomic insert (G keys/s) on MI355X by filter size:
+// one memory-side atomic request per key, slower once the filter is far
+// beyond the 256 MB last-level cache.
+static double atomic_rate_gkeys(uint64_t bytes) {
+  const uint64_t MiB = 1ull << 20;
+  if (bytes <= 256 * MiB) return 26.5;
+  if (bytes <= 512 * MiB) return 22.5;
+  if (bytes <= 2048 * MiB) return 19.0;
+  return 18.0;
+}
+
+// Extra cost (us) of a partition in two levels: the level-1 count and
+// scatter (about 6.2 us per million keys), one wait for the stream and the
+// fixed cost of a one-level call per group of slices.
+static double two_level_us(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
+  const uint32_t slices = partition_slices(f->num_blocks, partition_slice_shift(info, f->num_blocks, f->lanes));
+  if (slices <= partition_level_slices()) return 0.0;
+  const double groups = (double)((slices + partition_group_slices() - 1u) / partition_group_slices());
+  return 40.0 + 50.0 * groups + 6.2 * (double)n / 1e6;
+}
+
+// Library choice of insert strategy (SBBF_INSERT_AUTO) from a cost model
+// fitted to MI355X measurements (filters of 1 MiB to 4 GiB, 1M to 200M
+// keys): the partitioned insert takes about 100 us plus one read and one
+// write of the filter at 5 TB/s plus 6.3 us per million keys (plus the
+// second level's costs above 4,096 slices); the atomics take n / rate(filter
+// size). The partitioned insert needs at least 4M keys (below, its
+// workgroups are too few to be measured faster anywhere).
 static uint32_t auto_insert_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
-  if ((uint64_t)n >= 2u * (uint64_t)f->num_blocks && (uint64_t)n >= (4ull << 20) && partition_fits(info, f))
-    return SBBF_INSERT_PARTITIONED;
-  return SBBF_INSERT_ATOMIC32;
+  if ((uint64_t)n < (4ull << 20) || !partition_fits(info, f)) return SBBF_INSERT_ATOMIC32;
+  const double bytes = (double)filter_bytes(f);
+  const double part_us = 100.0 + 2.0 * bytes / 5e6 + 6.3 * (double)n / 1e6 + two_level_us(f, n, info);
+  const double atomic_us = (double)n / (atomic_rate_gkeys(filter_bytes(f)) * 1e3);
+  return part_us < atomic_us ? SBBF_INSERT_PARTITIONED : SBBF_INSERT_ATOMIC32;
 }
 
 // Rate of the gather lookup (G keys/s) on MI355X by filter size, measured
@@ -488,22 +518,15 @@ static double gather_rate_gkeys(uint64_t bytes) {
 }
 
 // Library choice of lookup strategy (SBBF_LOOKUP_AUTO) from a cost model
-// fitted to MI355X measurements (filters of 1 to 128 MiB, 1M to 200M keys):
-// the partitioned lookup takes about 50 us plus one read of the filter at
-// 5 TB/s plus 9 us per million keys; the gather takes n / rate(filter size).
-// The cheaper one is used (when the filter splits into few enough slices).
+// fitted to MI355X measurements (filters of 1 MiB to 4 GiB, 1M to 200M
+// keys): the partitioned lookup takes about 45 us plus one read of the
+// filter at 5 TB/s plus 7.7 us per million keys (plus the second level's
+// costs above 4,096 slices); the gather takes n / rate(filter size). The
+// cheaper one is used (when the filter splits into few enough slices).
 static uint32_t auto_lookup_strategy(const sbbf_filter *f, size_t n, const sbbf_device_info &info) {
   if (!partition_fits(info, f)) return SBBF_LOOKUP_GATHER;
   const double bytes = (double)filter_bytes(f);
-  double part_us = 45.0 + bytes / 5e6 + 7.7 * (double)n / 1e6;
-  // Filters of more slices than one level takes: a level-1 count and scatter
-  // (about 6.2 us per million keys), one wait for the stream and the fixed
-  // cost of a one-level call per group of slices.
-  const uint32_t slices = partition_slices(f->num_blocks, partition_slice_shift(info, f->num_blocks, f->lanes));
-  if (slices > partition_level_slices()) {
-    const double groups = (double)((slices + partition_group_slices() - 1u) / partition_group_slices());
-    part_us += 40.0 + 50.0 * groups + 6.2 * (double)n / 1e6;
-  }
+  const double part_us = 45.0 + bytes / 5e6 + 7.7 * (double)n / 1e6 + two_level_us(f, n, info);
   const double gather_us = (double)n / (gather_rate_gkeys(filter_bytes(f)) * 1e3);
   return part_us < gather_us ? SBBF_LOOKUP_PARTITIONED : SBBF_LOOKUP_GATHER;
 }

@@ -116,6 +116,10 @@ def test_deserialize_rejects_bad_input(P):
     (32, 1_048_576, 1, 1),        # partitioned insert loses below 4M keys
     (128, 200_000_000, 2, 4),     # the 100M-key workload's filter and batches
     (128, 100_000_000, 2, 4),
+    (1536, 64_000_000, 1, 4),     # two-level partitions: inserts win from about one key per block,
+    (4096, 64_000_000, 1, 1),     # lookups only at 1.5 GiB with 200M keys
+    (4096, 200_000_000, 1, 4),
+    (1536, 200_000_000, 2, 4),
 ])
 def test_auto_strategy_follows_the_measured_crossovers(P, mib, n, look, ins):
     """The automatic choice (no device work) against the crossovers measured
