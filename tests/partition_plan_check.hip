@@ -82,6 +82,27 @@ static void check_look(uint64_t n, uint32_t P, uint32_t mg) {
   }
 }
 
+static void check_insert_buckets(uint64_t n, uint32_t P, uint32_t mg) {
+  BucketPlan bp;
+  if (!bucket_plan(n, P, mg, &bp)) return;  // the counted insert partition then
+  const unsigned long long nn = n;
+  CHECK(bp.groups >= 1u && bp.groups <= kMaxBucketGroups && bp.chunk % kTile == 0u, "ins n=%llu P=%u mg=%u", nn, P,
+        mg);
+  CHECK((uint64_t)bp.groups * bp.chunk >= n && (uint64_t)(bp.groups - 1u) * bp.chunk < n, "ins n=%llu", nn);
+  CHECK(bp.cap % 8u == 0u && bp.cap >= 32u, "ins cap n=%llu P=%u", nn, P);   // whole 64-byte groups
+  const uint64_t positions = (uint64_t)bp.groups * P * bp.cap;
+  CHECK(positions < (1ull << 32), "ins positions n=%llu P=%u mg=%u", nn, P, mg);
+  const uint64_t off[] = {bp.count_off, bp.ovfn_off, bp.ovf_off, bp.keys_off, bp.bytes};
+  const uint64_t need[] = {(uint64_t)bp.groups * P * 4u, 4u, n * 8u, positions * 8u};
+  for (int k = 0; k < 4; ++k) {
+    CHECK(off[k] % 256u == 0u, "ins n=%llu", nn);
+    CHECK(off[k + 1] >= off[k] + need[k], "ins section %d: n=%llu P=%u mg=%u", k, nn, P, mg);
+  }
+  CHECK(partition_workspace_bytes(n, P, mg, false) >= bp.bytes, "ins ws n=%llu P=%u", nn, P);
+  const uint32_t R = P <= kScatterThreads ? 1u : 2u, L = R == 1u ? kScatterGroup : 4u;
+  CHECK(scatter_lds_bytes(P, false, L, R) <= kLdsPerCu, "ins scatter LDS P=%u", P);
+}
+
 static void check_counted(uint64_t n, uint32_t P, uint32_t mg) {
   uint32_t chunk, groups;
   chunking(n, mg, true, &chunk, &groups);
@@ -107,6 +128,7 @@ int main() {
     for (uint32_t P : Ps)
       for (uint32_t mg : mgs) {
         check_look(n, P, mg);
+        check_insert_buckets(n, P, mg);
         if (P <= kMaxSlices) check_counted(n, P, mg);
       }
   if (fails) {

@@ -532,3 +532,65 @@ def test_partitioned_lookup_grid_sizes(P, grid):
     bits = f.lookup_bits(dev(probes), launch=launch).cpu().numpy().view(np.uint32)
     assert np.array_equal(bits, oracle.lookup_bits(ref, B, probes))
     f.close()
+
+
+def test_partitioned_lookup_past_the_per_call_limit(P):
+    """2^31 + 1,000,003 lookups (a call takes at most 2^31 keys: the batch
+    runs as one full-size count-free partition, the largest its 32-bit
+    positions serve, then a 1M-key one; packed bits split at a word
+    boundary). Every sixteenth probe is a member; results are compared with
+    the oracle at 2M sampled positions plus both ends and the split, members
+    must all be found, and the bit output must pack the byte output."""
+    B = 4_194_304
+    n_ins = 10_000_000
+    n = (1 << 31) + 1_000_003
+    ins = splitmix64_stream(601, n_ins)
+    ref = oracle.build_filter(B, ins)
+    f = P.Filter(B)
+    f.insert(dev(ins), launch=dict(strategy=4))
+    probes = splitmix64_stream(602, n, backend="torch", device="cuda")
+    d_ins = dev(ins)
+    members = torch.arange(0, n, 16, device="cuda")
+    probes[members] = d_ins[members % n_ins]
+    del d_ins
+    out = f.lookup(probes, launch=dict(strategy=2))
+    assert bool(out[members].all().item())
+    rng = np.random.default_rng(603)
+    edges = np.concatenate([np.arange(0, 100_000), np.arange((1 << 31) - 100_000, (1 << 31) + 100_000),
+                            np.arange(n - 100_000, n)])
+    idx = np.unique(np.concatenate([rng.integers(0, n, 2_000_000), edges]))
+    d_idx = torch.from_numpy(idx.astype(np.int64)).to("cuda")
+    sample = probes[d_idx].cpu().numpy().view(np.uint64)
+    want = oracle.lookup(ref, B, sample)
+    assert np.array_equal(out[d_idx].cpu().numpy(), want)
+    bits = f.lookup_bits(probes, launch=dict(strategy=2))
+    del probes
+    got_bits = ((bits[d_idx // 32] >> (d_idx % 32).to(torch.int32)) & 1).to(torch.uint8).cpu().numpy()
+    assert np.array_equal(got_bits, want)
+    f.close()
+
+
+def test_partitioned_insert_past_the_per_call_limit(P):
+    """2^31 + 1,000,003 inserts (the partitioned insert takes at most 2^31
+    keys a call: one full-size bucketed partition, then a 1M-key one) give the
+    same filter as the 32-bit atomic insert of the same keys, and every
+    sixty-fourth key (a sample the oracle also inserts into an empty filter)
+    is then found. The atomic insert is compared with the oracle at smaller
+    sizes throughout this file."""
+    B = 4_194_304
+    n = (1 << 31) + 1_000_003
+    keys = splitmix64_stream(604, n, backend="torch", device="cuda")
+    f, g = P.Filter(B), P.Filter(B)
+    f.insert(keys, launch=dict(strategy=4))
+    g.insert(keys, launch=dict(strategy=1))
+    torch.cuda.synchronize()
+    assert torch.equal(f.words, g.words)
+    sample = keys[::64].contiguous()
+    del keys
+    assert bool(f.lookup(sample, launch=dict(strategy=2)).all().item())
+    # the oracle's filter of the sample alone is contained in the library's
+    ref = oracle.build_filter(B, sample[:2_000_000].cpu().numpy().view(np.uint64))
+    words = words_of(f)
+    assert np.array_equal(words & ref, ref)
+    f.close()
+    g.close()
