@@ -163,14 +163,14 @@ __device__ __forceinline__ uint64_t call_range(const uint64_t *off, const uint64
 // ---- insert -----------------------------------------------------------------
 
 // OR the mask of one key into the slice [b0, b0 + nb) of a filter of B blocks
-// held in LDS (four 64-bit words per block; pairs in a per-block rotated
-// order). A key outside the slice, or an invalid lane, ORs a zero mask into
+// held in LDS (four 64-bit words per block; pairs in the lane's rotated
+// order o). A key outside the slice, or an invalid lane, ORs a zero mask into
 // block 0.
 __device__ __forceinline__ void or_key(unsigned long long *lds2, uint64_t h, bool valid, uint32_t B, uint32_t b0,
-                                       uint32_t nb) {
+                                       uint32_t nb, const OrOrder<8> &o) {
   const uint32_t rel = block_of((uint32_t)(h >> 32), B) - b0;
   const bool in = valid && rel < nb;
-  lds_or_key<8>(lds2, in ? rel : 0u, (uint32_t)h, in ? 1u : 0u);
+  lds_or_key<8>(lds2, in ? rel : 0u, (uint32_t)h, in ? 1u : 0u, o);
 }
 
 // Partition of one chunk of a partitioned filter's insert keys by slice: rank
@@ -258,6 +258,7 @@ grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint32
   __shared__ uint32_t tile_id;
   const uint32_t lane = lane_id();
   const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const OrOrder<8> order = or_order<8>(lane);
   constexpr uint32_t waves = kInsertThreads / kWave;
   constexpr uint32_t U = 4;
   constexpr uint32_t kStep = 64u * U;
@@ -294,7 +295,7 @@ grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint32
         }
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u)
-          or_key(lds2, hv[u], base + 64u * u + lane < n, flt.num_blocks, tile.b0, tile.nb);
+          or_key(lds2, hv[u], base + 64u * u + lane < n, flt.num_blocks, tile.b0, tile.nb, order);
       }
     } else {
       const GRun *runs = plan.runs + plan.slices[tile.slice].run_off;
@@ -326,7 +327,7 @@ grouped_insert_kernel(GPlanDev plan, const uint64_t *__restrict__ hashes, uint32
           }
 #pragma unroll
           for (uint32_t u = 0; u < U; ++u)
-            or_key(lds2, hv[u], base + 64u * u + lane < total, flt.num_blocks, tile.b0, tile.nb);
+            or_key(lds2, hv[u], base + 64u * u + lane < total, flt.num_blocks, tile.b0, tile.nb, order);
         }
         __syncthreads();  // pre and off are rewritten by the next batch
       }

@@ -699,11 +699,14 @@ __device__ __forceinline__ void load_step(const uint64_t *__restrict__ keys, uin
 }
 
 // OR the masks of one step's keys into the slice in LDS: K/2 64-bit ORs per
-// key in a per-block rotated pair order (fewer LDS bank conflicts: on MI355X
-// the kernel takes 277 instead of 330 us for 1e8 keys into 128 MiB).
-template <uint32_t K>
+// key in the lane's rotated pair order o (fewer LDS bank conflicts than one
+// fixed order). kMaskTail: keys at or past ns OR nothing; without it they
+// are copies of the slice's last keys (clamped loads of whole, padded
+// groups), whose bits are set already.
+template <uint32_t K, bool kMaskTail>
 __device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, uint32_t ns, uint32_t num_blocks,
-                                            uint32_t b0, uint32_t nb, unsigned long long *lds2) {
+                                            uint32_t b0, uint32_t nb, unsigned long long *lds2,
+                                            const OrOrder<K> &o) {
   const uint32_t lane = lane_id();
 #pragma unroll
   for (uint32_t u = 0; u < kSliceSteps; ++u) {
@@ -713,8 +716,8 @@ __device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, u
       const uint64_t h = s.h[u][k];
       const uint32_t x = (uint32_t)h;
       const uint32_t bl = min(block_of((uint32_t)(h >> 32), num_blocks) - b0, nb - 1u);
-      const uint32_t one = at + k < ns ? 1u : 0u;
-      lds_or_key<K>(lds2, bl, x, one);
+      const uint32_t one = !kMaskTail || at + k < ns ? 1u : 0u;
+      lds_or_key<K>(lds2, bl, x, one, o);
     }
   }
 }
@@ -806,7 +809,8 @@ part_slice_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__re
   const uint32_t last = ((ns + 3u) & ~3u) - 4u;
   constexpr uint32_t waves = kPartThreads / kWave;
   constexpr bool kCachedKeys = false;
-#define SBBF_INSERT_STEP(S, BASE) insert_step<K>(S, BASE, ns, num_blocks, b0, nb, lds2)
+  const OrOrder<K> order = or_order<K>(lane_id());
+#define SBBF_INSERT_STEP(S, BASE) insert_step<K, true>(S, BASE, ns, num_blocks, b0, nb, lds2, order)
   SBBF_SLICE_LOOP(SBBF_INSERT_STEP);
 #undef SBBF_INSERT_STEP
   __syncthreads();
@@ -914,16 +918,17 @@ part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__r
   constexpr uint32_t stride = waves * 256u * kSliceSteps;
   uint32_t base = wave_index() * 256u * kSliceSteps;
   const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
+  const OrOrder<K> order = or_order<K>(lane_id());
   SliceStep sa, sb;
   load_step_buckets(part_slice, cap, prefix, map, map_shift, base, last, sa);
   for (uint32_t it = 0; it < steps; it += 2u) {
     load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sb);
     __builtin_amdgcn_sched_barrier(0);
-    insert_step<K>(sa, base, ns, num_blocks, b0, nb, lds2);
+    insert_step<K, false>(sa, base, ns, num_blocks, b0, nb, lds2, order);
     base += stride;
     load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sa);
     __builtin_amdgcn_sched_barrier(0);
-    insert_step<K>(sb, base, ns, num_blocks, b0, nb, lds2);
+    insert_step<K, false>(sb, base, ns, num_blocks, b0, nb, lds2, order);
     base += stride;
   }
   __syncthreads();

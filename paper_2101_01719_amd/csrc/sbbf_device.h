@@ -86,33 +86,47 @@ __device__ __forceinline__ uint32_t bit_of(uint32_t seed, uint32_t hash_lo) {
   return (seed * hash_lo) >> 27;
 }
 
-// OR the mask of one key (low hash half x) into block bl of a filter of K-word
-// blocks held in LDS as K/2 64-bit word pairs (one = 0 ORs nothing). The i-th
-// OR goes to pair p = (i + r) mod K/2, r taken from block-index bits above the
-// eight 32-byte blocks of one 256-byte LDS bank row: with one key per lane and
-// the pairs in a fixed order, the i-th ORs of a wave's keys all fall on one of
-// eight bank offsets; rotated, they spread over the whole row. OR is
-// order-free, so the filter is the same either way.
+// Order of the K/2 64-bit ORs with which lds_or_key sets a key's bits in an
+// LDS block of K words (as K/2 word pairs): the i-th OR goes to pair
+// p = (i + r) mod K/2 with seeds of words 2p and 2p + 1. With one key per
+// lane and the pairs in a fixed order, the i-th ORs of a wave's keys all fall
+// on one of eight 8-byte offsets of a 256-byte LDS bank row; with r taken from
+// the lane they spread over the whole row (random blocks give the rest). OR is
+// order-free, so the filter is the same either way. Built once per thread:
+// choosing the seeds per key costs about 25 compare-and-selects per key.
 template <uint32_t K>
-__device__ __forceinline__ void lds_or_key(unsigned long long *lds2, uint32_t bl, uint32_t x, uint32_t one) {
+struct OrOrder {
+  uint32_t sa[K / 2u], sb[K / 2u], pair[K / 2u];
+};
+
+template <uint32_t K>
+__device__ __forceinline__ OrOrder<K> or_order(uint32_t r) {
   constexpr uint32_t kPairs = K / 2u;
-  unsigned long long *blk = lds2 + (uint64_t)bl * kPairs;
-  const uint32_t r = ((bl >> 3) ^ (bl >> 5)) & (kPairs - 1u);
+  OrOrder<K> o;
 #pragma unroll
   for (uint32_t i = 0; i < kPairs; ++i) {
     const uint32_t p = (i + r) & (kPairs - 1u);
-    // seeds of words 2p and 2p + 1, picked by compare-and-select
-    uint32_t sa = seed_k(0), sb = seed_k(1);
-#pragma unroll
-    for (uint32_t j = 1; j < kPairs; ++j) {
-      sa = p == j ? seed_k(2u * j) : sa;
-      sb = p == j ? seed_k(2u * j + 1u) : sb;
-    }
-    __hip_atomic_fetch_or(blk + p,
-                          (unsigned long long)(one << bit_of(sa, x)) |
-                              ((unsigned long long)(one << bit_of(sb, x)) << 32),
-                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    o.sa[i] = seed_k(2u * p);
+    o.sb[i] = seed_k(2u * p + 1u);
+    o.pair[i] = p;
   }
+  return o;
+}
+
+// OR the mask of one key (low hash half x) into block bl of a filter of K-word
+// blocks held in LDS as K/2 64-bit word pairs (one = 0 ORs nothing), in the
+// order o.
+template <uint32_t K>
+__device__ __forceinline__ void lds_or_key(unsigned long long *lds2, uint32_t bl, uint32_t x, uint32_t one,
+                                           const OrOrder<K> &o) {
+  constexpr uint32_t kPairs = K / 2u;
+  unsigned long long *blk = lds2 + (uint64_t)bl * kPairs;
+#pragma unroll
+  for (uint32_t i = 0; i < kPairs; ++i)
+    __hip_atomic_fetch_or(blk + o.pair[i],
+                          (unsigned long long)(one << bit_of(o.sa[i], x)) |
+                              ((unsigned long long)(one << bit_of(o.sb[i], x)) << 32),
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
