@@ -341,7 +341,9 @@ def _union(P, torch, f, reps=10):
 
 def _keys(P, torch, f, w, ins_launch, look_launch, reps=5):
     """The same step with the hashes taken as keys (hashed on the device as
-    they are loaded): clear, insert_keys, lookup_keys."""
+    they are loaded): clear, insert_keys, lookup_keys; median of reps."""
+    import numpy as np
+
     out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
@@ -358,12 +360,13 @@ def _keys(P, torch, f, w, ins_launch, look_launch, reps=5):
 
     step(False)
     torch.cuda.synchronize()
-    ins_ms = look_ms = 0.0
+    t_ins, t_look = [], []
     for _ in range(reps):
         step(True)
         torch.cuda.synchronize()
-        ins_ms += ev[0].elapsed_time(ev[1]) / reps
-        look_ms += ev[1].elapsed_time(ev[2]) / reps
+        t_ins.append(ev[0].elapsed_time(ev[1]))
+        t_look.append(ev[1].elapsed_time(ev[2]))
+    ins_ms, look_ms = float(np.median(t_ins)), float(np.median(t_look))
     members_ok = bool(out[w.is_member].all().item())
     n = w.inserts.numel() + w.lookups.numel()
     return {"insert_ms": ins_ms, "lookup_ms": look_ms, "gkeys_per_s": n / ((ins_ms + look_ms) / 1e3) / 1e9,
@@ -373,8 +376,11 @@ def _keys(P, torch, f, w, ins_launch, look_launch, reps=5):
 def _variants(P, torch, w, reps=5):
     """The same step on the block variants with four and sixteen 32-bit words
     per block, each in a 128 MiB filter (the same bytes per key as the
-    eight-word filter): clear, insert, lookup with the library's strategies;
-    measured false-positive rate against the model with K words per block."""
+    eight-word filter): clear, insert, lookup with the library's strategies
+    (median of reps); measured false-positive rate against the model with K
+    words per block."""
+    import numpy as np
+
     out = torch.empty(w.lookups.numel(), dtype=torch.uint8, device="cuda")
     res = {}
     for lanes in (4, 16):
@@ -395,12 +401,13 @@ def _variants(P, torch, w, reps=5):
 
         step(False)
         torch.cuda.synchronize()
-        ins_ms = look_ms = 0.0
+        t_ins, t_look = [], []
         for _ in range(reps):
             step(True)
             torch.cuda.synchronize()
-            ins_ms += ev[0].elapsed_time(ev[1]) / reps
-            look_ms += ev[1].elapsed_time(ev[2]) / reps
+            t_ins.append(ev[0].elapsed_time(ev[1]))
+            t_look.append(ev[1].elapsed_time(ev[2]))
+        ins_ms, look_ms = float(np.median(t_ins)), float(np.median(t_look))
         n_ins, n_look = w.inserts.numel(), w.lookups.numel()
         fpr = float(out[~w.is_member].float().mean().item())
         res[str(lanes)] = {

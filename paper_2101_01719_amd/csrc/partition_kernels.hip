@@ -58,9 +58,14 @@ namespace {
 constexpr uint32_t kPartThreads = 1024;    // count, scan, slice and unpermute kernels
 constexpr uint32_t kMaxSlices = 4096;       // slices per partitioned filter
 constexpr uint32_t kScatterThreads = 1024;
-constexpr uint32_t kScatterPer = 7;        // keys per thread per scatter tile
+constexpr uint32_t kScatterPer = 7;        // keys per thread per scatter tile (lookups, counted inserts)
 constexpr uint32_t kScatterGroup = 8;      // keys per aligned group written by the scatter (64 bytes)
 constexpr uint32_t kTile = kScatterThreads * kScatterPer;
+// Keys per thread per tile of the bucketed insert scatter: one more than the
+// lookup scatter (which needs the registers for its positions), so fewer
+// barriers per key.
+constexpr uint32_t kInsertPer = 8;
+constexpr uint32_t kInsertTile = kScatterThreads * kInsertPer;
 constexpr uint32_t kScanRows = 256;    // rows per colsum/colscan workgroup (16 segments of 16)
 constexpr uint32_t kScanCols = 64;     // columns per colsum/colscan workgroup
 constexpr uint32_t kSliceSteps = 2;    // 256-key steps per wave per slice-loop iteration
@@ -207,16 +212,19 @@ part_offsets_kernel(const uint32_t *__restrict__ tot, uint32_t num_slices, uint3
 
 // Scatter LDS for groups of L keys (L = 1: no carry). The stage holds one
 // tile's keys sorted by slice, each slice's run preceded by the keys carried
-// over from the previous tile, so its size is kTile + (L - 1) * (slices),
-// slices = R * kScatterThreads.
-constexpr uint32_t stage_keys(uint32_t L, uint32_t R) { return kTile + (L - 1u) * R * kScatterThreads; }
+// over from the previous tile, so its size is (tile keys) + (L - 1) * (slices),
+// slices = R * kScatterThreads; a tile is per keys of each thread.
+constexpr uint32_t stage_keys(uint32_t L, uint32_t R, uint32_t per) {
+  return per * kScatterThreads + (L - 1u) * R * kScatterThreads;
+}
 
-constexpr size_t scatter_lds_bytes(uint32_t num_slices, bool with_pos, uint32_t L, uint32_t R) {
-  return (size_t)stage_keys(L, R) * 8u + (size_t)num_slices * (with_pos ? 20u : 16u) + 80u;
+constexpr size_t scatter_lds_bytes(uint32_t num_slices, bool with_pos, uint32_t L, uint32_t R,
+                                   uint32_t per = kScatterPer) {
+  return (size_t)stage_keys(L, R, per) * 8u + (size_t)num_slices * (with_pos ? 20u : 16u) + 80u;
 }
 
 struct ScatterLds {
-  uint64_t *stage;  // [stage_keys(L)] keys sorted by slice
+  uint64_t *stage;  // [stage_keys(L, R, per)] keys sorted by slice
   uint2 *info;      // [P] staged position k < info.y of slice s goes to k + info.x
   uint32_t *hist;   // [P] keys per slice in the tile (ranks come from it)
   uint32_t *sbase;  // [P] staged position of the tile's first key of slice s
@@ -234,12 +242,12 @@ struct ScatterLds {
 // MI355X at 1e8 inserts and 2e8 lookups into 128 MiB, that order is 6 %
 // faster for the lookup scatter (and its slice kernel) and 5 % faster for
 // the insert scatter than the other.
-template <bool kCached>
+template <bool kCached, uint32_t P>
 __device__ __forceinline__ void load_tile(const uint64_t *__restrict__ hashes, uint32_t t0, uint32_t e,
-                                          uint64_t (&h)[kScatterPer]) {
+                                          uint64_t (&h)[P]) {
   constexpr uint32_t kLoad = kCached ? (uint32_t)SBBF_HASH_LOAD_CACHED : 0u;
 #pragma unroll
-  for (uint32_t t = 0; t < kScatterPer; ++t) {
+  for (uint32_t t = 0; t < P; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
     h[t] = load_hash<kLoad>(hashes + (i < e ? i : e - 1u));
   }
@@ -321,8 +329,8 @@ __device__ __forceinline__ void look_bucket_chunk(SliceCursor<R> &C, uint32_t nu
 // of L keys with consecutive lanes; the incomplete tail of each slice's run
 // stays in the stage as the next tile's carry. kFull: the whole tile is
 // inside the chunk (no per-key guards).
-template <bool kWithPos, int R, uint32_t L, bool kBucket, bool kFull>
-__device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_t t0, uint32_t e,
+template <bool kWithPos, int R, uint32_t L, bool kBucket, bool kFull, uint32_t P>
+__device__ __forceinline__ void scatter_tile(uint64_t (&h)[P], uint32_t t0, uint32_t e,
                                              const uint32_t *__restrict__ new_chunk_hist, uint32_t new_chunk,
                                              uint32_t num_blocks,
                                              uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
@@ -332,7 +340,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
   // Keys are hashed here, where the prefetched tile is first used.
   if (keys) {
 #pragma unroll
-    for (uint32_t t = 0; t < kScatterPer; ++t) h[t] = key_hash(h[t]);
+    for (uint32_t t = 0; t < P; ++t) h[t] = key_hash(h[t]);
   }
   static_assert(L == 1u || R <= 2, "carried groups need at most two slices per thread");
   static_assert(!kBucket || L >= 4u, "buckets are written with carried groups");
@@ -357,9 +365,9 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
       }
     }
   }
-  uint32_t s[kScatterPer], rank[kScatterPer];
+  uint32_t s[P], rank[P];
 #pragma unroll
-  for (uint32_t t = 0; t < kScatterPer; ++t) {
+  for (uint32_t t = 0; t < P; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
     s[t] = local_slice(h[t], num_blocks, slice_shift, slice_base, num_slices);
     rank[t] = __hip_atomic_fetch_add(S.hist + s[t], (kFull || i < e) ? 1u : 0u, __ATOMIC_RELAXED,
@@ -429,7 +437,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
   }
   lds_barrier();
 #pragma unroll
-  for (uint32_t t = 0; t < kScatterPer; ++t) {
+  for (uint32_t t = 0; t < P; ++t) {
     const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
     if (kFull || i < e) {
       // Positions are read back only by the unpermute kernel, after the
@@ -454,7 +462,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
     // any position of their chunk (the overflow pass rewrites their results).
     if (*S.spilled) {
 #pragma unroll
-      for (uint32_t t = 0; t < kScatterPer; ++t) {
+      for (uint32_t t = 0; t < P; ++t) {
         const uint32_t i = t0 + t * kScatterThreads + threadIdx.x;
         if ((kFull || i < e) && rank[t] >= (S.sp[s[t]].y >> 16)) {
           const uint32_t o = __hip_atomic_fetch_add(Bk.ovf_n, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -470,7 +478,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
   if constexpr (kWithPos && kBucket)
     if (threadIdx.x == 0) *S.spilled = 0u;
 #pragma unroll
-  for (uint32_t t = 0; t < kScatterPer + (L - 1u) * R; ++t) {
+  for (uint32_t t = 0; t < P + (L - 1u) * R; ++t) {
     const uint32_t k = t * kScatterThreads + threadIdx.x;
     if ((L == 1u && kFull) || k < total) {
       const uint64_t key = S.stage[k];
@@ -496,7 +504,7 @@ __device__ __forceinline__ void scatter_tile(uint64_t (&h)[kScatterPer], uint32_
 // inside the chunk's own results, which is what the unpermute kernel reads
 // back from LDS: counted, the chunk's runs of all slices laid end to end in
 // slice order; bucketed, slot s of room positions for slice s.
-template <bool kWithPos, int R, uint32_t L, bool kBucket>
+template <bool kWithPos, int R, uint32_t L, bool kBucket, uint32_t P>
 __global__ void __launch_bounds__(kScatterThreads)
 part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t chunk, uint32_t chunks_per_group,
                     uint32_t num_blocks, uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices,
@@ -506,7 +514,7 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
   extern __shared__ unsigned long long smem[];
   ScatterLds S;
   S.stage = reinterpret_cast<uint64_t *>(smem);
-  S.info = reinterpret_cast<uint2 *>(S.stage + stage_keys(L, R));
+  S.info = reinterpret_cast<uint2 *>(S.stage + stage_keys(L, R, P));
   S.hist = reinterpret_cast<uint32_t *>(S.info + num_slices);
   S.sbase = S.hist + num_slices;
   S.pdelta = S.sbase + num_slices;
@@ -565,29 +573,30 @@ part_scatter_kernel(const uint64_t *__restrict__ hashes, uint32_t n, uint32_t ch
 
   // Tiles alternate between two register sets so the next tile's loads are
   // issued before this tile's stores and need no register copies.
-  const uint32_t nfull = (e - b) / kTile;
-  uint64_t ha[kScatterPer], hb[kScatterPer];
-  load_tile<kWithPos>(hashes, b, e, ha);
+  constexpr uint32_t kT = P * kScatterThreads;
+  const uint32_t nfull = (e - b) / kT;
+  uint64_t ha[P], hb[P];
+  load_tile<kWithPos, P>(hashes, b, e, ha);
   uint32_t t0 = b, k = 0;
 #define SBBF_SCATTER_TILE(FULL, H)                                                                            \
-  scatter_tile<kWithPos, R, L, kBucket, FULL>(                                                                \
+  scatter_tile<kWithPos, R, L, kBucket, FULL, P>(                                                              \
       H, t0, e,                                                                                               \
       kWithPos && !kBucket && t0 != b && t0 % chunk == 0u ? hist_rows + (uint64_t)(t0 / chunk) * num_slices  \
                                                           : nullptr,                                         \
       kWithPos && kBucket && t0 != b && t0 % chunk == 0u ? t0 / chunk : ~0u, num_blocks, slice_shift,         \
       slice_base, num_slices, keys, S, C, out_keys, out_pos, Bk)
   for (; k + 2u <= nfull; k += 2u) {
-    load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
+    load_tile<kWithPos, P>(hashes, t0 + kT, e, hb);
     SBBF_SCATTER_TILE(true, ha);
-    t0 += kTile;
-    load_tile<kWithPos>(hashes, t0 + kTile, e, ha);
+    t0 += kT;
+    load_tile<kWithPos, P>(hashes, t0 + kT, e, ha);
     SBBF_SCATTER_TILE(true, hb);
-    t0 += kTile;
+    t0 += kT;
   }
   if (k < nfull) {
-    load_tile<kWithPos>(hashes, t0 + kTile, e, hb);
+    load_tile<kWithPos, P>(hashes, t0 + kT, e, hb);
     SBBF_SCATTER_TILE(true, ha);
-    t0 += kTile;
+    t0 += kT;
     if (t0 < e) SBBF_SCATTER_TILE(false, hb);
   } else if (t0 < e) {
     SBBF_SCATTER_TILE(false, ha);
@@ -724,8 +733,8 @@ __device__ __forceinline__ void insert_step(const SliceStep &s, uint32_t base, u
 
 // Test one step's keys against the slice in LDS (K/4 16-byte reads per key)
 // and write their results as bits: lane l's four keys give a nibble, lanes
-// 8m .. 8m+7 OR theirs into the word of keys base + 32m .. +31 (three lane
-// exchanges), which lane 8m stores when that word starts inside the slice.
+// 8m .. 8m+7 OR theirs into the word of keys base + 32m .. +31 (three DPP
+// moves), which lane 8m stores when that word starts inside the slice.
 // begin and base are multiples of 32, so words are whole; keys at or past ns
 // give 0 bits.
 template <uint32_t K>
@@ -756,9 +765,7 @@ __device__ __forceinline__ void lookup_step(const SliceStep &s, uint32_t base, u
       r |= (at + k < ns ? t & 1u : 0u) << k;
     }
     uint32_t word = r << (4u * (lane & 7u));
-    word |= (uint32_t)__shfl_xor((int)word, 1);
-    word |= (uint32_t)__shfl_xor((int)word, 2);
-    word |= (uint32_t)__shfl_xor((int)word, 4);
+    word = or_over_eights(word);
     const uint32_t first = base + 256u * u + 32u * (lane >> 3);
     if ((lane & 7u) == 0u && first < ns) res32[(begin + first) / 32u] = word;
   }
@@ -1011,9 +1018,7 @@ __device__ __forceinline__ void bucket_lookup_step(const BucketLookStep &s, uint
       r |= (k < s.valid[u] ? t & 1u : 0u) << k;
     }
     uint32_t word = r << (4u * (lane & 7u));
-    word |= (uint32_t)__shfl_xor((int)word, 1);
-    word |= (uint32_t)__shfl_xor((int)word, 2);
-    word |= (uint32_t)__shfl_xor((int)word, 4);
+    word = or_over_eights(word);
     const uint32_t first = base + 256u * u + 32u * (lane >> 3);
     if ((lane & 7u) == 0u && first < ns) res32[s.dw[u]] = word;
   }
@@ -1276,9 +1281,7 @@ __device__ __forceinline__ void unpermute_write(const uint32_t *maps, uint32_t m
               if (i + k < e) nib |= bit(vals, pos[i + k]) << k;
           }
           uint32_t w = nib << (4u * (lane & 7u));
-          w |= (uint32_t)__shfl_xor((int)w, 1);
-          w |= (uint32_t)__shfl_xor((int)w, 2);
-          w |= (uint32_t)__shfl_xor((int)w, 4);
+          w = or_over_eights(w);
           const uint32_t first = span + 32u * (lane >> 3);
           if ((lane & 7u) == 0 && first < e) out_bits[first / 32u] = w;
         }
@@ -1498,14 +1501,15 @@ PartitionLayout layout(void *workspace, uint64_t n, uint32_t num_slices, uint32_
 // (chunk length + a tile of fixed work per chunk): e.g. 2e8 keys take 8-tile
 // chunks (3,488, seven full rounds of 512) rather than 9-tile ones (3,101, a
 // seventh round almost empty).
-void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uint32_t *groups) {
-  const uint64_t tiles = (n + kTile - 1) / kTile;
+void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uint32_t *groups,
+              uint32_t tile = kTile) {
+  const uint64_t tiles = (n + tile - 1) / tile;
   const uint64_t g0 = tiles < max_groups ? (tiles ? tiles : 1) : max_groups;
   uint64_t tiles_per = (tiles + g0 - 1) / g0;
-  if (lookup && tiles_per * kTile > kLookupChunk) {
+  if (lookup && tiles_per * tile > kLookupChunk) {
     const uint64_t slots = max_groups ? max_groups : 1u;
-    uint64_t best = kLookupChunk / kTile, best_cost = UINT64_MAX;
-    for (uint64_t tp = kLookupChunk / kTile; tp >= 5u; --tp) {
+    uint64_t best = kLookupChunk / tile, best_cost = UINT64_MAX;
+    for (uint64_t tp = kLookupChunk / tile; tp >= 5u; --tp) {
       const uint64_t g = (tiles + tp - 1u) / tp;
       // rounds x (chunk length + one tile for each chunk's fixed work: its
       // count row, the unpermute's scan over the slices)
@@ -1517,24 +1521,24 @@ void chunking(uint64_t n, uint32_t max_groups, bool lookup, uint32_t *chunk, uin
     }
     tiles_per = best;
   }
-  *chunk = (uint32_t)(tiles_per * kTile);
+  *chunk = (uint32_t)(tiles_per * tile);
   *groups = (uint32_t)((n + *chunk - 1) / *chunk);
   if (*groups == 0) *groups = 1;
 }
 
-template <bool kWithPos, int R, uint32_t L, bool kBucket = false>
+template <bool kWithPos, int R, uint32_t L, bool kBucket = false, uint32_t P = kScatterPer>
 hipError_t launch_scatter(const uint64_t *hashes, uint32_t n, uint32_t chunk, uint32_t groups, uint32_t num_blocks,
                           uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, uint32_t keys,
                           const PartitionLayout &L_, hipStream_t stream, const Buckets &Bk = Buckets{}) {
-  const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L, R);
+  const size_t lds = scatter_lds_bytes(num_slices, kWithPos, L, R, P);
   // Several chunks per workgroup (lookups cut the batch finer than inserts):
   // about two workgroups per compute unit.
   const uint32_t per = kWithPos ? (groups + L_.scatter_groups - 1u) / L_.scatter_groups : 1u;
   const uint32_t grid = (groups + per - 1u) / per;
-  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R, L, kBucket>,
+  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<kWithPos, R, L, kBucket, P>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
-  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L, kBucket>), dim3(grid), dim3(kScatterThreads), lds, stream,
+  hipLaunchKernelGGL((part_scatter_kernel<kWithPos, R, L, kBucket, P>), dim3(grid), dim3(kScatterThreads), lds, stream,
                      hashes, n, chunk, per, num_blocks, slice_shift, slice_base, num_slices, L_.offsets, L_.start,
                      L_.hist, keys, L_.keys, kWithPos ? L_.pos : nullptr, Bk);
   return hipGetLastError();
@@ -1660,7 +1664,7 @@ struct BucketPlan {
 
 bool bucket_plan(uint64_t n, uint32_t num_slices, uint32_t max_groups, BucketPlan *bp) {
   if (n == 0 || num_slices > 2u * kScatterThreads) return false;
-  chunking(n, max_groups, false, &bp->chunk, &bp->groups);
+  chunking(n, max_groups, false, &bp->chunk, &bp->groups, kInsertTile);
   if (bp->groups > kMaxBucketGroups) return false;
   // Keys of one chunk per slice: a slice holds at most 1 / (slices - 1) of
   // the blocks (all but the last are whole).
@@ -1717,11 +1721,11 @@ hipError_t insert_buckets(const uint64_t *hashes, uint32_t n, uint32_t *words, u
   L.keys = reinterpret_cast<uint64_t *>(base + bp.keys_off);
   L.scatter_groups = bp.groups;
   if (num_slices <= kScatterThreads)
-    e = launch_scatter<false, 1, kScatterGroup, true>(hashes, n, bp.chunk, bp.groups, num_blocks, slice_shift, 0u,
-                                                       num_slices, keys, L, stream, Bk);
+    e = launch_scatter<false, 1, kScatterGroup, true, kInsertPer>(hashes, n, bp.chunk, bp.groups, num_blocks,
+                                                                   slice_shift, 0u, num_slices, keys, L, stream, Bk);
   else
-    e = launch_scatter<false, 2, 4, true>(hashes, n, bp.chunk, bp.groups, num_blocks, slice_shift, 0u, num_slices,
-                                          keys, L, stream, Bk);
+    e = launch_scatter<false, 2, 4, true, kInsertPer>(hashes, n, bp.chunk, bp.groups, num_blocks, slice_shift, 0u,
+                                                      num_slices, keys, L, stream, Bk);
   if (e != hipSuccess) return e;
   if (lanes == 4) {
     e = launch_bucket_insert<4>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
@@ -1845,10 +1849,11 @@ hipError_t launch_look_scatter(const uint64_t *hashes, uint32_t n, const LookPla
                                uint32_t slice_shift, uint32_t slice_base, uint32_t num_slices, uint32_t keys,
                                uint64_t *part, uint16_t *pos, const Buckets &Bk, hipStream_t stream) {
   const size_t lds = scatter_lds_bytes(num_slices, true, L, R);
-  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<true, R, L, true>,
+  (void)hipFuncSetAttribute((const void *)part_scatter_kernel<true, R, L, true, kScatterPer>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   (void)hipGetLastError();
-  hipLaunchKernelGGL((part_scatter_kernel<true, R, L, true>), dim3(lp.sgroups), dim3(kScatterThreads), lds, stream,
+  hipLaunchKernelGGL((part_scatter_kernel<true, R, L, true, kScatterPer>), dim3(lp.sgroups), dim3(kScatterThreads), lds,
+                     stream,
                      hashes, n, lp.chunk, lp.per, num_blocks, slice_shift, slice_base, num_slices, nullptr, nullptr,
                      nullptr, keys, part, pos, Bk);
   return hipGetLastError();

@@ -131,6 +131,16 @@ __device__ __forceinline__ void lds_or_key(unsigned long long *lds2, uint32_t bl
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// OR of w over each aligned group of eight lanes, in every lane of the group,
+// by DPP moves (no LDS traffic): lanes exchanged within quads (xor 1, then
+// xor 2), then lane i with lane 7 - i of each eight (half-row mirror).
+__device__ __forceinline__ uint32_t or_over_eights(uint32_t w) {
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x141, 0xf, 0xf, false);  // row_half_mirror
+  return w;
+}
+
 // Value of `v` in lane `src` (0..63) of this wave.
 __device__ __forceinline__ uint32_t lane_read(uint32_t v, uint32_t src) {
   return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);

@@ -86,7 +86,7 @@ static void check_insert_buckets(uint64_t n, uint32_t P, uint32_t mg) {
   BucketPlan bp;
   if (!bucket_plan(n, P, mg, &bp)) return;  // the counted insert partition then
   const unsigned long long nn = n;
-  CHECK(bp.groups >= 1u && bp.groups <= kMaxBucketGroups && bp.chunk % kTile == 0u, "ins n=%llu P=%u mg=%u", nn, P,
+  CHECK(bp.groups >= 1u && bp.groups <= kMaxBucketGroups && bp.chunk % kInsertTile == 0u, "ins n=%llu P=%u mg=%u", nn, P,
         mg);
   CHECK((uint64_t)bp.groups * bp.chunk >= n && (uint64_t)(bp.groups - 1u) * bp.chunk < n, "ins n=%llu", nn);
   CHECK(bp.cap % 8u == 0u && bp.cap >= 32u, "ins cap n=%llu P=%u", nn, P);   // whole 64-byte groups
@@ -100,7 +100,7 @@ static void check_insert_buckets(uint64_t n, uint32_t P, uint32_t mg) {
   }
   CHECK(partition_workspace_bytes(n, P, mg, false) >= bp.bytes, "ins ws n=%llu P=%u", nn, P);
   const uint32_t R = P <= kScatterThreads ? 1u : 2u, L = R == 1u ? kScatterGroup : 4u;
-  CHECK(scatter_lds_bytes(P, false, L, R) <= kLdsPerCu, "ins scatter LDS P=%u", P);
+  CHECK(scatter_lds_bytes(P, false, L, R, kInsertPer) <= kLdsPerCu, "ins scatter LDS P=%u", P);
 }
 
 static void check_counted(uint64_t n, uint32_t P, uint32_t mg) {
