@@ -1015,8 +1015,9 @@ __device__ __forceinline__ void bucket_lookup_step(const BucketLookStep &s, uint
       for (uint32_t q = 0; q < V; ++q)
         t &= (w[k][q].x >> bit_of(seed_k(4u * q), x)) & (w[k][q].y >> bit_of(seed_k(4u * q + 1u), x)) &
              (w[k][q].z >> bit_of(seed_k(4u * q + 2u), x)) & (w[k][q].w >> bit_of(seed_k(4u * q + 3u), x));
-      r |= (k < s.valid[u] ? t & 1u : 0u) << k;
+      r |= (t & 1u) << k;
     }
+    r &= (1u << s.valid[u]) - 1u;  // the step's keys of the bucket (0 to 4)
     uint32_t word = r << (4u * (lane & 7u));
     word = or_over_eights(word);
     const uint32_t first = base + 256u * u + 32u * (lane >> 3);
