@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <string>
@@ -23,9 +24,12 @@ namespace {
 
 thread_local std::string t_last_error;
 
+// Indexed by device id. A deque: growing it for a new device keeps the entries
+// other threads already hold references to in place; an entry is written once,
+// under the lock, before it is marked valid, and never changes after.
 std::mutex g_info_mu;
-std::vector<sbbf_device_info> g_info;  // indexed by device id
-std::vector<bool> g_info_valid;
+std::deque<sbbf_device_info> g_info;
+std::deque<bool> g_info_valid;
 
 // Default launch shape: 256-thread workgroups and enough of them to give every
 // compute unit 8 workgroups (32 waves) when the batch is large enough; the
@@ -92,7 +96,8 @@ const sbbf_device_info &device_info(int device) {
       g_info_valid[device] = true;
     } else {
       (void)hipGetLastError();
-      return g_info[device];  // zeros; callers check compute_units
+      static const sbbf_device_info kNone{};  // zeros; callers check compute_units
+      return kNone;
     }
   }
   return g_info[device];

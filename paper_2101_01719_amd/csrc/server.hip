@@ -285,7 +285,10 @@ struct sbbf_server {
   std::vector<sbbf::Request> reqs;
   std::deque<uint32_t> ready;  // filters with pending requests, in order of first arrival
   std::vector<sbbf::Slot> slots;
-  std::vector<uint64_t> completed;  // completed request ids not yet polled
+  // completed request ids; those from completed_head on are not yet polled
+  // (a head index, so that polling in small batches does not shift the rest)
+  std::vector<uint64_t> completed;
+  size_t completed_head = 0;
   uint64_t pending = 0, inflight = 0;
   // statistics
   uint64_t steps = 0, keys_done = 0, req_done = 0;
@@ -634,9 +637,17 @@ sbbf_status sbbf_server_poll(sbbf_server *s, uint64_t *done_ids, uint32_t cap, u
   if (!s || !n_done || (cap && !done_ids)) return set_error(SBBF_EINVAL, "bad poll arguments");
   sbbf_status st = server_harvest(s, false);
   if (st != SBBF_OK) return st;
-  const uint32_t n = (uint32_t)std::min<size_t>(cap, s->completed.size());
-  for (uint32_t i = 0; i < n; ++i) done_ids[i] = s->completed[i];
-  s->completed.erase(s->completed.begin(), s->completed.begin() + n);
+  const uint32_t n = (uint32_t)std::min<size_t>(cap, s->completed.size() - s->completed_head);
+  for (uint32_t i = 0; i < n; ++i) done_ids[i] = s->completed[s->completed_head + i];
+  s->completed_head += n;
+  if (s->completed_head == s->completed.size()) {
+    s->completed.clear();
+    s->completed_head = 0;
+  } else if (s->completed_head >= 4096 && 2 * s->completed_head >= s->completed.size()) {
+    // drop the polled front once it is at least half of the list
+    s->completed.erase(s->completed.begin(), s->completed.begin() + (ptrdiff_t)s->completed_head);
+    s->completed_head = 0;
+  }
   *n_done = n;
   return n ? SBBF_OK : SBBF_EAGAIN;
 }
