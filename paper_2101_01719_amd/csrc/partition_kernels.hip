@@ -666,34 +666,6 @@ __device__ __forceinline__ void load_slice_to_lds(uint4 *lds4, const uint32_t *w
   }
 }
 
-// The words of a slice (nb blocks of K words from block b0, at most 128 KiB)
-// in registers, eight 16-byte pieces per thread (non-temporal: each slice is
-// read once per call), and their store into LDS. The persistent bucketed
-// slice kernels load the next slice this way while they test or insert the
-// keys of the current one.
-template <uint32_t K>
-__device__ __forceinline__ void load_slice_regs(const uint32_t *words, uint32_t b0, uint32_t nb, u64x2 (&q)[8]) {
-  static_assert(8u * kPartThreads * 16u >= (128u << 10), "one round of loads holds a slice");
-  const u64x2 *src = reinterpret_cast<const u64x2 *>(words + (uint64_t)b0 * K);
-  const uint32_t count4 = nb * (K / 4u);
-#pragma unroll
-  for (uint32_t u = 0; u < 8u; ++u) {
-    const uint32_t i = u * kPartThreads + threadIdx.x;
-    q[u] = i < count4 ? __builtin_nontemporal_load(src + i) : u64x2{0ull, 0ull};
-  }
-}
-
-template <uint32_t K>
-__device__ __forceinline__ void store_slice_lds(uint4 *lds4, uint32_t nb, const u64x2 (&q)[8]) {
-  const uint32_t count4 = nb * (K / 4u);
-#pragma unroll
-  for (uint32_t u = 0; u < 8u; ++u) {
-    const uint32_t i = u * kPartThreads + threadIdx.x;
-    if (i < count4) lds4[i] = make_uint4((uint32_t)q[u].x, (uint32_t)(q[u].x >> 32), (uint32_t)q[u].y,
-                                         (uint32_t)(q[u].y >> 32));
-  }
-}
-
 // Slice kernels: one lane per key, four keys per lane per step. Slice s's
 // keys start 32-byte aligned (offsets are multiples of four keys), so a lane
 // reads its four hashes with two 16-byte loads. Wave w takes steps of 256
@@ -890,90 +862,85 @@ __device__ __forceinline__ void load_step_buckets(const uint64_t *__restrict__ p
 }
 
 // Slice insert over the fixed-capacity buckets of a count-free partition
-// (one bucket per scatter workgroup). Persistent: workgroup w takes slices w,
-// w + G, w + 2G, ... (G = gridDim.x, at most one workgroup per compute unit).
-// Per slice: the buckets' key counts scanned into a prefix and a coarse map
-// behind the slice in LDS, the slice's words (loaded into registers during
-// the previous slice) stored into LDS, the next slice's words and counts
-// loaded into registers, the slice loop over the buckets as one sequence, and
-// the slice stored back.
+// (one bucket per scatter workgroup): the slice in LDS, then the buckets' key
+// counts scanned into a prefix and a coarse map after it, then the slice
+// loop over the buckets as one sequence.
 template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_bucket_insert_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ counts, uint32_t groups,
-                          uint32_t cap, uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift,
-                          uint32_t num_slices) {
+                          uint32_t cap, uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift) {
   extern __shared__ uint4 lds4[];
   unsigned long long *lds2 = reinterpret_cast<unsigned long long *>(lds4);
+  const uint32_t slice = blockIdx.x;
+  const uint32_t b0 = slice << slice_shift;
+  const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
   // after the largest slice: prefix [kMaxBucketGroups + 1], map [kBucketMap + 1], wsum [16]
   uint32_t *prefix = reinterpret_cast<uint32_t *>(lds4 + (((size_t)1 << slice_shift) * K) / 4u);
   uint16_t *map = reinterpret_cast<uint16_t *>(prefix + kMaxBucketGroups + 1u);
   uint32_t *wsum = prefix + kMaxBucketGroups + 1u + (kBucketMap + 2u) / 2u;
-  const OrOrder<K> order = or_order<K>(lane_id());
+  const uint32_t *my_counts = counts + (uint64_t)slice * groups;
+  uint32_t ns;
+  const uint32_t cnt = threadIdx.x < groups ? my_counts[threadIdx.x] : 0u;
+  // The slice's loads are issued before the scan and the map are built (a
+  // slice is at most 128 KiB: eight 16-byte pieces per thread) and stored to
+  // LDS after.
+  static_assert(8u * kPartThreads * 16u >= (128u << 10), "one round of loads holds a slice");
+  const u64x2 *src = reinterpret_cast<const u64x2 *>(words + (uint64_t)b0 * K);
+  const uint32_t count4 = nb * (K / 4u);
+  u64x2 q[8];
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    q[u] = i < count4 ? __builtin_nontemporal_load(src + i) : u64x2{0ull, 0ull};
+  }
+  uint32_t start;
+  {
+    const uint32_t c[1] = {cnt};
+    start = block_scan_owned<1>(c, wsum, &ns);
+  }
+  if (ns == 0) return;  // whole workgroup: the slice is unchanged
+  // Smallest map_shift >= 6 with at most kBucketMap map entries.
+  uint32_t map_shift = 6;
+  while (((ns - 1u) >> map_shift) + 1u > kBucketMap) ++map_shift;
+  const uint32_t entries = ((ns - 1u) >> map_shift) + 1u;
+  if (threadIdx.x < groups) {
+    prefix[threadIdx.x] = start;
+    // map entries whose position lies in this (non-empty) bucket
+    for (uint32_t m = (uint32_t)(((uint64_t)start + (1u << map_shift) - 1u) >> map_shift);
+         ((uint64_t)m << map_shift) < (uint64_t)start + cnt; ++m)
+      map[m] = (uint16_t)threadIdx.x;
+  }
+  if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);  // upper bound for the last entry
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    if (i < count4) lds4[i] = make_uint4((uint32_t)q[u].x, (uint32_t)(q[u].x >> 32), (uint32_t)q[u].y,
+                                         (uint32_t)(q[u].y >> 32));
+  }
+  __syncthreads();
+
+  const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
+  const uint32_t last = ns - 4u;  // counts are multiples of four
   constexpr uint32_t waves = kPartThreads / kWave;
   constexpr uint32_t stride = waves * 256u * kSliceSteps;
-  uint32_t slice = blockIdx.x;
-  uint32_t b0 = slice << slice_shift;
-  uint32_t nb = min(1u << slice_shift, num_blocks - b0);
-  uint32_t cnt = threadIdx.x < groups ? counts[(uint64_t)slice * groups + threadIdx.x] : 0u;
-  u64x2 q[8];
-  load_slice_regs<K>(words, b0, nb, q);
-  for (;;) {
-    // (the scan's barrier: every wave has finished the previous slice,
-    // including its reads of LDS for the store back)
-    uint32_t start, ns;
-    {
-      const uint32_t c[1] = {cnt};
-      start = block_scan_owned<1>(c, wsum, &ns);
-    }
-    uint32_t map_shift = 6;
-    if (ns > 0) {  // (uniform) an empty slice is left unchanged
-      // Smallest map_shift >= 6 with at most kBucketMap map entries.
-      while (((ns - 1u) >> map_shift) + 1u > kBucketMap) ++map_shift;
-      const uint32_t entries = ((ns - 1u) >> map_shift) + 1u;
-      if (threadIdx.x < groups) {
-        prefix[threadIdx.x] = start;
-        // map entries whose position lies in this (non-empty) bucket
-        for (uint32_t m = (uint32_t)(((uint64_t)start + (1u << map_shift) - 1u) >> map_shift);
-             ((uint64_t)m << map_shift) < (uint64_t)start + cnt; ++m)
-          map[m] = (uint16_t)threadIdx.x;
-      }
-      if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);  // upper bound for the last entry
-      store_slice_lds<K>(lds4, nb, q);
-    }
-    const uint32_t next = slice + gridDim.x;
-    const uint32_t b0n = next << slice_shift;
-    const uint32_t nbn = next < num_slices ? min(1u << slice_shift, num_blocks - b0n) : 0u;
-    if (next < num_slices) {
-      cnt = threadIdx.x < groups ? counts[(uint64_t)next * groups + threadIdx.x] : 0u;
-      load_slice_regs<K>(words, b0n, nbn, q);
-    }
-    __syncthreads();
-    if (ns > 0) {
-      const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
-      const uint32_t last = ns - 4u;  // counts are multiples of four
-      uint32_t base = wave_index() * 256u * kSliceSteps;
-      const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
-      SliceStep sa, sb;
-      load_step_buckets(part_slice, cap, prefix, map, map_shift, base, last, sa);
-      for (uint32_t it = 0; it < steps; it += 2u) {
-        load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sb);
-        __builtin_amdgcn_sched_barrier(0);
-        insert_step<K, false>(sa, base, ns, num_blocks, b0, nb, lds2, order);
-        base += stride;
-        load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sa);
-        __builtin_amdgcn_sched_barrier(0);
-        insert_step<K, false>(sb, base, ns, num_blocks, b0, nb, lds2, order);
-        base += stride;
-      }
-      __syncthreads();
-      uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * K);
-      for (uint32_t i = threadIdx.x; i < nb * (K / 4u); i += kPartThreads) dst4[i] = lds4[i];
-    }
-    if (next >= num_slices) break;
-    slice = next;
-    b0 = b0n;
-    nb = nbn;
+  uint32_t base = wave_index() * 256u * kSliceSteps;
+  const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
+  const OrOrder<K> order = or_order<K>(lane_id());
+  SliceStep sa, sb;
+  load_step_buckets(part_slice, cap, prefix, map, map_shift, base, last, sa);
+  for (uint32_t it = 0; it < steps; it += 2u) {
+    load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sb);
+    __builtin_amdgcn_sched_barrier(0);
+    insert_step<K, false>(sa, base, ns, num_blocks, b0, nb, lds2, order);
+    base += stride;
+    load_step_buckets(part_slice, cap, prefix, map, map_shift, base + stride, last, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    insert_step<K, false>(sb, base, ns, num_blocks, b0, nb, lds2, order);
+    base += stride;
   }
+  __syncthreads();
+  uint4 *dst4 = reinterpret_cast<uint4 *>(words + (uint64_t)b0 * K);
+  for (uint32_t i = threadIdx.x; i < nb * (K / 4u); i += kPartThreads) dst4[i] = lds4[i];
 }
 
 // Bucketed lookups: a slice's buckets are walked as one sequence of 32-key
@@ -1058,88 +1025,76 @@ __device__ __forceinline__ void bucket_lookup_step(const BucketLookStep &s, uint
   }
 }
 
-// Slice lookup over the buckets of a count-free lookup partition, persistent
-// as the bucketed slice insert: per slice, the buckets' word counts scanned
-// into a prefix and a coarse map behind the slice in LDS, the slice's words
-// (loaded during the previous slice) stored into LDS, the next slice's words
-// and counts loaded into registers, then the slice loop over the words of
-// all buckets.
+// Slice lookup over the buckets of a count-free lookup partition: the slice
+// in LDS, the buckets' word counts scanned into a prefix and a coarse map
+// after it, then the slice loop over the words of all buckets.
 template <uint32_t K>
 __global__ void __launch_bounds__(kPartThreads)
 part_bucket_lookup_kernel(const uint64_t *__restrict__ part, const uint32_t *__restrict__ counts, uint32_t groups,
                           uint32_t cap, const uint32_t *__restrict__ words, uint32_t num_blocks, uint32_t slice_shift,
-                          uint32_t slice_base, uint32_t num_slices, uint32_t *__restrict__ res32) {
+                          uint32_t slice_base, uint32_t *__restrict__ res32) {
   extern __shared__ uint4 lds4[];
+  const uint32_t slice = blockIdx.x;
+  const uint32_t b0 = (slice_base + slice) << slice_shift;
+  const uint32_t nb = min(1u << slice_shift, num_blocks - b0);
   // after the largest slice: wprefix [kMaxBucketGroups + 1], fill [kMaxBucketGroups],
   // map [kBucketMap + 1], wsum [16]
   uint32_t *wprefix = reinterpret_cast<uint32_t *>(lds4 + (((size_t)1 << slice_shift) * K) / 4u);
   uint32_t *fill = wprefix + kMaxBucketGroups + 1u;
   uint16_t *map = reinterpret_cast<uint16_t *>(fill + kMaxBucketGroups);
   uint32_t *wsum = fill + kMaxBucketGroups + (kBucketMap + 2u) / 2u;
+  const uint32_t cnt = threadIdx.x < groups ? counts[(uint64_t)slice * groups + threadIdx.x] : 0u;
+  const u64x2 *src = reinterpret_cast<const u64x2 *>(words + (uint64_t)b0 * K);
+  const uint32_t count4 = nb * (K / 4u);
+  u64x2 q[8];
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    q[u] = i < count4 ? __builtin_nontemporal_load(src + i) : u64x2{0ull, 0ull};
+  }
+  uint32_t start, nw;
+  {
+    const uint32_t c[1] = {(cnt + 31u) / 32u};
+    start = block_scan_owned<1>(c, wsum, &nw);
+  }
+  if (nw == 0) return;  // whole workgroup: no keys in this slice
+  uint32_t map_shift = 0;
+  while (((nw - 1u) >> map_shift) + 1u > kBucketMap) ++map_shift;
+  const uint32_t entries = ((nw - 1u) >> map_shift) + 1u;
+  if (threadIdx.x < groups) {
+    wprefix[threadIdx.x] = start;
+    fill[threadIdx.x] = cnt;
+    const uint32_t wc = (cnt + 31u) / 32u;
+    for (uint32_t m = (start + (1u << map_shift) - 1u) >> map_shift; (m << map_shift) < start + wc; ++m)
+      map[m] = (uint16_t)threadIdx.x;
+  }
+  if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);
+#pragma unroll
+  for (uint32_t u = 0; u < 8u; ++u) {
+    const uint32_t i = u * kPartThreads + threadIdx.x;
+    if (i < count4) lds4[i] = make_uint4((uint32_t)q[u].x, (uint32_t)(q[u].x >> 32), (uint32_t)q[u].y,
+                                         (uint32_t)(q[u].y >> 32));
+  }
+  __syncthreads();
+
+  const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
+  const uint32_t dw0 = (uint32_t)(((uint64_t)slice * groups * cap) / 32u);
+  const uint32_t ns = 32u * nw;
   constexpr uint32_t waves = kPartThreads / kWave;
   constexpr uint32_t stride = waves * 256u * kSliceSteps;
-  uint32_t slice = blockIdx.x;
-  uint32_t b0 = (slice_base + slice) << slice_shift;
-  uint32_t nb = min(1u << slice_shift, num_blocks - b0);
-  // Sixteen-word blocks need the registers for their slice loop: their
-  // slice is loaded at the start of its own iteration instead.
-  constexpr bool kPrefetch = K <= 8u;
-  uint32_t cnt = threadIdx.x < groups ? counts[(uint64_t)slice * groups + threadIdx.x] : 0u;
-  u64x2 q[8];
-  if constexpr (kPrefetch) load_slice_regs<K>(words, b0, nb, q);
-  for (;;) {
-    if constexpr (!kPrefetch) load_slice_regs<K>(words, b0, nb, q);
-    // (the scan's barrier: every wave has finished the previous slice)
-    uint32_t start, nw;
-    {
-      const uint32_t c[1] = {(cnt + 31u) / 32u};
-      start = block_scan_owned<1>(c, wsum, &nw);
-    }
-    uint32_t map_shift = 0;
-    if (nw > 0) {  // (uniform) a slice without keys has no results
-      while (((nw - 1u) >> map_shift) + 1u > kBucketMap) ++map_shift;
-      const uint32_t entries = ((nw - 1u) >> map_shift) + 1u;
-      if (threadIdx.x < groups) {
-        wprefix[threadIdx.x] = start;
-        fill[threadIdx.x] = cnt;
-        const uint32_t wc = (cnt + 31u) / 32u;
-        for (uint32_t m = (start + (1u << map_shift) - 1u) >> map_shift; (m << map_shift) < start + wc; ++m)
-          map[m] = (uint16_t)threadIdx.x;
-      }
-      if (threadIdx.x == 0) map[entries] = (uint16_t)(groups - 1u);
-      store_slice_lds<K>(lds4, nb, q);
-    }
-    const uint32_t next = slice + gridDim.x;
-    const uint32_t b0n = (slice_base + next) << slice_shift;
-    const uint32_t nbn = next < num_slices ? min(1u << slice_shift, num_blocks - b0n) : 0u;
-    if (next < num_slices) {
-      cnt = threadIdx.x < groups ? counts[(uint64_t)next * groups + threadIdx.x] : 0u;
-      if constexpr (kPrefetch) load_slice_regs<K>(words, b0n, nbn, q);
-    }
-    __syncthreads();
-    if (nw > 0) {
-      const uint64_t *part_slice = part + (uint64_t)slice * groups * cap;
-      const uint32_t dw0 = (uint32_t)(((uint64_t)slice * groups * cap) / 32u);
-      const uint32_t ns = 32u * nw;
-      uint32_t base = wave_index() * 256u * kSliceSteps;
-      const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
-      BucketLookStep sa, sb;
-      load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base, ns, dw0, sa);
-      for (uint32_t it = 0; it < steps; it += 2u) {
-        load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base + stride, ns, dw0, sb);
-        __builtin_amdgcn_sched_barrier(0);
-        bucket_lookup_step<K>(sa, base, ns, num_blocks, b0, nb, lds4, res32);
-        base += stride;
-        load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base + stride, ns, dw0, sa);
-        __builtin_amdgcn_sched_barrier(0);
-        bucket_lookup_step<K>(sb, base, ns, num_blocks, b0, nb, lds4, res32);
-        base += stride;
-      }
-    }
-    if (next >= num_slices) break;
-    slice = next;
-    b0 = b0n;
-    nb = nbn;
+  uint32_t base = wave_index() * 256u * kSliceSteps;
+  const uint32_t steps = base < ns ? (ns - base + stride - 1u) / stride : 0u;
+  BucketLookStep sa, sb;
+  load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base, ns, dw0, sa);
+  for (uint32_t it = 0; it < steps; it += 2u) {
+    load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base + stride, ns, dw0, sb);
+    __builtin_amdgcn_sched_barrier(0);
+    bucket_lookup_step<K>(sa, base, ns, num_blocks, b0, nb, lds4, res32);
+    base += stride;
+    load_step_look_buckets(part_slice, cap, wprefix, fill, map, map_shift, base + stride, ns, dw0, sa);
+    __builtin_amdgcn_sched_barrier(0);
+    bucket_lookup_step<K>(sb, base, ns, num_blocks, b0, nb, lds4, res32);
+    base += stride;
   }
 }
 
@@ -1733,24 +1688,17 @@ bool bucket_plan(uint64_t n, uint32_t num_slices, uint32_t max_groups, BucketPla
   return true;
 }
 
-// Persistent bucketed slice kernels: one workgroup per compute unit (the
-// slice fills its LDS), at most one per slice. max_groups is the partition's
-// workgroup budget, two per compute unit.
-uint32_t slice_grid(uint32_t num_slices, uint32_t max_groups) {
-  return std::min(num_slices, std::max(1u, max_groups / 2u));
-}
-
 template <uint32_t K>
 hipError_t launch_bucket_insert(const uint64_t *part, const uint32_t *counts, const BucketPlan &bp,
                                 uint32_t num_slices, uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
-                                uint32_t max_groups, hipStream_t stream) {
+                                hipStream_t stream) {
   const size_t lds_bytes =
       ((size_t)1 << slice_shift) * 4u * K + (kMaxBucketGroups + 1u + (kBucketMap + 2u) / 2u + 16u) * 4u;
   (void)hipFuncSetAttribute((const void *)part_bucket_insert_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(part_bucket_insert_kernel<K>, dim3(slice_grid(num_slices, max_groups)), dim3(kPartThreads),
-                     lds_bytes, stream, part, counts, bp.groups, bp.cap, words, num_blocks, slice_shift, num_slices);
+  hipLaunchKernelGGL(part_bucket_insert_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, part,
+                     counts, bp.groups, bp.cap, words, num_blocks, slice_shift);
   return hipGetLastError();
 }
 
@@ -1763,7 +1711,7 @@ hipError_t launch_overflow_insert(const Buckets &Bk, uint32_t *words, uint32_t n
 
 hipError_t insert_buckets(const uint64_t *hashes, uint32_t n, uint32_t *words, uint32_t num_blocks,
                           uint32_t slice_shift, uint32_t num_slices, void *workspace, const BucketPlan &bp,
-                          uint32_t max_groups, uint32_t keys, hipStream_t stream, uint32_t lanes) {
+                          uint32_t keys, hipStream_t stream, uint32_t lanes) {
   char *base = static_cast<char *>(workspace);
   const Buckets Bk{bp.cap, reinterpret_cast<uint32_t *>(base + bp.count_off),
                    reinterpret_cast<uint64_t *>(base + bp.ovf_off), reinterpret_cast<uint32_t *>(base + bp.ovfn_off),
@@ -1781,17 +1729,14 @@ hipError_t insert_buckets(const uint64_t *hashes, uint32_t n, uint32_t *words, u
                                                       num_slices, keys, L, stream, Bk);
   if (e != hipSuccess) return e;
   if (lanes == 4) {
-    e = launch_bucket_insert<4>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, max_groups,
-                                 stream);
+    e = launch_bucket_insert<4>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
     return e != hipSuccess ? e : launch_overflow_insert<4>(Bk, words, num_blocks, stream);
   }
   if (lanes == 16) {
-    e = launch_bucket_insert<16>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, max_groups,
-                                  stream);
+    e = launch_bucket_insert<16>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
     return e != hipSuccess ? e : launch_overflow_insert<16>(Bk, words, num_blocks, stream);
   }
-  e = launch_bucket_insert<8>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, max_groups,
-                                 stream);
+  e = launch_bucket_insert<8>(L.keys, Bk.count, bp, num_slices, words, num_blocks, slice_shift, stream);
   return e != hipSuccess ? e : launch_overflow_insert<8>(Bk, words, num_blocks, stream);
 }
 
@@ -1881,15 +1826,14 @@ uint32_t look_unpermute_chunks(const LookPlan &lp, uint32_t num_slices) {
 template <uint32_t K>
 hipError_t launch_bucket_lookup(const uint64_t *part, const uint32_t *counts, const LookPlan &lp,
                                 uint32_t num_slices, const uint32_t *words, uint32_t num_blocks, uint32_t slice_shift,
-                                uint32_t slice_base, uint32_t *res32, uint32_t max_groups, hipStream_t stream) {
+                                uint32_t slice_base, uint32_t *res32, hipStream_t stream) {
   const size_t lds_bytes = ((size_t)1 << slice_shift) * 4u * K +
                            (2u * kMaxBucketGroups + 1u + (kBucketMap + 2u) / 2u + 16u) * 4u;
   (void)hipFuncSetAttribute((const void *)part_bucket_lookup_kernel<K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds_bytes);
   (void)hipGetLastError();
-  hipLaunchKernelGGL(part_bucket_lookup_kernel<K>, dim3(slice_grid(num_slices, max_groups)), dim3(kPartThreads),
-                     lds_bytes, stream, part, counts, lp.sgroups, lp.cap, words, num_blocks, slice_shift, slice_base,
-                     num_slices, res32);
+  hipLaunchKernelGGL(part_bucket_lookup_kernel<K>, dim3(num_slices), dim3(kPartThreads), lds_bytes, stream, part,
+                     counts, lp.sgroups, lp.cap, words, num_blocks, slice_shift, slice_base, res32);
   return hipGetLastError();
 }
 
@@ -1946,13 +1890,13 @@ hipError_t lookup_buckets(const uint64_t *hashes, uint32_t n, const uint32_t *wo
   if (e != hipSuccess) return e;
   if (lanes == 4)
     e = launch_bucket_lookup<4>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
-                                slots, stream);
+                                stream);
   else if (lanes == 16)
     e = launch_bucket_lookup<16>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
-                                 slots, stream);
+                                 stream);
   else
     e = launch_bucket_lookup<8>(part, Bk.count, lp, num_slices, words, num_blocks, slice_shift, slice_base, res32,
-                                slots, stream);
+                                stream);
   if (e != hipSuccess) return e;
   const uint32_t per_u = look_unpermute_chunks(lp, num_slices);
   const uint32_t upw = (lp.per + per_u - 1u) / per_u;
@@ -1960,6 +1904,7 @@ hipError_t lookup_buckets(const uint64_t *hashes, uint32_t n, const uint32_t *wo
   const size_t u_lds = look_unpermute_lds(per_u, num_slices, lp.room);
   uint32_t room_shift = 5;
   while ((1u << room_shift) < lp.room) ++room_shift;
+  (void)slots;
   if (out_bits) {
     (void)hipFuncSetAttribute((const void *)part_unpermute_buckets_kernel<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)u_lds);
@@ -2095,8 +2040,8 @@ hipError_t launch_insert_partitioned(const uint64_t *hashes, uint64_t n, uint32_
     BucketPlan bp;
     // (the bucketed slice insert loads a slice of at most 128 KiB in one round)
     if (((uint64_t)4u * lanes << slice_shift) <= (128u << 10) && bucket_plan(n, num_slices, max_groups, &bp))
-      return insert_buckets(hashes, (uint32_t)n, words, num_blocks, slice_shift, num_slices, workspace, bp, max_groups,
-                            keys, stream, lanes);
+      return insert_buckets(hashes, (uint32_t)n, words, num_blocks, slice_shift, num_slices, workspace, bp, keys,
+                            stream, lanes);
     return insert_level(hashes, (uint32_t)n, words, num_blocks, slice_shift, 0u, num_slices, workspace, max_groups,
                         keys, stream, lanes);
   }
