@@ -32,9 +32,15 @@
  *     lookup sees every insert enqueued before it on the same stream. Device
  *     faults surface when the caller synchronises the stream.
  *   - Caller-owned buffers must stay valid until the stream passes the call.
- *   - Handles are not locked; concurrent inserts into one filter from
- *     several streams are safe on the device (they use atomic OR), and a
- *     lookup running concurrently with inserts sees some subset of them.
+ *   - Handles are not locked. Inserts into one filter that run at the same
+ *     time (on several streams) are safe on the device only with the atomic
+ *     strategies (SBBF_INSERT_ATOMIC32, SBBF_INSERT_ATOMIC64): the
+ *     partitioned and LDS strategies read a part of the filter into LDS, OR
+ *     into it and store it back whole, so another insert running at the same
+ *     time into that part can lose its bits. SBBF_INSERT_AUTO may choose
+ *     either kind; order such calls (one stream, or events) or name an atomic
+ *     strategy. A lookup running concurrently with inserts sees some subset of
+ *     them.
  *   - The filter bytes produced by any insert strategy and any launch
  *     configuration are identical: the final filter is the OR of all masks.
  */

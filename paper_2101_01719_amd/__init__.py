@@ -75,6 +75,9 @@ def _hashes(t: torch.Tensor):
         raise TypeError("hashes must be int64 or uint64")
     if t.dim() != 1 or not t.is_contiguous():
         raise ValueError("hashes must be a 1-D contiguous tensor")
+    if t.device.index != torch.cuda.current_device():
+        # the library launches on the current device
+        raise ValueError(f"hashes are on {t.device}, the current device is cuda:{torch.cuda.current_device()}")
     return ctypes.c_void_p(t.data_ptr()), t.numel()
 
 
@@ -257,6 +260,8 @@ def _out_bytes(out, n, device):
         return torch.empty(n, dtype=torch.uint8, device=device)
     if out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
         raise ValueError("out must be a contiguous uint8 CUDA tensor of at least n elements")
+    if out.device != torch.device(device):
+        raise ValueError(f"out is on {out.device}, the hashes on {device}")
     return out
 
 
@@ -267,6 +272,8 @@ def _out_bits(bits, n, device):
     if bits.dtype not in (torch.int32, torch.uint32) or not bits.is_cuda or not bits.is_contiguous() \
             or bits.numel() < words:
         raise ValueError("bits must be a contiguous int32 CUDA tensor of at least ceil(n/32) words")
+    if bits.device != torch.device(device):
+        raise ValueError(f"bits are on {bits.device}, the hashes on {device}")
     return bits
 
 
